@@ -1,0 +1,178 @@
+/*
+ * CPU oracle — TEST INFRASTRUCTURE ONLY (see oracle.h).
+ *
+ * What each function follows:
+ *  - oracle_sort_u32 / oracle_sort_pairs_u32 / oracle_segmented_sort_u32:
+ *    the plain definition of an ascending sort, which the bitonic network of
+ *    the paper's running example (Motivating Example section, Figure 1)
+ *    reaches exactly. Pairs use the lexicographic (key, payload) order so
+ *    that exactly one output is correct. Segments follow the BIT benchmark's
+ *    per-bucket sort (Evaluation section, "Bitonic Sort (BIT)").
+ *  - oracle_bitonic_emulate: the Figure 1 network itself, executed one
+ *    (k, j) step at a time on a power-of-two array: for each thread index
+ *    t with partner p = t xor j and p > t, keep ascending order when
+ *    (t & k) == 0 and descending order otherwise, using strict compares.
+ *  - oracle_region_f32: the two-sided loop region evaluated lane by lane in
+ *    the order its two source sides run (Detailed Design section: a
+ *    divergent branch whose sides hold similar instruction sequences; the
+ *    melded form must compute the same values). One fused multiply-add per
+ *    step, correctly rounded (std::fma).
+ *  - oracle_mixed_waves: the share of 64-lane waves whose branch mask is
+ *    neither all-true nor all-false (Background section: only such waves
+ *    pay the IPDOM serialisation).
+ *
+ * Built with g++ -O2 -ffp-contract=off and without fast-math.
+ */
+#include "oracle.h"
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+namespace {
+
+constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+
+// SplitMix64 output mixer, from its published definition (Steele, Lea and
+// Flood, OOPSLA 2014).
+uint64_t mix64(uint64_t z) {
+    z ^= z >> 30;
+    z *= 0xBF58476D1CE4E5B9ull;
+    z ^= z >> 27;
+    z *= 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return z;
+}
+
+// Branch-bit stream of the region: tag 4.
+uint64_t branch_hash(uint64_t seed, uint64_t i) { return mix64(mix64(seed + 4 * kGolden) + i); }
+
+bool branch_true(uint64_t seed, uint64_t thr, uint64_t i) { return (branch_hash(seed, i) >> 32) < thr; }
+
+inline uint64_t composite(uint32_t k, uint32_t v) { return ((uint64_t)k << 32) | v; }
+
+bool is_pow2(size_t n) { return n != 0 && (n & (n - 1)) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+uint64_t oracle_mix64(uint64_t z) { return mix64(z); }
+
+uint64_t oracle_branch_hash(uint64_t seed, uint64_t i) { return branch_hash(seed, i); }
+
+void oracle_sort_u32(uint32_t *keys, size_t n) { std::sort(keys, keys + n); }
+
+void oracle_sort_pairs_u32(uint32_t *keys, uint32_t *vals, size_t n) {
+    std::vector<uint64_t> tmp(n);
+    for (size_t i = 0; i < n; ++i) tmp[i] = composite(keys[i], vals[i]);
+    std::sort(tmp.begin(), tmp.end());
+    for (size_t i = 0; i < n; ++i) {
+        keys[i] = (uint32_t)(tmp[i] >> 32);
+        vals[i] = (uint32_t)tmp[i];
+    }
+}
+
+int oracle_segmented_sort_u32(uint32_t *keys, const uint32_t *offsets, size_t nseg) {
+    if (nseg == 0) return 0;
+    if (offsets[0] != 0) return -1;
+    for (size_t s = 0; s < nseg; ++s)
+        if (offsets[s + 1] < offsets[s]) return -1;
+    for (size_t s = 0; s < nseg; ++s) std::sort(keys + offsets[s], keys + offsets[s + 1]);
+    return 0;
+}
+
+// Number of (k, j) steps of the network on n_pow2 elements: sum over phases
+// k = 2, 4, ..., n of log2(k).
+uint64_t oracle_bitonic_num_steps(size_t n_pow2) {
+    uint64_t steps = 0;
+    for (size_t k = 2; k <= n_pow2; k *= 2)
+        for (size_t j = k / 2; j > 0; j /= 2) ++steps;
+    return steps;
+}
+
+// Runs the first max_steps steps (all of them when max_steps < 0) of the
+// Figure 1 network. vals may be NULL (keys only); with vals the compare is on
+// the composite (key, payload). The array length must be a power of two;
+// callers pad with 0xFFFFFFFF themselves.
+int oracle_bitonic_emulate(uint32_t *keys, uint32_t *vals, size_t n_pow2, int64_t max_steps) {
+    if (n_pow2 == 0) return 0;
+    if (!is_pow2(n_pow2)) return -1;
+    int64_t done = 0;
+    for (size_t k = 2; k <= n_pow2; k *= 2) {
+        for (size_t j = k / 2; j > 0; j /= 2) {
+            if (max_steps >= 0 && done == max_steps) return 0;
+            for (size_t tid = 0; tid < n_pow2; ++tid) {
+                size_t ixj = tid ^ j;
+                if (ixj <= tid) continue;
+                uint64_t a = composite(keys[tid], vals ? vals[tid] : 0);
+                uint64_t b = composite(keys[ixj], vals ? vals[ixj] : 0);
+                bool do_swap = ((tid & k) == 0) ? (b < a) : (b > a);
+                if (do_swap) {
+                    std::swap(keys[tid], keys[ixj]);
+                    if (vals) std::swap(vals[tid], vals[ixj]);
+                }
+            }
+            ++done;
+        }
+    }
+    return 0;
+}
+
+// Lanes i0 .. i0+n-1 of the two-sided loop region:
+//   side  = branch bit of lane i (true when (H(seed,4,i) >> 32) < thr)
+//   acc   = x[i]
+//   step k = 0 .. trips-1 of that side:
+//           idx = (i + off + k * step) mod 2^32, masked to the table length
+//           acc = fma(acc, a, tab[idx])
+//   y[i]  = acc
+// x and y are indexed from 0 (they hold lanes i0 .. i0+n-1).
+int oracle_region_f32(const float *x, float *y, uint64_t i0, size_t n, const float *tab,
+                      size_t tab_len, uint64_t seed, uint64_t thr, oracle_side side_true,
+                      oracle_side side_false) {
+    if (!is_pow2(tab_len) || thr > (1ull << 32)) return -1;
+    const uint32_t mask = (uint32_t)(tab_len - 1);
+    for (size_t j = 0; j < n; ++j) {
+        const uint64_t i = i0 + j;
+        const bool taken = branch_true(seed, thr, i);
+        float acc = x[j];
+        if (taken) {
+            for (uint32_t k = 0; k < side_true.trips; ++k) {
+                uint32_t idx = ((uint32_t)i + side_true.off + k * side_true.step) & mask;
+                acc = std::fma(acc, side_true.a, tab[idx]);
+            }
+        } else {
+            for (uint32_t k = 0; k < side_false.trips; ++k) {
+                uint32_t idx = ((uint32_t)i + side_false.off + k * side_false.step) & mask;
+                acc = std::fma(acc, side_false.a, tab[idx]);
+            }
+        }
+        y[j] = acc;
+    }
+    return 0;
+}
+
+uint64_t oracle_count_true(uint64_t seed, uint64_t thr, uint64_t i0, size_t n) {
+    uint64_t c = 0;
+    for (size_t j = 0; j < n; ++j) c += branch_true(seed, thr, i0 + j) ? 1 : 0;
+    return c;
+}
+
+// Waves are the lanes [w*wave, (w+1)*wave) intersected with [0, n).
+uint64_t oracle_mixed_waves(uint64_t seed, uint64_t thr, size_t n, uint32_t wave) {
+    uint64_t mixed = 0;
+    for (size_t base = 0; base < n; base += wave) {
+        size_t end = std::min(n, base + (size_t)wave);
+        size_t ones = 0;
+        for (size_t i = base; i < end; ++i) ones += branch_true(seed, thr, i) ? 1 : 0;
+        if (ones != 0 && ones != end - base) ++mixed;
+    }
+    return mixed;
+}
+
+// For independent lanes with P(true) = p: 1 - p^W - (1-p)^W.
+double oracle_mixed_fraction_closed_form(double p, uint32_t wave) {
+    return 1.0 - std::pow(p, (double)wave) - std::pow(1.0 - p, (double)wave);
+}
+
+}  // extern "C"
