@@ -1,0 +1,171 @@
+/*
+ * meld — hand-melded SIMT kernels for MI355X (gfx950), C ABI.
+ *
+ * Every compute entry point exists in two forms selected by meld_variant:
+ *   MELD_DIVERGENT  the divergent if/else region runs as written: the two
+ *                   sides execute one after the other under exec masks and
+ *                   the wave reconverges at the immediate post-dominator
+ *                   (Background section, "GPGPU Architecture").
+ *   MELD_MELDED     the two sides are melded as the paper's subgraph melding
+ *                   does (Detailed Design section, "DARM Code Generation",
+ *                   Algorithm 2): aligned instructions run once on the whole
+ *                   wave, operands that differ are chosen by a select on the
+ *                   branch condition, memory operations with identical
+ *                   operands become one access, and only unaligned work stays
+ *                   under a branch (the "Unpredication" subsection).
+ *   MELD_AUTO       the library picks per stage (measured divergence and the
+ *                   tuned plan).
+ *   MELD_MELDED_INPLACE  for the region: the melded form with the two sides'
+ *                   gathers aligned too (one gather instruction per step,
+ *                   address selected per lane). MELD_MELDED leaves those
+ *                   gathers unaligned (one conditional block per side and
+ *                   batch), which is faster on gfx950 when the sides read
+ *                   different addresses. For the sorts it is MELD_MELDED.
+ * Both forms return bit-identical results.
+ *
+ * Conventions for every call below:
+ *   - Array arguments are DEVICE pointers on the context's device, owned by
+ *     the caller; the library never frees or keeps them.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream). Calls are
+ *     asynchronous on it; results are ready once the stream has reached the
+ *     call. Kernel faults surface at the caller's next synchronisation.
+ *   - Argument errors are detected before anything is enqueued and return
+ *     MELD_EINVAL with a message in meld_last_error(); the arrays are then
+ *     untouched. A failed launch returns MELD_EHIP.
+ *   - Calls on one context must not overlap from several host threads.
+ *   - The library never calls exit() or abort().
+ */
+#ifndef MELD_H
+#define MELD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct meld_ctx meld_ctx;
+
+typedef enum {
+    MELD_OK = 0,
+    MELD_EINVAL = 1,
+    MELD_ENOMEM = 2,
+    MELD_EHIP = 3,
+    MELD_EUNSUPPORTED = 4
+} meld_status;
+
+typedef enum {
+    MELD_DIVERGENT = 0,
+    MELD_MELDED = 1,
+    MELD_AUTO = 2,
+    MELD_MELDED_INPLACE = 3
+} meld_variant;
+
+/* Library version as major*10000 + minor*100 + patch. */
+int meld_version(void);
+
+/* Creates a context on HIP device `hip_device`. The context owns the
+ * library's scratch memory (tail padding for non-power-of-two sorts, work
+ * queues, counters), which grows on demand and is freed by meld_destroy. */
+meld_status meld_create(int hip_device, meld_ctx **out);
+
+/* Waits for the context's pending work and frees its scratch. NULL is a no-op. */
+void meld_destroy(meld_ctx *ctx);
+
+/* Message of the last failed call on this host thread ("" if none). The
+ * pointer stays valid until the next library call on the same thread. */
+const char *meld_last_error(void);
+
+/* In-place ascending sort of keys[0..n) with the bitonic network of the
+ * paper's running example (Motivating Example section, Figure 1): phases
+ * k = 2, 4, ..., N and steps j = k/2, ..., 1 over N = the next power of two
+ * >= n; element i is kept in ascending order when (i & k) == 0 and in
+ * descending order otherwise, with strict compares. Positions n..N-1 hold
+ * the value 0xFFFFFFFF (for pairs (0xFFFFFFFF, 0xFFFFFFFF)) in library
+ * scratch; nothing past n is read or written in the caller's arrays.
+ *
+ * keys:    device u32[n], sorted in place (unsigned order).
+ * payload: NULL, or device u32[n] moved with its key. With a payload the
+ *          order is the lexicographic (key, payload) order, so the output is
+ *          unique; with payload = original index this is a stable sort.
+ * n:       number of elements, n < 2^31; n <= 1 is a no-op.
+ * Errors:  MELD_EINVAL for NULL/host pointers when n > 1 or n >= 2^31;
+ *          MELD_ENOMEM when scratch for a non-power-of-two n cannot be
+ *          allocated.
+ */
+meld_status meld_sort_u32(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n,
+                          meld_variant variant, void *stream);
+
+/* Runs only the first max_steps (k, j) steps of the same network (all of
+ * them when max_steps < 0), in the same order, for stage-by-stage checks and
+ * tracing. n must be a power of two in [2, 2^30]; nothing is padded.
+ * Errors: as meld_sort_u32, plus MELD_EINVAL when n is not a power of two. */
+meld_status meld_sort_u32_steps(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n,
+                                int64_t max_steps, meld_variant variant, void *stream);
+
+/* Sorts each segment keys[offsets[s] .. offsets[s+1]) ascending in place;
+ * no key crosses a segment boundary. This is the per-bucket sort of the
+ * paper's bitonic benchmark (Evaluation section, "Bitonic Sort (BIT)": each
+ * thread block sorts one bucket), batched over many uneven buckets.
+ *
+ * keys:    device u32[offsets[nseg]].
+ * offsets: device u32[nseg + 1], offsets[0] = 0, non-decreasing. Segments
+ *          may be empty. Segment length <= 65536.
+ * nseg:    number of segments, < 2^31; 0 is a no-op.
+ * Errors:  MELD_EINVAL for NULL/host pointers. Offsets live on the device
+ *          and are not inspected on the host: a segment longer than 65536,
+ *          decreasing offsets or offsets[0] != 0 leave the keys untouched
+ *          and set the context's device error flag, read by
+ *          meld_segmented_sort_check().
+ */
+meld_status meld_segmented_sort_u32(meld_ctx *ctx, uint32_t *keys, const uint32_t *offsets,
+                                    size_t nseg, meld_variant variant, void *stream);
+
+/* Synchronises `stream` and reports whether the last segmented sorts on the
+ * context found invalid offsets (MELD_EINVAL, with the reason) or not
+ * (MELD_OK). Clears the flag. */
+meld_status meld_segmented_sort_check(meld_ctx *ctx, void *stream);
+
+/* One side of the two-sided loop region: multiplier, table offset, index
+ * stride and trip count. */
+typedef struct {
+    float a;
+    uint32_t off;
+    uint32_t step;
+    uint32_t trips;
+} meld_side;
+
+/* The two-sided loop region, lane by lane (the paper's synthetic benchmarks:
+ * a divergent region whose two sides hold the same instruction sequence on
+ * different data, Evaluation section, "Synthetic Benchmarks"):
+ *   taken = (mix64(mix64(seed + 4*0x9E3779B97F4A7C15) + i) >> 32) < thr
+ *           (SplitMix64 output mixer, Steele, Lea and Flood, OOPSLA 2014)
+ *   s     = taken ? side_true : side_false
+ *   acc   = x[i]
+ *   for k in 0 .. s.trips-1:
+ *       idx = (uint32)(i + s.off + k*s.step) & (tab_len - 1)
+ *       acc = fmaf(acc, s.a, tab[idx])      (one rounding per step)
+ *   y[i]  = acc
+ * The melded form runs one loop of min(trips) steps on the whole wave (the
+ * fma multiplier selected per lane; each side's gathers of a batch in one
+ * conditional block) and leaves the remaining steps of the longer side under
+ * an exec mask.
+ *
+ * x, y:    device f32[n]; y may not alias x.
+ * tab:     device f32[tab_len], tab_len a power of two <= 2^32.
+ * thr:     threshold in [0, 2^32]; P(taken) = thr / 2^32.
+ * trips:   each side's trip count <= 65536.
+ * n:       lanes, n < 2^32; 0 is a no-op.
+ * Errors:  MELD_EINVAL for NULL/host pointers, tab_len not a power of two,
+ *          thr > 2^32, trips > 65536, n >= 2^32.
+ */
+meld_status meld_divergent_region_f32(meld_ctx *ctx, const float *x, float *y, size_t n,
+                                      const float *tab, size_t tab_len, uint64_t seed,
+                                      uint64_t thr, meld_side side_true, meld_side side_false,
+                                      meld_variant variant, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,199 @@
+"""Python binding of libmeld.so, the MI355X melded-kernel library.
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+PyTorch supplies device memory (``data_ptr()``) and the current stream.
+
+The library must be built in-tree first (``__graft_entry__.build()`` or
+``python paper_2107_05681_amd/build.py``); importing the functions below
+without it raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libmeld.so")
+
+DIVERGENT = 0
+MELDED = 1
+AUTO = 2
+MELDED_INPLACE = 3
+_VARIANTS = {"divergent": DIVERGENT, "melded": MELDED, "auto": AUTO,
+             "melded_inplace": MELDED_INPLACE,
+             DIVERGENT: DIVERGENT, MELDED: MELDED, AUTO: AUTO, MELDED_INPLACE: MELDED_INPLACE}
+
+OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, 1, 2, 3, 4
+_STATUS = {1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "EUNSUPPORTED"}
+
+# Every function the C header declares.
+EXPORTS = ("meld_version", "meld_create", "meld_destroy", "meld_last_error", "meld_sort_u32",
+           "meld_sort_u32_steps", "meld_segmented_sort_u32", "meld_segmented_sort_check",
+           "meld_divergent_region_f32")
+
+
+class MeldError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class Side(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_float), ("off", ctypes.c_uint32),
+                ("step", ctypes.c_uint32), ("trips", ctypes.c_uint32)]
+
+
+_lib = None
+_lock = threading.Lock()
+_ctxs: dict[int, ctypes.c_void_p] = {}
+
+
+def load_library():
+    """Loads libmeld.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build the HIP extension first "
+                           "(python -c 'import __graft_entry__ as g; g.build()')")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, sz, u64, i64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint64, ctypes.c_int64
+    st = ctypes.c_int
+    lib.meld_version.restype = ctypes.c_int
+    lib.meld_version.argtypes = []
+    lib.meld_create.restype = st
+    lib.meld_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
+    lib.meld_destroy.restype = None
+    lib.meld_destroy.argtypes = [vp]
+    lib.meld_last_error.restype = ctypes.c_char_p
+    lib.meld_last_error.argtypes = []
+    lib.meld_sort_u32.restype = st
+    lib.meld_sort_u32.argtypes = [vp, vp, vp, sz, st, vp]
+    lib.meld_sort_u32_steps.restype = st
+    lib.meld_sort_u32_steps.argtypes = [vp, vp, vp, sz, i64, st, vp]
+    lib.meld_segmented_sort_u32.restype = st
+    lib.meld_segmented_sort_u32.argtypes = [vp, vp, vp, sz, st, vp]
+    lib.meld_segmented_sort_check.restype = st
+    lib.meld_segmented_sort_check.argtypes = [vp, vp]
+    lib.meld_divergent_region_f32.restype = st
+    lib.meld_divergent_region_f32.argtypes = [vp, vp, vp, sz, vp, sz, u64, u64, Side, Side, st, vp]
+    _lib = lib
+    return lib
+
+
+def _check(status: int) -> None:
+    if status != OK:
+        msg = load_library().meld_last_error().decode(errors="replace")
+        raise MeldError(status, msg)
+
+
+def context(device: int):
+    """The library context of HIP device ``device`` (created on first use)."""
+    with _lock:
+        ctx = _ctxs.get(device)
+        if ctx is None:
+            lib = load_library()
+            ctx = ctypes.c_void_p()
+            _check(lib.meld_create(device, ctypes.byref(ctx)))
+            _ctxs[device] = ctx
+        return ctx
+
+
+def _variant(v) -> int:
+    try:
+        return _VARIANTS[v]
+    except KeyError:
+        raise ValueError(f"unknown variant {v!r}") from None
+
+
+def _stream_of(t, stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(t.device)
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _u32_tensor(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype not in (torch.uint32, torch.int32) or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous uint32/int32 tensor")
+    return t
+
+
+def sort(keys, payload=None, variant=AUTO, stream=None):
+    """In-place ascending bitonic sort of ``keys`` (u32 bits), moving ``payload`` along."""
+    _u32_tensor(keys, "keys")
+    if payload is not None:
+        _u32_tensor(payload, "payload")
+        if payload.numel() != keys.numel() or payload.device != keys.device:
+            raise ValueError("payload must match keys in length and device")
+    lib = load_library()
+    _check(lib.meld_sort_u32(context(keys.device.index), ctypes.c_void_p(keys.data_ptr()),
+                             None if payload is None else ctypes.c_void_p(payload.data_ptr()),
+                             keys.numel(), _variant(variant), _stream_of(keys, stream)))
+    return keys if payload is None else (keys, payload)
+
+
+def sort_steps(keys, payload=None, max_steps=-1, variant=AUTO, stream=None):
+    """The first ``max_steps`` steps of the sorting network (power-of-two length)."""
+    _u32_tensor(keys, "keys")
+    if payload is not None:
+        _u32_tensor(payload, "payload")
+    lib = load_library()
+    _check(lib.meld_sort_u32_steps(context(keys.device.index), ctypes.c_void_p(keys.data_ptr()),
+                                   None if payload is None else ctypes.c_void_p(payload.data_ptr()),
+                                   keys.numel(), int(max_steps), _variant(variant),
+                                   _stream_of(keys, stream)))
+    return keys if payload is None else (keys, payload)
+
+
+def segmented_sort(keys, offsets, variant=AUTO, stream=None):
+    """Sorts every segment keys[offsets[s]:offsets[s+1]] in place."""
+    _u32_tensor(keys, "keys")
+    _u32_tensor(offsets, "offsets")
+    lib = load_library()
+    _check(lib.meld_segmented_sort_u32(context(keys.device.index),
+                                       ctypes.c_void_p(keys.data_ptr()),
+                                       ctypes.c_void_p(offsets.data_ptr()),
+                                       max(offsets.numel() - 1, 0), _variant(variant),
+                                       _stream_of(keys, stream)))
+    return keys
+
+
+def segmented_sort_check(device: int = 0, stream=None):
+    """Raises MeldError if a segmented sort on ``device`` met invalid offsets."""
+    import torch
+    lib = load_library()
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    _check(lib.meld_segmented_sort_check(context(device), ctypes.c_void_p(s.cuda_stream)))
+
+
+def side(a: float, off: int, step: int, trips: int) -> Side:
+    return Side(float(a), int(off), int(step), int(trips))
+
+
+def _as_side(s) -> Side:
+    if isinstance(s, Side):
+        return s
+    return side(s["a"], s["off"], s["step"], s["trips"])
+
+
+def divergent_region(x, tab, seed: int, thr: int, side_true, side_false, variant=AUTO,
+                     out=None, stream=None):
+    """Two-sided loop region over the lanes of ``x`` (see meld_divergent_region_f32)."""
+    import torch
+    for t, name in ((x, "x"), (tab, "tab")):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 \
+                or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous float32 CUDA tensor")
+    if out is None:
+        out = torch.empty_like(x)
+    lib = load_library()
+    _check(lib.meld_divergent_region_f32(
+        context(x.device.index), ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+        x.numel(), ctypes.c_void_p(tab.data_ptr()), tab.numel(), int(seed), int(thr),
+        _as_side(side_true), _as_side(side_false), _variant(variant), _stream_of(x, stream)))
+    return out

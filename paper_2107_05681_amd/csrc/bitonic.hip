@@ -1,0 +1,425 @@
+// Bitonic sort network (the paper's running example, Motivating Example
+// section, Figure 1): divergent and melded compare-exchange, LDS tiles and
+// register-resident streaming passes.
+//
+// Network: phases k = 2, 4, ..., N; steps j = k/2, ..., 1. Step (k, j) pairs
+// element lo with hi = lo + j for every lo whose bit j is clear; the pair is
+// put in ascending order when bit k of lo is clear and in descending order
+// otherwise, with strict compares (equal elements are never swapped). Pairs
+// of u32 (key, payload) are compared as the 64-bit composite key:payload.
+//
+// Tile kernel: one workgroup owns a tile of T = 2^log_t consecutive
+// elements in LDS and runs a range of steps on it; each lane takes one
+// comparator c per iteration (lo = c with a zero bit inserted at bit j).
+// The direction of a comparator is bit k of lo, i.e. bit k-1 of c; for
+// k <= 64 that is one of the six lane bits, so the direction branch is
+// divergent inside every wave. That is the region the two forms differ in:
+//
+//   divergent (Figure 1 as written): if (up) { a = s[lo]; b = s[hi];
+//       if (b < a) swap } else { a = s[lo]; b = s[hi]; if (b > a) swap }
+//   melded (the paper's melded bitonic, "Putting All Together"): the loads
+//       of the two sides align with identical operands and become one load
+//       pair; the two compares do not align and both run; the branch
+//       condition of the swap is select(up, b < a, b > a); the swap stores
+//       align with identical operands and become one store pair.
+//
+// Steps with j >= 128 exchange data between waves and end with a workgroup
+// barrier. For j <= 64 the 64 comparators of a wave (one iteration) touch
+// only the 128-element block [2*c0, 2*c0 + 128) of their first comparator
+// c0, the same block in every such step, so those steps need only the wave's
+// own LDS operations to have completed.
+//
+// Streaming pass: for steps whose j is at least the tile size every thread
+// loads the 2^R elements that differ only in bits b_lo .. b_hi (R = b_hi -
+// b_lo + 1) and runs the R steps in registers. The direction bit k lies above
+// b_hi, so it is the same for all of a thread's elements and, because the
+// low bits of the index come from the lane, for the whole wave: both forms
+// coincide there and a single kernel serves them.
+#include "device_common.h"
+#include "kernels.h"
+
+namespace meld {
+
+namespace {
+
+constexpr uint32_t kPadValue = 0xFFFFFFFFu;  // value of every position >= n
+
+template <bool PAIRS>
+struct ElemOf {
+    using type = uint32_t;
+};
+template <>
+struct ElemOf<true> {
+    using type = uint64_t;
+};
+
+// Where the elements of a launch live:
+//   kPlain     every position is below n: direct loads and stores.
+//   kPlainVec  as kPlain, with 16-byte aligned arrays: tiles move 4 elements
+//              per lane per access.
+//   kTail      positions >= n live in the tail workspace: the address is
+//              selected per element (no branch).
+//   kSentinel  positions >= n read as the sentinel and are never stored
+//              (a single tile padded in LDS).
+enum IoMode { kPlain = kIoPlain, kPlainVec = kIoPlainVec, kTail = kIoTail, kSentinel = kIoSentinel };
+
+template <int MODE>
+__device__ __forceinline__ uint32_t ld_u32(const uint32_t *main, const uint32_t *tail, uint32_t n,
+                                           uint32_t p) {
+    if constexpr (MODE == kTail) {
+        const uint32_t *src = p < n ? main + p : tail + (p - n);
+        return *src;
+    } else if constexpr (MODE == kSentinel) {
+        return p < n ? main[p] : kPadValue;
+    } else {
+        return main[p];
+    }
+}
+
+template <int MODE>
+__device__ __forceinline__ void st_u32(uint32_t *main, uint32_t *tail, uint32_t n, uint32_t p,
+                                       uint32_t v) {
+    if constexpr (MODE == kTail) {
+        uint32_t *dst = p < n ? main + p : tail + (p - n);
+        *dst = v;
+    } else if constexpr (MODE == kSentinel) {
+        if (p < n) main[p] = v;
+    } else {
+        main[p] = v;
+    }
+}
+
+template <bool PAIRS, int MODE>
+__device__ __forceinline__ typename ElemOf<PAIRS>::type load_elem(const SortArray &a, uint32_t p) {
+    const uint32_t k = ld_u32<MODE>(a.keys, a.tk, a.n, p);
+    if constexpr (PAIRS) {
+        const uint32_t v = ld_u32<MODE>(a.vals, a.tv, a.n, p);
+        return ((uint64_t)k << 32) | v;
+    } else {
+        return k;
+    }
+}
+
+template <bool PAIRS, int MODE>
+__device__ __forceinline__ void store_elem(const SortArray &a, uint32_t p,
+                                           typename ElemOf<PAIRS>::type e) {
+    if constexpr (PAIRS) {
+        st_u32<MODE>(a.keys, a.tk, a.n, p, (uint32_t)(e >> 32));
+        st_u32<MODE>(a.vals, a.tv, a.n, p, (uint32_t)e);
+    } else {
+        st_u32<MODE>(a.keys, a.tk, a.n, p, e);
+    }
+}
+
+// Moves tile [base, base + T) between global memory and LDS.
+template <bool PAIRS, int MODE, int NT>
+__device__ __forceinline__ void tile_load(const SortArray &a, typename ElemOf<PAIRS>::type *s,
+                                          uint32_t base, uint32_t T) {
+    using E = typename ElemOf<PAIRS>::type;
+    if constexpr (MODE == kPlainVec) {
+        for (uint32_t p = threadIdx.x * 4; p < T; p += NT * 4) {
+            const uint4 k = *reinterpret_cast<const uint4 *>(a.keys + base + p);
+            if constexpr (PAIRS) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(a.vals + base + p);
+                s[p + 0] = ((E)k.x << 32) | v.x;
+                s[p + 1] = ((E)k.y << 32) | v.y;
+                s[p + 2] = ((E)k.z << 32) | v.z;
+                s[p + 3] = ((E)k.w << 32) | v.w;
+            } else {
+                *reinterpret_cast<uint4 *>(s + p) = k;
+            }
+        }
+    } else {
+        for (uint32_t p = threadIdx.x; p < T; p += NT) s[p] = load_elem<PAIRS, MODE>(a, base + p);
+    }
+}
+
+template <bool PAIRS, int MODE, int NT>
+__device__ __forceinline__ void tile_store(const SortArray &a,
+                                           const typename ElemOf<PAIRS>::type *s, uint32_t base,
+                                           uint32_t T) {
+    if constexpr (MODE == kPlainVec) {
+        for (uint32_t p = threadIdx.x * 4; p < T; p += NT * 4) {
+            if constexpr (PAIRS) {
+                const uint64_t e0 = s[p], e1 = s[p + 1], e2 = s[p + 2], e3 = s[p + 3];
+                *reinterpret_cast<uint4 *>(a.keys + base + p) =
+                    make_uint4((uint32_t)(e0 >> 32), (uint32_t)(e1 >> 32), (uint32_t)(e2 >> 32),
+                               (uint32_t)(e3 >> 32));
+                *reinterpret_cast<uint4 *>(a.vals + base + p) =
+                    make_uint4((uint32_t)e0, (uint32_t)e1, (uint32_t)e2, (uint32_t)e3);
+            } else {
+                *reinterpret_cast<uint4 *>(a.keys + base + p) =
+                    *reinterpret_cast<const uint4 *>(s + p);
+            }
+        }
+    } else {
+        for (uint32_t p = threadIdx.x; p < T; p += NT) store_elem<PAIRS, MODE>(a, base + p, s[p]);
+    }
+}
+
+// Waits for this wave's LDS operations and keeps the compiler from moving
+// memory operations across the point.
+__device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// Figure 1's region as written: each side holds its own loads, compare and
+// conditional swap.
+template <typename E>
+__device__ __forceinline__ void cex_divergent(E *s, uint32_t lo, uint32_t hi, bool up) {
+    // The marks keep each side's loads and stores inside that side: without
+    // them the compiler sinks the two identical swap-store blocks into one,
+    // which would already be a (partial) meld.
+    if (up) {
+        MELD_SIDE_MARK("ascending");
+        const E a = s[lo];
+        const E b = s[hi];
+        if (b < a) {
+            s[lo] = b;
+            s[hi] = a;
+            MELD_SIDE_MARK("ascending swap");
+        }
+    } else {
+        MELD_SIDE_MARK("descending");
+        const E a = s[lo];
+        const E b = s[hi];
+        if (b > a) {
+            s[lo] = b;
+            s[hi] = a;
+            MELD_SIDE_MARK("descending swap");
+        }
+    }
+}
+
+// The melded region: one load pair, both compares, a select of the swap
+// condition, one conditional store pair.
+template <typename E>
+__device__ __forceinline__ void cex_melded(E *s, uint32_t lo, uint32_t hi, bool up) {
+    const E a = s[lo];
+    const E b = s[hi];
+    const bool lt = b < a;
+    const bool gt = b > a;
+    const bool swap = (up & lt) | (!up & gt);  // select(up, lt, gt) on lane masks
+    if (swap) {
+        s[lo] = b;
+        s[hi] = a;
+    }
+}
+
+template <bool PAIRS, bool MELDED, int NT, int MODE>
+__global__ __launch_bounds__(NT) void bitonic_tile_kernel(SortArray a, uint32_t log_t,
+                                                          uint32_t m_begin, uint32_t m_end,
+                                                          uint32_t j_first, int32_t step_limit) {
+    using E = typename ElemOf<PAIRS>::type;
+    extern __shared__ __align__(16) unsigned char smem[];
+    E *s = reinterpret_cast<E *>(smem);
+    const uint32_t T = 1u << log_t;
+    const uint32_t half = T >> 1;
+    const uint32_t base = blockIdx.x << log_t;
+    const uint32_t tid = threadIdx.x;
+
+    const bool below_n = MODE == kTail && base + T <= a.n;  // uniform per workgroup
+    if (below_n)
+        tile_load<PAIRS, kPlain, NT>(a, s, base, T);
+    else
+        tile_load<PAIRS, MODE, NT>(a, s, base, T);
+    __syncthreads();
+
+    int32_t steps = 0;
+    bool stop = false;
+    for (uint32_t m = m_begin; m <= m_end && !stop; ++m) {
+        const uint32_t k = 1u << m;
+        for (uint32_t j = (m == m_begin) ? (1u << j_first) : (k >> 1); j > 0; j >>= 1) {
+            if (steps == step_limit) {
+                stop = true;
+                break;
+            }
+            ++steps;
+            for (uint32_t c = tid; c < half; c += NT) {
+                const uint32_t lo = ((c & ~(j - 1)) << 1) | (c & (j - 1));
+                const uint32_t hi = lo + j;
+                const bool up = (((base | lo) >> m) & 1u) == 0;
+                if constexpr (MELDED)
+                    cex_melded(s, lo, hi, up);
+                else
+                    cex_divergent(s, lo, hi, up);
+            }
+            const bool next_crosses_waves = (j >= 128) || (j == 1 && k >= 128);
+            if (next_crosses_waves)
+                __syncthreads();
+            else
+                wave_lds_sync();
+        }
+    }
+    __syncthreads();
+    if (below_n)
+        tile_store<PAIRS, kPlain, NT>(a, s, base, T);
+    else
+        tile_store<PAIRS, MODE, NT>(a, s, base, T);
+}
+
+template <typename E>
+__device__ __forceinline__ void cex_regs(E &x, E &y, bool up) {
+    const E mn = x < y ? x : y;
+    const E mx = x < y ? y : x;
+    x = up ? mn : mx;
+    y = up ? mx : mn;
+}
+
+constexpr int kGlobalThreads = 256;
+
+template <bool PAIRS, int R, int MODE>
+__global__ __launch_bounds__(kGlobalThreads) void bitonic_global_kernel(SortArray a,
+                                                                      uint32_t n_threads,
+                                                                      uint32_t m, uint32_t b_lo,
+                                                                      int32_t nsteps) {
+    using E = typename ElemOf<PAIRS>::type;
+    const uint32_t t = blockIdx.x * kGlobalThreads + threadIdx.x;
+    if (t >= n_threads) return;
+    const uint32_t low = t & ((1u << b_lo) - 1);
+    const uint32_t base = ((t >> b_lo) << (b_lo + R)) | low;
+    const bool up = ((base >> m) & 1u) == 0;
+    E e[1 << R];
+#pragma unroll
+    for (int q = 0; q < (1 << R); ++q)
+        e[q] = load_elem<PAIRS, MODE>(a, base + ((uint32_t)q << b_lo));
+#pragma unroll
+    for (int s = R - 1; s >= 0; --s) {
+        if (R - 1 - s < nsteps) {
+#pragma unroll
+            for (int q = 0; q < (1 << R); ++q)
+                if ((q & (1 << s)) == 0) cex_regs(e[q], e[q | (1 << s)], up);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < (1 << R); ++q)
+        store_elem<PAIRS, MODE>(a, base + ((uint32_t)q << b_lo), e[q]);
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, uint32_t value, size_t count) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = value;
+}
+
+template <bool PAIRS, bool MELDED, int NT, int MODE>
+hipError_t launch_tile_m(const SortArray &a, uint32_t log_t, uint32_t n_tiles, uint32_t m_begin,
+                         uint32_t m_end, uint32_t j_first, int32_t step_limit,
+                         hipStream_t stream) {
+    using E = typename ElemOf<PAIRS>::type;
+    const size_t lds = ((size_t)1 << log_t) * sizeof(E);
+    auto kern = bitonic_tile_kernel<PAIRS, MELDED, NT, MODE>;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3(n_tiles), dim3(NT), lds, stream, a, log_t, m_begin, m_end,
+                       j_first, step_limit);
+    return hipGetLastError();
+}
+
+template <bool PAIRS, bool MELDED, int NT>
+hipError_t launch_tile_t(const SortArray &a, uint32_t log_t, uint32_t n_tiles, uint32_t m_begin,
+                         uint32_t m_end, uint32_t j_first, int32_t step_limit, int io_mode,
+                         hipStream_t stream) {
+    switch (io_mode) {
+        case kPlain:
+            return launch_tile_m<PAIRS, MELDED, NT, kPlain>(a, log_t, n_tiles, m_begin, m_end,
+                                                            j_first, step_limit, stream);
+        case kPlainVec:
+            return launch_tile_m<PAIRS, MELDED, NT, kPlainVec>(a, log_t, n_tiles, m_begin, m_end,
+                                                               j_first, step_limit, stream);
+        case kTail:
+            return launch_tile_m<PAIRS, MELDED, NT, kTail>(a, log_t, n_tiles, m_begin, m_end,
+                                                           j_first, step_limit, stream);
+        case kSentinel:
+            return launch_tile_m<PAIRS, MELDED, NT, kSentinel>(a, log_t, n_tiles, m_begin, m_end,
+                                                               j_first, step_limit, stream);
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+template <bool PAIRS, bool MELDED>
+hipError_t launch_tile_nt(const SortArray &a, uint32_t log_t, uint32_t n_tiles, uint32_t m_begin,
+                          uint32_t m_end, uint32_t j_first, int32_t step_limit, int io_mode,
+                          int threads, hipStream_t stream) {
+    switch (threads) {
+        case 64:
+            return launch_tile_t<PAIRS, MELDED, 64>(a, log_t, n_tiles, m_begin, m_end, j_first,
+                                                    step_limit, io_mode, stream);
+        case 256:
+            return launch_tile_t<PAIRS, MELDED, 256>(a, log_t, n_tiles, m_begin, m_end, j_first,
+                                                     step_limit, io_mode, stream);
+        case 512:
+            return launch_tile_t<PAIRS, MELDED, 512>(a, log_t, n_tiles, m_begin, m_end, j_first,
+                                                     step_limit, io_mode, stream);
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+template <bool PAIRS, int R, int MODE>
+hipError_t launch_global_r(const SortArray &a, uint32_t log_n, uint32_t m, uint32_t b_lo,
+                           int32_t step_limit, hipStream_t stream) {
+    const uint32_t n_threads = 1u << (log_n - R);
+    const uint32_t blocks = (n_threads + kGlobalThreads - 1) / kGlobalThreads;
+    hipLaunchKernelGGL((bitonic_global_kernel<PAIRS, R, MODE>), dim3(blocks),
+                       dim3(kGlobalThreads), 0, stream, a, n_threads, m, b_lo,
+                       step_limit < 0 ? R : step_limit);
+    return hipGetLastError();
+}
+
+template <bool PAIRS, int MODE>
+hipError_t launch_global_p(const SortArray &a, uint32_t log_n, uint32_t m, uint32_t b_hi,
+                           uint32_t b_lo, int32_t step_limit, hipStream_t stream) {
+    switch (b_hi - b_lo + 1) {
+        case 1: return launch_global_r<PAIRS, 1, MODE>(a, log_n, m, b_lo, step_limit, stream);
+        case 2: return launch_global_r<PAIRS, 2, MODE>(a, log_n, m, b_lo, step_limit, stream);
+        case 3: return launch_global_r<PAIRS, 3, MODE>(a, log_n, m, b_lo, step_limit, stream);
+        case 4: return launch_global_r<PAIRS, 4, MODE>(a, log_n, m, b_lo, step_limit, stream);
+        case 5: return launch_global_r<PAIRS, 5, MODE>(a, log_n, m, b_lo, step_limit, stream);
+        case 6: return launch_global_r<PAIRS, 6, MODE>(a, log_n, m, b_lo, step_limit, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_bitonic_tile(const SortArray &a, uint32_t log_t, uint32_t n_tiles,
+                               uint32_t m_begin, uint32_t m_end, uint32_t j_first,
+                               int32_t step_limit, bool melded, int io_mode, int threads,
+                               hipStream_t stream) {
+    if (n_tiles == 0 || step_limit == 0) return hipSuccess;
+    if (io_mode == kPlainVec && log_t < 2) io_mode = kPlain;
+    const bool pairs = a.vals != nullptr;
+    if (pairs)
+        return melded ? launch_tile_nt<true, true>(a, log_t, n_tiles, m_begin, m_end, j_first,
+                                                   step_limit, io_mode, threads, stream)
+                      : launch_tile_nt<true, false>(a, log_t, n_tiles, m_begin, m_end, j_first,
+                                                    step_limit, io_mode, threads, stream);
+    return melded ? launch_tile_nt<false, true>(a, log_t, n_tiles, m_begin, m_end, j_first,
+                                                step_limit, io_mode, threads, stream)
+                  : launch_tile_nt<false, false>(a, log_t, n_tiles, m_begin, m_end, j_first,
+                                                 step_limit, io_mode, threads, stream);
+}
+
+hipError_t launch_bitonic_global(const SortArray &a, uint32_t log_n, uint32_t m, uint32_t b_hi,
+                                 uint32_t b_lo, int32_t step_limit, hipStream_t stream) {
+    if (step_limit == 0) return hipSuccess;
+    const bool tail = a.tk != nullptr;
+    if (a.vals != nullptr)
+        return tail ? launch_global_p<true, kTail>(a, log_n, m, b_hi, b_lo, step_limit, stream)
+                    : launch_global_p<true, kPlain>(a, log_n, m, b_hi, b_lo, step_limit, stream);
+    return tail ? launch_global_p<false, kTail>(a, log_n, m, b_hi, b_lo, step_limit, stream)
+                : launch_global_p<false, kPlain>(a, log_n, m, b_hi, b_lo, step_limit, stream);
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t count, hipStream_t stream) {
+    if (count == 0) return hipSuccess;
+    const int threads = 256;
+    const size_t blocks = (count + threads - 1) / threads;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((uint32_t)blocks), dim3(threads), 0, stream, p,
+                       value, count);
+    return hipGetLastError();
+}
+
+}  // namespace meld

@@ -1,0 +1,33 @@
+// Shared device-side helpers of the melded kernel library (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace meld {
+
+constexpr int kWave = 64;
+constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+
+// SplitMix64 output mixer (Steele, Lea and Flood, OOPSLA 2014).
+__host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z ^= z >> 30;
+    z *= 0xBF58476D1CE4E5B9ull;
+    z ^= z >> 27;
+    z *= 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return z;
+}
+
+// Key of stream `tag` for `seed`: counter i of that stream is mix64(key + i).
+__host__ __device__ __forceinline__ uint64_t stream_key(uint64_t seed, uint64_t tag) {
+    return mix64(seed + tag * kGolden);
+}
+
+// Compiler-only fence: keeps the compiler from moving memory operations
+// across it and, because the text differs per call site, from treating two
+// sides of a branch as identical code (no hoisting or sinking of common
+// instructions out of the sides). Emits no instruction.
+#define MELD_SIDE_MARK(tag) asm volatile("; side " tag ::: "memory")
+
+}  // namespace meld

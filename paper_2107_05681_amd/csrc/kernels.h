@@ -1,0 +1,59 @@
+// Internal launch interface between the C-ABI host layer and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace meld {
+
+struct RegionSide {
+    float a;
+    uint32_t off;
+    uint32_t step;
+    uint32_t trips;
+};
+
+enum class RegionForm { kDivergent, kMelded, kMeldedInPlace };
+
+hipError_t launch_region(const float *x, float *y, uint32_t n, const float *tab, uint32_t mask,
+                         uint64_t seed, uint64_t thr, RegionSide T, RegionSide F, RegionForm form,
+                         hipStream_t stream);
+
+// Array with virtual padding: position p < n lives in keys/vals[p], position
+// n <= p < N in the tail workspace tk/tv[p - n] (pre-filled with the
+// sentinel); without a workspace, positions >= n read as the sentinel and
+// are not written.
+struct SortArray {
+    uint32_t *keys;
+    uint32_t *vals;  // NULL for keys-only
+    uint32_t *tk;    // tail workspace for keys (may be NULL)
+    uint32_t *tv;    // tail workspace for vals (may be NULL)
+    uint32_t n;
+};
+
+// Runs, on every tile of 2^log_t elements, the network steps of phases
+// k = 2^m for m in [m_begin, m_end], starting phase m_begin at j = 2^j_first
+// (later phases start at j = k/2). At most step_limit steps run (negative:
+// all). Tiles: n_tiles. Threads per workgroup: 64, 256 or 512.
+// io_mode: 0 plain, 1 plain with 16-byte aligned arrays (vector I/O),
+// 2 tail workspace, 3 sentinel padding of a single tile.
+constexpr int kIoPlain = 0, kIoPlainVec = 1, kIoTail = 2, kIoSentinel = 3;
+hipError_t launch_bitonic_tile(const SortArray &a, uint32_t log_t, uint32_t n_tiles,
+                               uint32_t m_begin, uint32_t m_end, uint32_t j_first,
+                               int32_t step_limit, bool melded, int io_mode, int threads,
+                               hipStream_t stream);
+
+// One streaming pass over all N = 2^log_n elements for the steps
+// j = 2^b_hi .. 2^b_lo of phase k = 2^m (b_hi - b_lo + 1 <= kMaxFusedSteps),
+// all in registers. At most step_limit steps run (negative: all).
+constexpr uint32_t kMaxFusedSteps = 6;
+hipError_t launch_bitonic_global(const SortArray &a, uint32_t log_n, uint32_t m, uint32_t b_hi,
+                                 uint32_t b_lo, int32_t step_limit, hipStream_t stream);
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t count, hipStream_t stream);
+
+// Largest tile (log2 elements) the tile kernel supports for keys / pairs.
+constexpr uint32_t kMaxLogTileKeys = 14;
+constexpr uint32_t kMaxLogTilePairs = 13;
+
+}  // namespace meld

@@ -1,0 +1,225 @@
+// Two-sided loop region: divergent (IPDOM) and melded forms.
+//
+// Per lane i the region computes (Evaluation section, "Synthetic Benchmarks":
+// a divergent region inside a loop whose two sides hold the same instruction
+// sequence on different data):
+//   taken = (mix64(bkey + i) >> 32) < thr
+//   s     = taken ? T : F
+//   acc   = x[i];  for k < s.trips: acc = fma(acc, s.a, tab[(i + s.off + k*s.step) & mask])
+//   y[i]  = acc
+//
+// Divergent form: `if (taken) loop_T else loop_F`. In a wave holding both
+// kinds of lanes the two loops run one after the other under exec masks.
+//
+// Melded form (Detailed Design section, Algorithm 2 and "Unpredication"):
+// the two loops are isomorphic subgraphs and become one loop whose exit runs
+// to min(T.trips, F.trips), which both sides share; the |T.trips - F.trips|
+// steps only the longer side has are unaligned and run in a conditional block
+// entered by that side's lanes only, with that side's own (uniform) operands.
+// Inside the melded loop the fma is aligned (its multiplier selected once per
+// lane, a v_cndmask). The gathers read different addresses on the two sides;
+// the library leaves them unaligned, each side's batch of gathers in one
+// conditional block, because on gfx950 one gather serving two address
+// streams costs more than two single-stream gathers (the paper notes the same
+// for global memory: melded accesses to different cache lines gain little).
+// The form with the gathers aligned too is kept as MELD_MELDED_INPLACE.
+//
+// Both forms issue the gathers of a batch of consecutive steps before the
+// dependent fmas (the gathers do not depend on acc), and both keep the fma
+// order of the definition, so their results are bit-identical.
+#include "device_common.h"
+#include "kernels.h"
+
+namespace meld {
+
+namespace {
+
+constexpr int kRegionThreads = 256;
+
+// Steps of one side. The gathers of B consecutive steps are issued before the
+// B dependent fmas (the gathers do not depend on acc); the last steps%B steps
+// issue their gathers back to back too (guards on the uniform count).
+template <int B, bool GUARDED_TAIL>
+__device__ __forceinline__ float side_steps_t(float acc, uint32_t idx, uint32_t steps, float a,
+                                              uint32_t step, const float *__restrict__ tab,
+                                              uint32_t mask) {
+    uint32_t k = 0;
+    for (; k + B <= steps; k += B) {
+        float g[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) g[u] = tab[(idx + (uint32_t)u * step) & mask];
+#pragma unroll
+        for (int u = 0; u < B; ++u) acc = __builtin_fmaf(acc, a, g[u]);
+        idx += (uint32_t)B * step;
+    }
+    if constexpr (GUARDED_TAIL) {
+        const uint32_t rem = steps - k;
+        if (rem != 0) {
+            float g[B - 1];
+#pragma unroll
+            for (int u = 0; u < B - 1; ++u)
+                if ((uint32_t)u < rem) g[u] = tab[(idx + (uint32_t)u * step) & mask];
+#pragma unroll
+            for (int u = 0; u < B - 1; ++u)
+                if ((uint32_t)u < rem) acc = __builtin_fmaf(acc, a, g[u]);
+        }
+    } else {
+        for (; k < steps; ++k) {
+            acc = __builtin_fmaf(acc, a, tab[idx & mask]);
+            idx += step;
+        }
+    }
+    return acc;
+}
+
+// Batch 8 with a guarded tail was the fastest divergent form in a sweep of
+// batch 4..32 at 2^24 lanes (larger batches lengthen the guarded tail).
+constexpr int kBatch = 8;
+
+__device__ __forceinline__ float side_steps(float acc, uint32_t idx, uint32_t steps, float a,
+                                            uint32_t step, const float *__restrict__ tab,
+                                            uint32_t mask) {
+    return side_steps_t<kBatch, true>(acc, idx, steps, a, step, tab, mask);
+}
+
+__device__ __forceinline__ bool branch_taken(uint64_t bkey, uint32_t i, uint64_t thr) {
+    return (mix64(bkey + i) >> 32) < thr;
+}
+
+__global__ __launch_bounds__(kRegionThreads) void region_divergent_kernel(
+    const float *__restrict__ x, float *__restrict__ y, uint32_t n, const float *__restrict__ tab,
+    uint32_t mask, uint64_t bkey, uint64_t thr, RegionSide T, RegionSide F) {
+    const uint32_t i = blockIdx.x * kRegionThreads + threadIdx.x;
+    if (i >= n) return;
+    const bool taken = branch_taken(bkey, i, thr);
+    float acc = x[i];
+    if (taken) {
+        MELD_SIDE_MARK("true");
+        acc = side_steps(acc, i + T.off, T.trips, T.a, T.step, tab, mask);
+    } else {
+        MELD_SIDE_MARK("false");
+        acc = side_steps(acc, i + F.off, F.trips, F.a, F.step, tab, mask);
+    }
+    y[i] = acc;
+}
+
+// Melded loop over the steps both sides have, with the gathers left
+// unaligned: the side-specific gathers of a batch sit in one conditional
+// block per side (what unpredication makes of consecutive unaligned
+// instructions), while the index arithmetic, the fma chain and the loop
+// control run once on the whole wave with the multiplier selected per lane.
+template <int B>
+__device__ __forceinline__ float melded_common_steps(float acc, bool taken, uint32_t idx_t,
+                                                     uint32_t idx_f, uint32_t steps, float a,
+                                                     uint32_t step_t, uint32_t step_f,
+                                                     const float *__restrict__ tab,
+                                                     uint32_t mask) {
+    uint32_t k = 0;
+    for (; k + B <= steps; k += B) {
+        float g[B];
+        if (taken) {
+            MELD_SIDE_MARK("gathers true");
+#pragma unroll
+            for (int u = 0; u < B; ++u) g[u] = tab[(idx_t + (uint32_t)u * step_t) & mask];
+        } else {
+            MELD_SIDE_MARK("gathers false");
+#pragma unroll
+            for (int u = 0; u < B; ++u) g[u] = tab[(idx_f + (uint32_t)u * step_f) & mask];
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u) acc = __builtin_fmaf(acc, a, g[u]);
+        idx_t += (uint32_t)B * step_t;
+        idx_f += (uint32_t)B * step_f;
+    }
+    const uint32_t rem = steps - k;
+    if (rem != 0) {
+        float g[B - 1];
+        if (taken) {
+            MELD_SIDE_MARK("gathers true");
+#pragma unroll
+            for (int u = 0; u < B - 1; ++u)
+                if ((uint32_t)u < rem) g[u] = tab[(idx_t + (uint32_t)u * step_t) & mask];
+        } else {
+            MELD_SIDE_MARK("gathers false");
+#pragma unroll
+            for (int u = 0; u < B - 1; ++u)
+                if ((uint32_t)u < rem) g[u] = tab[(idx_f + (uint32_t)u * step_f) & mask];
+        }
+#pragma unroll
+        for (int u = 0; u < B - 1; ++u)
+            if ((uint32_t)u < rem) acc = __builtin_fmaf(acc, a, g[u]);
+    }
+    return acc;
+}
+
+// Steps only the longer side has: unaligned, run by that side's lanes with
+// that side's own operands.
+__device__ __forceinline__ float longer_side_steps(float acc, uint32_t i, bool taken,
+                                                   const float *__restrict__ tab, uint32_t mask,
+                                                   const RegionSide &T, const RegionSide &F,
+                                                   uint32_t common) {
+    const bool true_longer = T.trips > F.trips;
+    const uint32_t extra = true_longer ? T.trips - common : F.trips - common;
+    if (extra != 0 && taken == true_longer) {
+        const RegionSide L = true_longer ? T : F;
+        acc = side_steps(acc, i + L.off + common * L.step, extra, L.a, L.step, tab, mask);
+    }
+    return acc;
+}
+
+// The melded form used by the library.
+__global__ __launch_bounds__(kRegionThreads) void region_melded_kernel(
+    const float *__restrict__ x, float *__restrict__ y, uint32_t n, const float *__restrict__ tab,
+    uint32_t mask, uint64_t bkey, uint64_t thr, RegionSide T, RegionSide F) {
+    const uint32_t i = blockIdx.x * kRegionThreads + threadIdx.x;
+    if (i >= n) return;
+    const bool taken = branch_taken(bkey, i, thr);
+    const float a = taken ? T.a : F.a;  // differing operand of the aligned fma: a select
+    const uint32_t common = T.trips < F.trips ? T.trips : F.trips;
+    float acc = x[i];
+    acc = melded_common_steps<kBatch>(acc, taken, i + T.off, i + F.off, common, a,
+                                                 T.step, F.step, tab, mask);
+    y[i] = longer_side_steps(acc, i, taken, tab, mask, T, F, common);
+}
+
+// The melded form with the gathers aligned as well: one gather instruction per
+// step serves both sides, its address selected per lane. This is the melded
+// code as the transformation emits it when it pairs the two loads; on gfx950
+// a gather whose lanes mix two address streams costs several times the
+// vector-memory work of one lane-linear stream, which makes this form slower
+// than the divergent one whenever the sides read different data.
+__global__ __launch_bounds__(kRegionThreads) void region_melded_inplace_kernel(
+    const float *__restrict__ x, float *__restrict__ y, uint32_t n, const float *__restrict__ tab,
+    uint32_t mask, uint64_t bkey, uint64_t thr, RegionSide T, RegionSide F) {
+    const uint32_t i = blockIdx.x * kRegionThreads + threadIdx.x;
+    if (i >= n) return;
+    const bool taken = branch_taken(bkey, i, thr);
+    const float a = taken ? T.a : F.a;
+    const uint32_t off = taken ? T.off : F.off;
+    const uint32_t step = taken ? T.step : F.step;
+    const uint32_t common = T.trips < F.trips ? T.trips : F.trips;
+    float acc = side_steps(x[i], i + off, common, a, step, tab, mask);
+    y[i] = longer_side_steps(acc, i, taken, tab, mask, T, F, common);
+}
+
+}  // namespace
+
+hipError_t launch_region(const float *x, float *y, uint32_t n, const float *tab, uint32_t mask,
+                         uint64_t seed, uint64_t thr, RegionSide T, RegionSide F, RegionForm form,
+                         hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    const uint64_t bkey = stream_key(seed, 4);
+    const dim3 grid((n + kRegionThreads - 1) / kRegionThreads);
+    if (form == RegionForm::kMelded)
+        hipLaunchKernelGGL(region_melded_kernel, grid, dim3(kRegionThreads), 0, stream, x, y, n,
+                           tab, mask, bkey, thr, T, F);
+    else if (form == RegionForm::kMeldedInPlace)
+        hipLaunchKernelGGL(region_melded_inplace_kernel, grid, dim3(kRegionThreads), 0, stream, x,
+                           y, n, tab, mask, bkey, thr, T, F);
+    else
+        hipLaunchKernelGGL(region_divergent_kernel, grid, dim3(kRegionThreads), 0, stream, x, y,
+                           n, tab, mask, bkey, thr, T, F);
+    return hipGetLastError();
+}
+
+}  // namespace meld

@@ -1,0 +1,150 @@
+"""GPU parity of the bitonic sort (both forms) against the CPU oracle.
+
+Bar: bit-exact. Keys-only output is unique; with a payload the
+lexicographic (key, payload) order makes it unique too. The stage tests pin
+that the GPU runs the Figure 1 network itself: after every prefix of steps
+the array equals the oracle's step-by-step emulation.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+meld = pytest.importorskip("paper_2107_05681_amd")
+
+VARIANTS = ("divergent", "melded")  # for the sorts MELDED_INPLACE == MELDED
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.uint32).view(np.int32)).to(_dev())
+
+
+def _to_host(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def _gpu_sort(keys, vals, variant):
+    kd = _to_dev(keys)
+    vd = None if vals is None else _to_dev(vals)
+    meld.sort(kd, vd, variant=variant)
+    torch.cuda.synchronize()
+    return _to_host(kd), (None if vd is None else _to_host(vd))
+
+
+SIZES = [2, 3, 63, 64, 65, 1000, 1025, 4096, 1 << 13, (1 << 13) + 1, 1 << 14, (1 << 14) + 1,
+         1 << 16, (1 << 17) + 3, 1 << 20]
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_sort_keys(n):
+    keys = workloads.keys_u32(n, n)
+    ref = oracle.sort_u32(keys)
+    for v in VARIANTS:
+        got, _ = _gpu_sort(keys, None, v)
+        assert np.array_equal(got, ref), (n, v)
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_sort_pairs(n):
+    keys = workloads.keys_u32(n + 1, n)
+    vals = workloads.iota_u32(n)
+    rk, rv = oracle.sort_pairs_u32(keys, vals)
+    for v in VARIANTS:
+        gk, gv = _gpu_sort(keys, vals, v)
+        assert np.array_equal(gk, rk) and np.array_equal(gv, rv), (n, v)
+
+
+def test_sort_pairs_heavy_ties_and_extremes():
+    n = (1 << 15) + 77
+    keys = (workloads.keys_u32(8, n) % np.uint32(5)).astype(np.uint32)
+    keys[::97] = 0xFFFFFFFF  # real elements equal to the padding sentinel
+    vals = (workloads.keys_u32(9, n) % np.uint32(3)).astype(np.uint32)
+    vals[::89] = 0xFFFFFFFF
+    rk, rv = oracle.sort_pairs_u32(keys, vals)
+    for v in VARIANTS:
+        gk, gv = _gpu_sort(keys, vals, v)
+        assert np.array_equal(gk, rk) and np.array_equal(gv, rv), v
+
+
+def test_sort_n_below_two_is_noop():
+    for n in (0, 1):
+        k = _to_dev(np.array([7] * n, np.uint32))
+        meld.sort(k)
+        assert _to_host(k).tolist() == [7] * n
+
+
+@pytest.mark.parametrize("log_n,pairs", [(10, False), (10, True), (15, False), (14, True),
+                                         (16, True)])
+def test_stage_parity_with_figure1_emulator(log_n, pairs):
+    n = 1 << log_n
+    keys = workloads.keys_u32(log_n, n)
+    vals = workloads.iota_u32(n) if pairs else None
+    total = oracle.bitonic_num_steps(n)
+    rng = np.random.default_rng(log_n)
+    if log_n <= 10:
+        checks = list(range(1, total + 1))
+    else:
+        checks = sorted(set([1, 2, 3, 21, 28, total - 1, total] +
+                            rng.integers(1, total, 12).tolist()))
+    for s in checks:
+        ref = oracle.bitonic_emulate(keys, vals, max_steps=s)
+        for v in VARIANTS:
+            kd = _to_dev(keys)
+            vd = None if vals is None else _to_dev(vals)
+            meld.sort_steps(kd, vd, max_steps=s, variant=v)
+            torch.cuda.synchronize()
+            if pairs:
+                assert np.array_equal(_to_host(kd), ref[0]) and \
+                    np.array_equal(_to_host(vd), ref[1]), (s, v)
+            else:
+                assert np.array_equal(_to_host(kd), ref), (s, v)
+
+
+def test_sort_pairs_full_size_properties():
+    # 2^28 (key, payload = index) pairs. A non-decreasing composite order plus
+    # key[i] == in_key[payload[i]] plus payload being a permutation fixes the
+    # output completely, so this is an exact check at full size.
+    dev = _dev()
+    n = 1 << 28
+    keys = workloads.keys_u32(1, n)
+    kin = torch.from_numpy(keys.view(np.int32)).to(dev)
+    del keys
+    for v in VARIANTS:
+        k = kin.clone()
+        p = torch.arange(n, dtype=torch.int32, device=dev)
+        meld.sort(k, p, variant=v)
+        torch.cuda.synchronize()
+        # (key - 2^31) * 2^32 + payload orders like the unsigned (key, payload)
+        # pair and fits a signed 64-bit integer.
+        k64 = (k.to(torch.int64) & 0xFFFFFFFF) - (1 << 31)
+        comp = (k64 << 32) + (p.to(torch.int64) & 0xFFFFFFFF)
+        del k64
+        assert bool((comp[1:] > comp[:-1]).all()), v
+        del comp
+        seen = torch.zeros(n, dtype=torch.bool, device=dev)
+        seen[p.long()] = True
+        assert bool(seen.all()), v
+        del seen
+        assert torch.equal(kin[p.long()], k), v
+        del k, p
+        torch.cuda.empty_cache()
+
+
+def test_sort_rejects_host_pointer():
+    import ctypes
+    lib = meld.load_library()
+    _dev()
+    host = (ctypes.c_uint32 * 64)()
+    st = lib.meld_sort_u32(meld.context(0), ctypes.cast(host, ctypes.c_void_p), None, 64, 1, None)
+    assert st == meld.EINVAL
+    assert b"device pointer" in lib.meld_last_error()
