@@ -73,6 +73,17 @@ meld_status meld_create(int hip_device, meld_ctx **out);
 /* Waits for the context's pending work and frees its scratch. NULL is a no-op. */
 void meld_destroy(meld_ctx *ctx);
 
+typedef enum {
+    /* 1 (default): segmented sorts replay a captured hipGraph of their five
+     * launches (captured once per keys/offsets/nseg/forms, at most 8 kept);
+     * 0: launch them one by one. A stream that is itself being captured
+     * always gets the launches directly. */
+    MELD_OPT_USE_GRAPHS = 0
+} meld_option;
+
+/* Sets a context option. MELD_EINVAL for an unknown option. */
+meld_status meld_set_option(meld_ctx *ctx, meld_option option, int64_t value);
+
 /* Message of the last failed call on this host thread ("" if none). The
  * pointer stays valid until the next library call on the same thread. */
 const char *meld_last_error(void);
@@ -113,6 +124,10 @@ meld_status meld_sort_u32_steps(meld_ctx *ctx, uint32_t *keys, uint32_t *payload
  * offsets: device u32[nseg + 1], offsets[0] = 0, non-decreasing. Segments
  *          may be empty. Segment length <= 65536.
  * nseg:    number of segments, < 2^31; 0 is a no-op.
+ * Runs as one persistent launch after three small planning kernels that
+ * build a largest-first work queue on the device; nothing is read back to
+ * the host. Scratch: 17 bytes per segment plus 128 KiB per CU, owned by the
+ * context.
  * Errors:  MELD_EINVAL for NULL/host pointers. Offsets live on the device
  *          and are not inspected on the host: a segment longer than 65536,
  *          decreasing offsets or offsets[0] != 0 leave the keys untouched
@@ -122,9 +137,18 @@ meld_status meld_sort_u32_steps(meld_ctx *ctx, uint32_t *keys, uint32_t *payload
 meld_status meld_segmented_sort_u32(meld_ctx *ctx, uint32_t *keys, const uint32_t *offsets,
                                     size_t nseg, meld_variant variant, void *stream);
 
-/* Synchronises `stream` and reports whether the last segmented sorts on the
- * context found invalid offsets (MELD_EINVAL, with the reason) or not
- * (MELD_OK). Clears the flag. */
+/* As meld_segmented_sort_u32, with the form chosen per stage: low_phases for
+ * the phases k <= 64, whose direction bit is one of the six lane bits (the
+ * direction branch is divergent inside a wave), high_phases for the phases
+ * k >= 128 (direction uniform per wave). Used by the tuner and for
+ * per-stage measurements. MELD_AUTO counts as MELD_MELDED here. */
+meld_status meld_segmented_sort_u32_staged(meld_ctx *ctx, uint32_t *keys, const uint32_t *offsets,
+                                           size_t nseg, meld_variant low_phases,
+                                           meld_variant high_phases, void *stream);
+
+/* Synchronises `stream` and reports whether any segmented sort on the context
+ * since the last check found invalid offsets (MELD_EINVAL, with the reason)
+ * or not (MELD_OK). Clears the flag. */
 meld_status meld_segmented_sort_check(meld_ctx *ctx, void *stream);
 
 /* One side of the two-sided loop region: multiplier, table offset, index

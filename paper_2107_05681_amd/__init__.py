@@ -29,7 +29,8 @@ _STATUS = {1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "EUNSUPPORTED"}
 
 # Every function the C header declares.
 EXPORTS = ("meld_version", "meld_create", "meld_destroy", "meld_last_error", "meld_sort_u32",
-           "meld_sort_u32_steps", "meld_segmented_sort_u32", "meld_segmented_sort_check",
+           "meld_sort_u32_steps", "meld_segmented_sort_u32", "meld_segmented_sort_u32_staged",
+           "meld_segmented_sort_check", "meld_set_option",
            "meld_divergent_region_f32")
 
 
@@ -74,8 +75,12 @@ def load_library():
     lib.meld_sort_u32_steps.argtypes = [vp, vp, vp, sz, i64, st, vp]
     lib.meld_segmented_sort_u32.restype = st
     lib.meld_segmented_sort_u32.argtypes = [vp, vp, vp, sz, st, vp]
+    lib.meld_segmented_sort_u32_staged.restype = st
+    lib.meld_segmented_sort_u32_staged.argtypes = [vp, vp, vp, sz, st, st, vp]
     lib.meld_segmented_sort_check.restype = st
     lib.meld_segmented_sort_check.argtypes = [vp, vp]
+    lib.meld_set_option.restype = st
+    lib.meld_set_option.argtypes = [vp, st, i64]
     lib.meld_divergent_region_f32.restype = st
     lib.meld_divergent_region_f32.argtypes = [vp, vp, vp, sz, vp, sz, u64, u64, Side, Side, st, vp]
     _lib = lib
@@ -150,16 +155,27 @@ def sort_steps(keys, payload=None, max_steps=-1, variant=AUTO, stream=None):
     return keys if payload is None else (keys, payload)
 
 
-def segmented_sort(keys, offsets, variant=AUTO, stream=None):
-    """Sorts every segment keys[offsets[s]:offsets[s+1]] in place."""
+def segmented_sort(keys, offsets, variant=AUTO, stream=None, low=None, high=None):
+    """Sorts every segment keys[offsets[s]:offsets[s+1]] in place.
+
+    ``low`` / ``high`` pick the form per stage (phases k <= 64 / k >= 128);
+    when either is given the other defaults to ``variant``."""
     _u32_tensor(keys, "keys")
     _u32_tensor(offsets, "offsets")
+    if offsets.device != keys.device:
+        raise ValueError("keys and offsets must be on the same device")
+    nseg = max(offsets.numel() - 1, 0)
+    if keys.numel() == 0 or nseg == 0:
+        return keys
     lib = load_library()
-    _check(lib.meld_segmented_sort_u32(context(keys.device.index),
-                                       ctypes.c_void_p(keys.data_ptr()),
-                                       ctypes.c_void_p(offsets.data_ptr()),
-                                       max(offsets.numel() - 1, 0), _variant(variant),
-                                       _stream_of(keys, stream)))
+    args = (context(keys.device.index), ctypes.c_void_p(keys.data_ptr()),
+            ctypes.c_void_p(offsets.data_ptr()), nseg)
+    if low is None and high is None:
+        _check(lib.meld_segmented_sort_u32(*args, _variant(variant), _stream_of(keys, stream)))
+    else:
+        lo = _variant(variant if low is None else low)
+        hi = _variant(variant if high is None else high)
+        _check(lib.meld_segmented_sort_u32_staged(*args, lo, hi, _stream_of(keys, stream)))
     return keys
 
 
@@ -169,6 +185,14 @@ def segmented_sort_check(device: int = 0, stream=None):
     lib = load_library()
     s = stream if stream is not None else torch.cuda.current_stream(device)
     _check(lib.meld_segmented_sort_check(context(device), ctypes.c_void_p(s.cuda_stream)))
+
+
+OPT_USE_GRAPHS = 0
+
+
+def set_option(device: int, option: int, value: int) -> None:
+    """Sets a context option (see meld_set_option)."""
+    _check(load_library().meld_set_option(context(device), int(option), int(value)))
 
 
 def side(a: float, off: int, step: int, trips: int) -> Side:

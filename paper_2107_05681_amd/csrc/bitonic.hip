@@ -37,6 +37,7 @@
 // coincide there and a single kernel serves them.
 #include "device_common.h"
 #include "kernels.h"
+#include "network.h"
 
 namespace meld {
 
@@ -157,53 +158,6 @@ __device__ __forceinline__ void tile_store(const SortArray &a,
     }
 }
 
-// Waits for this wave's LDS operations and keeps the compiler from moving
-// memory operations across the point.
-__device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
-
-// Figure 1's region as written: each side holds its own loads, compare and
-// conditional swap.
-template <typename E>
-__device__ __forceinline__ void cex_divergent(E *s, uint32_t lo, uint32_t hi, bool up) {
-    // The marks keep each side's loads and stores inside that side: without
-    // them the compiler sinks the two identical swap-store blocks into one,
-    // which would already be a (partial) meld.
-    if (up) {
-        MELD_SIDE_MARK("ascending");
-        const E a = s[lo];
-        const E b = s[hi];
-        if (b < a) {
-            s[lo] = b;
-            s[hi] = a;
-            MELD_SIDE_MARK("ascending swap");
-        }
-    } else {
-        MELD_SIDE_MARK("descending");
-        const E a = s[lo];
-        const E b = s[hi];
-        if (b > a) {
-            s[lo] = b;
-            s[hi] = a;
-            MELD_SIDE_MARK("descending swap");
-        }
-    }
-}
-
-// The melded region: one load pair, both compares, a select of the swap
-// condition, one conditional store pair.
-template <typename E>
-__device__ __forceinline__ void cex_melded(E *s, uint32_t lo, uint32_t hi, bool up) {
-    const E a = s[lo];
-    const E b = s[hi];
-    const bool lt = b < a;
-    const bool gt = b > a;
-    const bool swap = (up & lt) | (!up & gt);  // select(up, lt, gt) on lane masks
-    if (swap) {
-        s[lo] = b;
-        s[hi] = a;
-    }
-}
-
 template <bool PAIRS, bool MELDED, int NT, int MODE>
 __global__ __launch_bounds__(NT) void bitonic_tile_kernel(SortArray a, uint32_t log_t,
                                                           uint32_t m_begin, uint32_t m_end,
@@ -212,9 +166,7 @@ __global__ __launch_bounds__(NT) void bitonic_tile_kernel(SortArray a, uint32_t 
     extern __shared__ __align__(16) unsigned char smem[];
     E *s = reinterpret_cast<E *>(smem);
     const uint32_t T = 1u << log_t;
-    const uint32_t half = T >> 1;
     const uint32_t base = blockIdx.x << log_t;
-    const uint32_t tid = threadIdx.x;
 
     const bool below_n = MODE == kTail && base + T <= a.n;  // uniform per workgroup
     if (below_n)
@@ -222,33 +174,8 @@ __global__ __launch_bounds__(NT) void bitonic_tile_kernel(SortArray a, uint32_t 
     else
         tile_load<PAIRS, MODE, NT>(a, s, base, T);
     __syncthreads();
-
-    int32_t steps = 0;
-    bool stop = false;
-    for (uint32_t m = m_begin; m <= m_end && !stop; ++m) {
-        const uint32_t k = 1u << m;
-        for (uint32_t j = (m == m_begin) ? (1u << j_first) : (k >> 1); j > 0; j >>= 1) {
-            if (steps == step_limit) {
-                stop = true;
-                break;
-            }
-            ++steps;
-            for (uint32_t c = tid; c < half; c += NT) {
-                const uint32_t lo = ((c & ~(j - 1)) << 1) | (c & (j - 1));
-                const uint32_t hi = lo + j;
-                const bool up = (((base | lo) >> m) & 1u) == 0;
-                if constexpr (MELDED)
-                    cex_melded(s, lo, hi, up);
-                else
-                    cex_divergent(s, lo, hi, up);
-            }
-            const bool next_crosses_waves = (j >= 128) || (j == 1 && k >= 128);
-            if (next_crosses_waves)
-                __syncthreads();
-            else
-                wave_lds_sync();
-        }
-    }
+    lds_network<E, MELDED, MELDED, NT, true>(s, T, base, m_begin, m_end, j_first, step_limit,
+                                            threadIdx.x);
     __syncthreads();
     if (below_n)
         tile_store<PAIRS, kPlain, NT>(a, s, base, T);

@@ -52,6 +52,36 @@ hipError_t launch_bitonic_global(const SortArray &a, uint32_t log_n, uint32_t m,
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t count, hipStream_t stream);
 
+// Segmented sort (segsort.hip).
+constexpr uint32_t kSegThreads = 1024;
+constexpr uint32_t kSegLogTile = 15;  // 2^15 keys = 128 KiB of LDS per workgroup
+constexpr uint32_t kSegTile = 1u << kSegLogTile;
+constexpr uint32_t kSegMaxLen = 1u << 16;
+constexpr uint32_t kSegClasses = 17;  // size class ceil(log2(len)) in 0..16
+constexpr uint32_t kSegBadFirst = 1, kSegDecreasing = 2, kSegTooLong = 4;
+
+// Device-side work-queue state of one segmented sort.
+struct SegState {
+    uint32_t cnt[kSegClasses];   // segments per size class
+    uint32_t fill[kSegClasses];  // scatter cursors
+    uint32_t base[kSegClasses];  // queue start of each class (largest class first)
+    uint32_t head;               // next work item
+    uint32_t flag;               // invalid-offset bits of this call
+    uint32_t sticky;             // invalid-offset bits since the last check
+    uint32_t n_big;              // segments of more than 128 keys (one item each)
+    uint32_t n_small;            // segments of 2..128 keys (16 per item)
+    uint32_t n_items;
+};
+
+// Persistent grid size: CUs x resident 1024-lane workgroups with 128 KiB LDS.
+hipError_t seg_sort_grid(int device, uint32_t *grid);
+
+// Enqueues reset, classify, plan, scatter and the persistent sort. cls holds
+// nseg bytes, queue nseg words, pad grid * kSegTile words.
+hipError_t launch_segmented_sort(uint32_t *keys, const uint32_t *off, uint32_t nseg,
+                                 SegState *st, uint8_t *cls, uint32_t *queue, uint32_t *pad,
+                                 uint32_t grid, bool meld_lo, bool meld_hi, hipStream_t stream);
+
 // Largest tile (log2 elements) the tile kernel supports for keys / pairs.
 constexpr uint32_t kMaxLogTileKeys = 14;
 constexpr uint32_t kMaxLogTilePairs = 13;

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cstdarg>
+#include <list>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -18,6 +19,27 @@ struct meld_ctx {
     // Tail workspace backing the virtual padding of non-power-of-two sorts.
     uint32_t *tail = nullptr;
     size_t tail_words = 0;
+    // Segmented sort: queue state, per-segment class and queue, and the
+    // per-workgroup padding scratch of the persistent grid.
+    meld::SegState *seg_state = nullptr;
+    uint8_t *seg_cls = nullptr;
+    uint32_t *seg_queue = nullptr;
+    size_t seg_cap = 0;  // segments the two arrays above hold
+    uint32_t *seg_pad = nullptr;
+    uint32_t seg_grid = 0;
+    // Captured segmented-sort sequences (reset, classify, plan, scatter,
+    // persistent sort), most recently used first, replayed on the caller's
+    // stream. A graph bakes in its arguments, hence the key.
+    struct SegGraph {
+        const void *keys;
+        const void *offsets;
+        size_t nseg;
+        bool lo, hi;
+        hipGraphExec_t exec;
+    };
+    std::list<SegGraph> seg_graphs;
+    hipStream_t capture_stream = nullptr;
+    bool use_graphs = true;
 };
 
 namespace {
@@ -90,6 +112,127 @@ meld_status ensure_tail(meld_ctx *ctx, size_t words) {
 }
 
 bool use_melded(meld_variant v) { return v != MELD_DIVERGENT; }
+
+meld_status dev_alloc(void **p, size_t bytes, const char *what) {
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(MELD_ENOMEM, "cannot allocate %zu bytes of %s", bytes, what);
+    }
+    return MELD_OK;
+}
+
+// Scratch of the segmented sort for up to nseg segments.
+meld_status ensure_seg(meld_ctx *ctx, size_t nseg) {
+    if (ctx->seg_state == nullptr) {
+        hipError_t e = meld::seg_sort_grid(ctx->device, &ctx->seg_grid);
+        if (e != hipSuccess) return hip_fail(e, "segmented sort occupancy query");
+        meld_status st = dev_alloc(reinterpret_cast<void **>(&ctx->seg_state),
+                                   sizeof(meld::SegState), "segmented sort state");
+        if (st != MELD_OK) return st;
+        if (hipMemset(ctx->seg_state, 0, sizeof(meld::SegState)) != hipSuccess)
+            return fail(MELD_EHIP, "hipMemset of segmented sort state failed");
+        st = dev_alloc(reinterpret_cast<void **>(&ctx->seg_pad),
+                       (size_t)ctx->seg_grid * meld::kSegTile * sizeof(uint32_t),
+                       "segmented sort padding");
+        if (st != MELD_OK) return st;
+    }
+    if (nseg > ctx->seg_cap) {
+        if (ctx->seg_cls != nullptr || ctx->seg_queue != nullptr) {
+            hipError_t e = hipDeviceSynchronize();
+            if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+            (void)hipFree(ctx->seg_cls);
+            (void)hipFree(ctx->seg_queue);
+            ctx->seg_cls = nullptr;
+            ctx->seg_queue = nullptr;
+            ctx->seg_cap = 0;
+        }
+        meld_status st = dev_alloc(reinterpret_cast<void **>(&ctx->seg_cls), nseg, "segment classes");
+        if (st != MELD_OK) return st;
+        st = dev_alloc(reinterpret_cast<void **>(&ctx->seg_queue), nseg * sizeof(uint32_t),
+                       "segment queue");
+        if (st != MELD_OK) return st;
+        ctx->seg_cap = nseg;
+    }
+    return MELD_OK;
+}
+
+constexpr size_t kMaxSegGraphs = 8;
+
+void drop_seg_graphs(meld_ctx *ctx) {
+    for (auto &g : ctx->seg_graphs) (void)hipGraphExecDestroy(g.exec);
+    ctx->seg_graphs.clear();
+}
+
+// The graph of (keys, offsets, nseg, forms), captured on first use.
+meld_status seg_graph(meld_ctx *ctx, uint32_t *keys, const uint32_t *offsets, size_t nseg,
+                      bool lo, bool hi, hipGraphExec_t *out) {
+    for (auto it = ctx->seg_graphs.begin(); it != ctx->seg_graphs.end(); ++it) {
+        if (it->keys == keys && it->offsets == offsets && it->nseg == nseg && it->lo == lo &&
+            it->hi == hi) {
+            ctx->seg_graphs.splice(ctx->seg_graphs.begin(), ctx->seg_graphs, it);
+            *out = it->exec;
+            return MELD_OK;
+        }
+    }
+    if (ctx->capture_stream == nullptr) {
+        hipError_t e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
+    }
+    hipError_t e = hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    hipError_t le = meld::launch_segmented_sort(keys, offsets, (uint32_t)nseg, ctx->seg_state,
+                                                ctx->seg_cls, ctx->seg_queue, ctx->seg_pad,
+                                                ctx->seg_grid, lo, hi, ctx->capture_stream);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(ctx->capture_stream, &graph);
+    if (le != hipSuccess || e != hipSuccess) {
+        if (graph != nullptr) (void)hipGraphDestroy(graph);
+        return hip_fail(le != hipSuccess ? le : e, "capturing the segmented sort");
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    if (ctx->seg_graphs.size() >= kMaxSegGraphs) {
+        (void)hipGraphExecDestroy(ctx->seg_graphs.back().exec);
+        ctx->seg_graphs.pop_back();
+    }
+    ctx->seg_graphs.push_front({keys, offsets, nseg, lo, hi, exec});
+    *out = exec;
+    return MELD_OK;
+}
+
+meld_status segmented_impl(meld_ctx *ctx, uint32_t *keys, const uint32_t *offsets, size_t nseg,
+                           bool meld_lo, bool meld_hi, hipStream_t stream, const char *fn) {
+    if (nseg == 0) return MELD_OK;
+    if (nseg >= (1ull << 31)) return fail(MELD_EINVAL, "%s: nseg = %zu >= 2^31", fn, nseg);
+    DeviceGuard g(ctx->device);
+    if (!is_device_ptr(ctx, keys) || !is_device_ptr(ctx, offsets))
+        return fail(MELD_EINVAL, "%s: keys and offsets must be device pointers on device %d", fn,
+                    ctx->device);
+    const size_t cap_before = ctx->seg_cap;
+    meld_status st = ensure_seg(ctx, nseg);
+    if (st != MELD_OK) return st;
+    if (ctx->seg_cap != cap_before) drop_seg_graphs(ctx);  // scratch moved
+    // A caller that is itself capturing gets the launches in its own graph.
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(stream, &cs);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+    if (!ctx->use_graphs || cs != hipStreamCaptureStatusNone) {
+        e = meld::launch_segmented_sort(keys, offsets, (uint32_t)nseg, ctx->seg_state,
+                                        ctx->seg_cls, ctx->seg_queue, ctx->seg_pad, ctx->seg_grid,
+                                        meld_lo, meld_hi, stream);
+        if (e != hipSuccess) return hip_fail(e, "segmented sort launch");
+        return MELD_OK;
+    }
+    hipGraphExec_t exec = nullptr;
+    st = seg_graph(ctx, keys, offsets, nseg, meld_lo, meld_hi, &exec);
+    if (st != MELD_OK) return st;
+    e = hipGraphLaunch(exec, stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return MELD_OK;
+}
 
 // Threads per workgroup for a tile of 2^log_t elements: one comparator per
 // lane per iteration, at most 512 lanes.
@@ -204,10 +347,12 @@ meld_status meld_create(int hip_device, meld_ctx **out) {
 void meld_destroy(meld_ctx *ctx) {
     if (ctx == nullptr) return;
     DeviceGuard g(ctx->device);
-    if (ctx->tail != nullptr) {
-        (void)hipDeviceSynchronize();
-        (void)hipFree(ctx->tail);
-    }
+    (void)hipDeviceSynchronize();
+    drop_seg_graphs(ctx);
+    if (ctx->capture_stream != nullptr) (void)hipStreamDestroy(ctx->capture_stream);
+    for (void *p : {(void *)ctx->tail, (void *)ctx->seg_state, (void *)ctx->seg_cls,
+                    (void *)ctx->seg_queue, (void *)ctx->seg_pad})
+        if (p != nullptr) (void)hipFree(p);
     delete ctx;
 }
 
@@ -278,19 +423,53 @@ meld_status meld_divergent_region_f32(meld_ctx *ctx, const float *x, float *y, s
 
 meld_status meld_segmented_sort_u32(meld_ctx *ctx, uint32_t *keys, const uint32_t *offsets,
                                     size_t nseg, meld_variant variant, void *stream) {
-    (void)keys;
-    (void)offsets;
-    (void)variant;
-    (void)stream;
     if (ctx == nullptr) return fail(MELD_EINVAL, "meld_segmented_sort_u32: ctx is NULL");
-    if (nseg == 0) return MELD_OK;
-    return fail(MELD_EUNSUPPORTED, "meld_segmented_sort_u32: not built yet");
+    if ((unsigned)variant > MELD_MELDED_INPLACE)
+        return fail(MELD_EINVAL, "meld_segmented_sort_u32: bad variant");
+    const bool m = use_melded(variant);
+    return segmented_impl(ctx, keys, offsets, nseg, m, m, static_cast<hipStream_t>(stream),
+                          "meld_segmented_sort_u32");
+}
+
+meld_status meld_segmented_sort_u32_staged(meld_ctx *ctx, uint32_t *keys, const uint32_t *offsets,
+                                           size_t nseg, meld_variant low_phases,
+                                           meld_variant high_phases, void *stream) {
+    if (ctx == nullptr) return fail(MELD_EINVAL, "meld_segmented_sort_u32_staged: ctx is NULL");
+    if ((unsigned)low_phases > MELD_MELDED_INPLACE || (unsigned)high_phases > MELD_MELDED_INPLACE)
+        return fail(MELD_EINVAL, "meld_segmented_sort_u32_staged: bad variant");
+    return segmented_impl(ctx, keys, offsets, nseg, use_melded(low_phases),
+                          use_melded(high_phases), static_cast<hipStream_t>(stream),
+                          "meld_segmented_sort_u32_staged");
+}
+
+meld_status meld_set_option(meld_ctx *ctx, meld_option option, int64_t value) {
+    if (ctx == nullptr) return fail(MELD_EINVAL, "meld_set_option: ctx is NULL");
+    switch (option) {
+        case MELD_OPT_USE_GRAPHS:
+            ctx->use_graphs = value != 0;
+            return MELD_OK;
+        default:
+            return fail(MELD_EINVAL, "meld_set_option: unknown option %d", (int)option);
+    }
 }
 
 meld_status meld_segmented_sort_check(meld_ctx *ctx, void *stream) {
-    (void)stream;
     if (ctx == nullptr) return fail(MELD_EINVAL, "meld_segmented_sort_check: ctx is NULL");
-    return MELD_OK;
+    if (ctx->seg_state == nullptr) return MELD_OK;
+    DeviceGuard g(ctx->device);
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    uint32_t sticky = 0;
+    e = hipMemcpy(&sticky, &ctx->seg_state->sticky, sizeof sticky, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "reading the segmented sort flag");
+    const uint32_t zero = 0;
+    e = hipMemcpy(&ctx->seg_state->sticky, &zero, sizeof zero, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "clearing the segmented sort flag");
+    if (sticky == 0) return MELD_OK;
+    return fail(MELD_EINVAL, "segmented sort: invalid offsets (%s%s%s); keys left untouched",
+                (sticky & meld::kSegBadFirst) ? "offsets[0] != 0 " : "",
+                (sticky & meld::kSegDecreasing) ? "decreasing offsets " : "",
+                (sticky & meld::kSegTooLong) ? "segment longer than 65536" : "");
 }
 
 }  // extern "C"

@@ -1,0 +1,114 @@
+// Bitonic compare-exchange in LDS: the divergent and melded forms of the
+// direction region (Motivating Example, Figure 1; Detailed Design, "Putting
+// All Together") and the loop that runs a range of network steps on a tile.
+#pragma once
+
+#include "device_common.h"
+
+namespace meld {
+
+// Waits for this wave's LDS operations and keeps the compiler from moving
+// memory operations across the point.
+__device__ __forceinline__ void wave_lds_sync() {
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
+
+// Figure 1's region as written: each side holds its own loads, compare and
+// conditional swap.
+template <typename E>
+__device__ __forceinline__ void cex_divergent(E *s, uint32_t lo, uint32_t hi, bool up) {
+    // The marks keep each side's loads and stores inside that side: without
+    // them the compiler sinks the two identical swap-store blocks into one,
+    // which would already be a (partial) meld.
+    if (up) {
+        MELD_SIDE_MARK("ascending");
+        const E a = s[lo];
+        const E b = s[hi];
+        if (b < a) {
+            s[lo] = b;
+            s[hi] = a;
+            MELD_SIDE_MARK("ascending swap");
+        }
+    } else {
+        MELD_SIDE_MARK("descending");
+        const E a = s[lo];
+        const E b = s[hi];
+        if (b > a) {
+            s[lo] = b;
+            s[hi] = a;
+            MELD_SIDE_MARK("descending swap");
+        }
+    }
+}
+
+// The melded region: one load pair, both compares, a select of the swap
+// condition, one conditional store pair.
+template <typename E>
+__device__ __forceinline__ void cex_melded(E *s, uint32_t lo, uint32_t hi, bool up) {
+    const E a = s[lo];
+    const E b = s[hi];
+    const bool lt = b < a;
+    const bool gt = b > a;
+    const bool swap = (up & lt) | (!up & gt);  // select(up, lt, gt) on lane masks
+    if (swap) {
+        s[lo] = b;
+        s[hi] = a;
+    }
+}
+
+// One network step (k = 2^m, j) on the tile: each lane takes comparators
+// c = lane0, lane0 + NT, ... below T/2; lo is c with a zero inserted at bit j.
+// The direction is bit m of the element's index base | lo.
+template <typename E, bool MELDED, int NT>
+__device__ __forceinline__ void lds_step(E *s, uint32_t half, uint32_t base, uint32_t m,
+                                         uint32_t j, uint32_t lane0) {
+    for (uint32_t c = lane0; c < half; c += NT) {
+        const uint32_t lo = ((c & ~(j - 1)) << 1) | (c & (j - 1));
+        const uint32_t hi = lo + j;
+        const bool up = (((base | lo) >> m) & 1u) == 0;
+        if constexpr (MELDED)
+            cex_melded(s, lo, hi, up);
+        else
+            cex_divergent(s, lo, hi, up);
+    }
+}
+
+// Runs the steps of phases m_begin..m_end (phase m_begin from j = 2^j_first,
+// the others from j = k/2) on the T-element LDS tile s, at most step_limit
+// steps (negative: all). Returns the number of steps run.
+//
+// MELD_LO selects the form for phases k <= 64, whose direction bit is one of
+// the six lane bits of the comparator index (divergent inside a wave);
+// MELD_HI for phases k >= 128, whose direction is uniform per wave.
+//
+// Steps with j >= 128 exchange data between waves: a workgroup barrier
+// follows them (BLOCK) — callers with T <= 128 that run one wave per tile
+// pass BLOCK = false. For j <= 64, the comparators one wave takes in one
+// iteration touch only the 128-element block [2*c0, 2*c0 + 128), the same in
+// every such step, so only the wave's own LDS operations need to complete.
+template <typename E, bool MELD_LO, bool MELD_HI, int NT, bool BLOCK>
+__device__ __forceinline__ int32_t lds_network(E *s, uint32_t T, uint32_t base, uint32_t m_begin,
+                                               uint32_t m_end, uint32_t j_first,
+                                               int32_t step_limit, uint32_t lane0) {
+    const uint32_t half = T >> 1;
+    int32_t steps = 0;
+    for (uint32_t m = m_begin; m <= m_end; ++m) {
+        const uint32_t k = 1u << m;
+        for (uint32_t j = (m == m_begin) ? (1u << j_first) : (k >> 1); j > 0; j >>= 1) {
+            if (steps == step_limit) return steps;
+            ++steps;
+            if (k <= 64)
+                lds_step<E, MELD_LO, NT>(s, half, base, m, j, lane0);
+            else
+                lds_step<E, MELD_HI, NT>(s, half, base, m, j, lane0);
+            const bool next_crosses_waves = (j >= 128) || (j == 1 && k >= 128);
+            if (BLOCK && next_crosses_waves)
+                __syncthreads();
+            else
+                wave_lds_sync();
+        }
+    }
+    return steps;
+}
+
+}  // namespace meld

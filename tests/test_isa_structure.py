@@ -1,0 +1,106 @@
+"""Structure of the gfx950 code the compiler emits for our own kernels.
+
+Compiles the library's HIP sources to AMDGPU assembly (this repository's code
+only) and checks that the two forms differ where they should:
+  * the divergent bitonic compare-exchange keeps a load pair, a compare and a
+    store pair inside each side of the direction branch (Figure 1 as written),
+  * the melded one has a single load pair / store pair and no side blocks,
+  * the divergent region runs one gather loop per side, the melded region
+    keeps each side's gathers in its own block and the fma chain outside, and
+    the in-place melded region has no side blocks at all.
+"""
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2107_05681_amd", "csrc")
+HIPCC = "/opt/rocm/bin/hipcc"
+
+pytestmark = pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not available")
+
+
+def _asm(src, tmp_path):
+    out = tmp_path / (os.path.basename(src) + ".s")
+    subprocess.check_call(
+        [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}", "--offload-device-only", "-S",
+         os.path.join(CSRC, src), "-o", str(out)], stderr=subprocess.DEVNULL)
+    return out.read_text()
+
+
+def _kernel(asm, pattern):
+    names = re.findall(r"^(_Z\S*):", asm, flags=re.M)
+    match = [n for n in names if re.search(pattern, n)]
+    assert match, f"no kernel matches {pattern}"
+    start = asm.index(match[0] + ":")
+    end = asm.index("s_endpgm", start)
+    return asm[start:end]
+
+
+def _blocks_after(body, marker):
+    """Instruction text from each occurrence of an asm marker to the next marker."""
+    parts = re.split(r";;#ASMSTART\s*\n\s*; side ", body)
+    return [p for p in parts[1:] if p.startswith(marker)]
+
+
+@pytest.fixture(scope="module")
+def bitonic_asm(tmp_path_factory):
+    return _asm("bitonic.hip", tmp_path_factory.mktemp("isa"))
+
+
+@pytest.fixture(scope="module")
+def region_asm(tmp_path_factory):
+    return _asm("region.hip", tmp_path_factory.mktemp("isa"))
+
+
+@pytest.mark.parametrize("pairs", [False, True])
+def test_bitonic_divergent_sides_hold_lds_ops(bitonic_asm, pairs):
+    p = "b1" if pairs else "b0"
+    body = _kernel(bitonic_asm, rf"bitonic_tile_kernelIL{p}ELb0ELi512ELi1E")
+    width = "b64" if pairs else "b32"
+    for side in ("ascending\n", "descending\n"):
+        blocks = _blocks_after(body, side)
+        assert blocks, side
+        text = blocks[0]
+        assert text.count(f"ds_read_{width}") == 2, side
+        assert text.count(f"ds_write_{width}") == 2, side
+        assert re.search(r"v_cmp_[lg]t_u(32|64)", text), side
+    assert "s_and_saveexec_b64" in body
+
+
+@pytest.mark.parametrize("pairs", [False, True])
+def test_bitonic_melded_has_one_load_store_pair(bitonic_asm, pairs):
+    p = "b1" if pairs else "b0"
+    body = _kernel(bitonic_asm, rf"bitonic_tile_kernelIL{p}ELb1ELi512ELi1E")
+    width = "b64" if pairs else "b32"
+    assert "; side" not in body
+    # the comparator loop: one load pair and one (conditional) store pair
+    loop = body[body.index(f"ds_read_{width}", body.index("s_barrier")):]
+    assert loop.count(f"ds_write_{width}") >= 2
+    cmp_lt = len(re.findall(r"v_cmp_lt_u(32|64)", body))
+    cmp_gt = len(re.findall(r"v_cmp_gt_u(32|64)", body))
+    assert cmp_lt >= 1 and cmp_gt >= 1  # both unaligned compares run
+
+
+def test_region_divergent_has_a_loop_per_side(region_asm):
+    body = _kernel(region_asm, r"region_divergent_kernel")
+    for side in ("true\n", "false\n"):
+        blocks = _blocks_after(body, side)
+        assert blocks and "global_load_dword" in blocks[0] and "v_fma" in blocks[0], side
+
+
+def test_region_melded_gathers_per_side_fma_once(region_asm):
+    body = _kernel(region_asm, r"region_melded_kernel")
+    assert _blocks_after(body, "gathers true") and _blocks_after(body, "gathers false")
+    assert "v_cndmask_b32" in body  # the selected multiplier
+
+
+def test_region_melded_inplace_has_no_side_blocks(region_asm):
+    body = _kernel(region_asm, r"region_melded_inplace_kernel")
+    assert "; side" not in body
+    assert "v_cndmask_b32" in body and "global_load_dword" in body
