@@ -189,6 +189,61 @@ meld_status meld_divergent_region_f32(meld_ctx *ctx, const float *x, float *y, s
                                       uint64_t thr, meld_side side_true, meld_side side_false,
                                       meld_variant variant, void *stream);
 
+/* ---- Divergence probes (synchronous: they wait for `stream`) -----------
+ * Only waves whose lanes take both outcomes of a branch pay the IPDOM
+ * serialisation (Background section, "GPGPU Architecture"). The probes
+ * evaluate the exact predicate a kernel branches on, under that kernel's
+ * lane mapping, with one ballot per 64-lane wave, and return host counts. */
+
+/* Region branch over lanes [0, n): out[0] = waves whose mask is mixed,
+ * out[1] = lanes taking the true side, out[2] = waves (64 consecutive lanes,
+ * the last one ragged). Errors: MELD_EINVAL for NULL ctx/out, n >= 2^32 or
+ * thr > 2^32. */
+meld_status meld_probe_region(meld_ctx *ctx, size_t n, uint64_t seed, uint64_t thr,
+                              uint64_t out[3], void *stream);
+
+/* Sort network on one LDS tile of 2^log_t elements, comparators dealt to
+ * lanes in waves of 64 consecutive indices: out[2(m-1)] = mixed
+ * comparator-waves of phase k = 2^m summed over its steps, out[2(m-1)+1] =
+ * all comparator-waves of that phase, m = 1..log_t (out holds 2*log_t
+ * words). Errors: MELD_EINVAL for NULL ctx/out or log_t outside 1..16. */
+meld_status meld_probe_network(meld_ctx *ctx, uint32_t log_t, uint64_t *out, void *stream);
+
+/* Segmented sort on device offsets[nseg+1]: out[0] / out[1] = comparator-
+ * steps in mixed waves / all comparator-steps of the phases k <= 64, out[2] /
+ * out[3] the same for k >= 128, under the segmented kernel's mapping.
+ * Invalid segments are skipped. */
+meld_status meld_probe_segments(meld_ctx *ctx, const uint32_t *offsets, size_t nseg,
+                                uint64_t out[4], void *stream);
+
+/* ---- Autotuner -------------------------------------------------------------
+ * MELD_AUTO resolves per shape class (sort: log2 n and pairs; segmented:
+ * log2 nseg and log2 of the key count; region: log2 n, log2 tab_len, the
+ * trip counts and p in tenths). The first call of a class times the
+ * candidates on the caller's stream — sorts on a scratch copy of the input
+ * (tile size x divergent/melded per stage), the region on the caller's own
+ * arrays (its three forms) — runs the matching divergence probe, and keeps
+ * the decision (see meld_tune_choose). Later calls reuse it. A stream that is
+ * being captured gets the untuned default (melded) without timing. */
+
+/* Loads decisions from the JSON file cache_path (if it exists and was
+ * written on the same GPU architecture and HIP runtime) and saves every new
+ * decision there. The environment variable MELD_TUNE_CACHE does the same at
+ * meld_create. Errors: MELD_EINVAL for a malformed file. */
+meld_status meld_tune(meld_ctx *ctx, const char *cache_path);
+
+/* Writes the context's decisions as JSON into buf (NUL-terminated).
+ * Errors: MELD_EINVAL when len is too small (the message gives the size). */
+meld_status meld_plan_describe(meld_ctx *ctx, char *buf, size_t len);
+
+/* The tuner's decision rule over n timed candidates: the fastest, unless
+ * others are within `tie` (relative) of it; among those the candidate whose
+ * per-stage forms agree most with the probe wins (melded for a stage whose
+ * mixed-wave fraction is at least theta, divergent otherwise). Returns the
+ * index, or -1 for n <= 0 or NULL arrays. Pure host function. */
+int meld_tune_choose(int n, const double *ms, const int *melded_lo, const int *melded_hi,
+                     double mixed_lo, double mixed_hi, double theta, double tie);
+
 #ifdef __cplusplus
 }
 #endif

@@ -30,7 +30,9 @@ _STATUS = {1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "EUNSUPPORTED"}
 # Every function the C header declares.
 EXPORTS = ("meld_version", "meld_create", "meld_destroy", "meld_last_error", "meld_sort_u32",
            "meld_sort_u32_steps", "meld_segmented_sort_u32", "meld_segmented_sort_u32_staged",
-           "meld_segmented_sort_check", "meld_set_option",
+           "meld_segmented_sort_check", "meld_set_option", "meld_probe_region",
+           "meld_probe_network", "meld_probe_segments", "meld_tune", "meld_plan_describe",
+           "meld_tune_choose",
            "meld_divergent_region_f32")
 
 
@@ -79,6 +81,20 @@ def load_library():
     lib.meld_segmented_sort_u32_staged.argtypes = [vp, vp, vp, sz, st, st, vp]
     lib.meld_segmented_sort_check.restype = st
     lib.meld_segmented_sort_check.argtypes = [vp, vp]
+    lib.meld_probe_region.restype = st
+    lib.meld_probe_region.argtypes = [vp, sz, u64, u64, ctypes.POINTER(u64), vp]
+    lib.meld_probe_network.restype = st
+    lib.meld_probe_network.argtypes = [vp, ctypes.c_uint32, ctypes.POINTER(u64), vp]
+    lib.meld_probe_segments.restype = st
+    lib.meld_probe_segments.argtypes = [vp, vp, sz, ctypes.POINTER(u64), vp]
+    lib.meld_tune.restype = st
+    lib.meld_tune.argtypes = [vp, ctypes.c_char_p]
+    lib.meld_plan_describe.restype = st
+    lib.meld_plan_describe.argtypes = [vp, ctypes.c_char_p, sz]
+    dp, ip = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+    lib.meld_tune_choose.restype = ctypes.c_int
+    lib.meld_tune_choose.argtypes = [ctypes.c_int, dp, ip, ip, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_double]
     lib.meld_set_option.restype = st
     lib.meld_set_option.argtypes = [vp, st, i64]
     lib.meld_divergent_region_f32.restype = st
@@ -221,3 +237,60 @@ def divergent_region(x, tab, seed: int, thr: int, side_true, side_false, variant
         x.numel(), ctypes.c_void_p(tab.data_ptr()), tab.numel(), int(seed), int(thr),
         _as_side(side_true), _as_side(side_false), _variant(variant), _stream_of(x, stream)))
     return out
+
+
+def _cur_stream(device: int):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def probe_region(n: int, seed: int, thr: int, device: int = 0):
+    """(mixed waves, true lanes, waves) of the region branch over lanes [0, n)."""
+    out = (ctypes.c_uint64 * 3)()
+    _check(load_library().meld_probe_region(context(device), n, seed, thr, out,
+                                            _cur_stream(device)))
+    return tuple(int(v) for v in out)
+
+
+def probe_network(log_t: int, device: int = 0):
+    """[(mixed comparator-waves, comparator-waves) for phases k = 2 .. 2^log_t]."""
+    out = (ctypes.c_uint64 * (2 * log_t))()
+    _check(load_library().meld_probe_network(context(device), log_t, out, _cur_stream(device)))
+    return [(int(out[2 * i]), int(out[2 * i + 1])) for i in range(log_t)]
+
+
+def probe_segments(offsets):
+    """(mixed, all) comparator-steps of the phases k <= 64 and of k >= 128."""
+    _u32_tensor(offsets, "offsets")
+    out = (ctypes.c_uint64 * 4)()
+    dev = offsets.device.index
+    _check(load_library().meld_probe_segments(context(dev), ctypes.c_void_p(offsets.data_ptr()),
+                                              max(offsets.numel() - 1, 0), out, _cur_stream(dev)))
+    return (int(out[0]), int(out[1])), (int(out[2]), int(out[3]))
+
+
+def tune(cache_path: str, device: int = 0) -> None:
+    """Attaches a JSON tuning cache (loads it if present, saves new decisions)."""
+    _check(load_library().meld_tune(context(device), cache_path.encode()))
+
+
+def plan_describe(device: int = 0) -> str:
+    """The context's tuning decisions as JSON text."""
+    lib = load_library()
+    size = 1 << 16
+    while True:
+        buf = ctypes.create_string_buffer(size)
+        st = lib.meld_plan_describe(context(device), buf, size)
+        if st == OK:
+            return buf.value.decode()
+        if size >= 1 << 26:
+            _check(st)
+        size *= 4
+
+
+def tune_choose(ms, melded_lo, melded_hi, mixed_lo, mixed_hi, theta=0.5, tie=0.02) -> int:
+    """The tuner's decision rule (pure host function)."""
+    n = len(ms)
+    return int(load_library().meld_tune_choose(
+        n, (ctypes.c_double * n)(*ms), (ctypes.c_int * n)(*melded_lo),
+        (ctypes.c_int * n)(*melded_hi), mixed_lo, mixed_hi, theta, tie))

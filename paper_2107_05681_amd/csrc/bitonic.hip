@@ -158,7 +158,7 @@ __device__ __forceinline__ void tile_store(const SortArray &a,
     }
 }
 
-template <bool PAIRS, bool MELDED, int NT, int MODE>
+template <bool PAIRS, bool MELD_LO, bool MELD_HI, int NT, int MODE>
 __global__ __launch_bounds__(NT) void bitonic_tile_kernel(SortArray a, uint32_t log_t,
                                                           uint32_t m_begin, uint32_t m_end,
                                                           uint32_t j_first, int32_t step_limit) {
@@ -174,8 +174,8 @@ __global__ __launch_bounds__(NT) void bitonic_tile_kernel(SortArray a, uint32_t 
     else
         tile_load<PAIRS, MODE, NT>(a, s, base, T);
     __syncthreads();
-    lds_network<E, MELDED, MELDED, NT, true>(s, T, base, m_begin, m_end, j_first, step_limit,
-                                            threadIdx.x);
+    lds_network<E, MELD_LO, MELD_HI, NT, true>(s, T, base, m_begin, m_end, j_first, step_limit,
+                                              threadIdx.x);
     __syncthreads();
     if (below_n)
         tile_store<PAIRS, kPlain, NT>(a, s, base, T);
@@ -226,13 +226,13 @@ __global__ void fill_u32_kernel(uint32_t *p, uint32_t value, size_t count) {
     if (i < count) p[i] = value;
 }
 
-template <bool PAIRS, bool MELDED, int NT, int MODE>
+template <bool PAIRS, bool LO, bool HI, int NT, int MODE>
 hipError_t launch_tile_m(const SortArray &a, uint32_t log_t, uint32_t n_tiles, uint32_t m_begin,
                          uint32_t m_end, uint32_t j_first, int32_t step_limit,
                          hipStream_t stream) {
     using E = typename ElemOf<PAIRS>::type;
     const size_t lds = ((size_t)1 << log_t) * sizeof(E);
-    auto kern = bitonic_tile_kernel<PAIRS, MELDED, NT, MODE>;
+    auto kern = bitonic_tile_kernel<PAIRS, LO, HI, NT, MODE>;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -243,45 +243,58 @@ hipError_t launch_tile_m(const SortArray &a, uint32_t log_t, uint32_t n_tiles, u
     return hipGetLastError();
 }
 
-template <bool PAIRS, bool MELDED, int NT>
+template <bool PAIRS, bool LO, bool HI, int NT>
 hipError_t launch_tile_t(const SortArray &a, uint32_t log_t, uint32_t n_tiles, uint32_t m_begin,
                          uint32_t m_end, uint32_t j_first, int32_t step_limit, int io_mode,
                          hipStream_t stream) {
+#define MELD_TILE_MODE(M)                                                                    \
+    case M:                                                                                  \
+        return launch_tile_m<PAIRS, LO, HI, NT, M>(a, log_t, n_tiles, m_begin, m_end, j_first, \
+                                                   step_limit, stream);
     switch (io_mode) {
-        case kPlain:
-            return launch_tile_m<PAIRS, MELDED, NT, kPlain>(a, log_t, n_tiles, m_begin, m_end,
-                                                            j_first, step_limit, stream);
-        case kPlainVec:
-            return launch_tile_m<PAIRS, MELDED, NT, kPlainVec>(a, log_t, n_tiles, m_begin, m_end,
-                                                               j_first, step_limit, stream);
-        case kTail:
-            return launch_tile_m<PAIRS, MELDED, NT, kTail>(a, log_t, n_tiles, m_begin, m_end,
-                                                           j_first, step_limit, stream);
-        case kSentinel:
-            return launch_tile_m<PAIRS, MELDED, NT, kSentinel>(a, log_t, n_tiles, m_begin, m_end,
-                                                               j_first, step_limit, stream);
+        MELD_TILE_MODE(kPlain)
+        MELD_TILE_MODE(kPlainVec)
+        MELD_TILE_MODE(kTail)
+        MELD_TILE_MODE(kSentinel)
         default:
             return hipErrorInvalidValue;
     }
+#undef MELD_TILE_MODE
 }
 
-template <bool PAIRS, bool MELDED>
+template <bool PAIRS, bool LO, bool HI>
 hipError_t launch_tile_nt(const SortArray &a, uint32_t log_t, uint32_t n_tiles, uint32_t m_begin,
                           uint32_t m_end, uint32_t j_first, int32_t step_limit, int io_mode,
                           int threads, hipStream_t stream) {
     switch (threads) {
         case 64:
-            return launch_tile_t<PAIRS, MELDED, 64>(a, log_t, n_tiles, m_begin, m_end, j_first,
+            return launch_tile_t<PAIRS, LO, HI, 64>(a, log_t, n_tiles, m_begin, m_end, j_first,
                                                     step_limit, io_mode, stream);
         case 256:
-            return launch_tile_t<PAIRS, MELDED, 256>(a, log_t, n_tiles, m_begin, m_end, j_first,
+            return launch_tile_t<PAIRS, LO, HI, 256>(a, log_t, n_tiles, m_begin, m_end, j_first,
                                                      step_limit, io_mode, stream);
         case 512:
-            return launch_tile_t<PAIRS, MELDED, 512>(a, log_t, n_tiles, m_begin, m_end, j_first,
+            return launch_tile_t<PAIRS, LO, HI, 512>(a, log_t, n_tiles, m_begin, m_end, j_first,
                                                      step_limit, io_mode, stream);
         default:
             return hipErrorInvalidValue;
     }
+}
+
+template <bool PAIRS>
+hipError_t launch_tile_p(const SortArray &a, uint32_t log_t, uint32_t n_tiles, uint32_t m_begin,
+                         uint32_t m_end, uint32_t j_first, int32_t step_limit, bool lo, bool hi,
+                         int io_mode, int threads, hipStream_t stream) {
+    if (lo)
+        return hi ? launch_tile_nt<PAIRS, true, true>(a, log_t, n_tiles, m_begin, m_end, j_first,
+                                                      step_limit, io_mode, threads, stream)
+                  : launch_tile_nt<PAIRS, true, false>(a, log_t, n_tiles, m_begin, m_end,
+                                                       j_first, step_limit, io_mode, threads,
+                                                       stream);
+    return hi ? launch_tile_nt<PAIRS, false, true>(a, log_t, n_tiles, m_begin, m_end, j_first,
+                                                   step_limit, io_mode, threads, stream)
+              : launch_tile_nt<PAIRS, false, false>(a, log_t, n_tiles, m_begin, m_end, j_first,
+                                                    step_limit, io_mode, threads, stream);
 }
 
 template <bool PAIRS, int R, int MODE>
@@ -313,20 +326,15 @@ hipError_t launch_global_p(const SortArray &a, uint32_t log_n, uint32_t m, uint3
 
 hipError_t launch_bitonic_tile(const SortArray &a, uint32_t log_t, uint32_t n_tiles,
                                uint32_t m_begin, uint32_t m_end, uint32_t j_first,
-                               int32_t step_limit, bool melded, int io_mode, int threads,
-                               hipStream_t stream) {
+                               int32_t step_limit, bool meld_lo, bool meld_hi, int io_mode,
+                               int threads, hipStream_t stream) {
     if (n_tiles == 0 || step_limit == 0) return hipSuccess;
     if (io_mode == kPlainVec && log_t < 2) io_mode = kPlain;
-    const bool pairs = a.vals != nullptr;
-    if (pairs)
-        return melded ? launch_tile_nt<true, true>(a, log_t, n_tiles, m_begin, m_end, j_first,
-                                                   step_limit, io_mode, threads, stream)
-                      : launch_tile_nt<true, false>(a, log_t, n_tiles, m_begin, m_end, j_first,
-                                                    step_limit, io_mode, threads, stream);
-    return melded ? launch_tile_nt<false, true>(a, log_t, n_tiles, m_begin, m_end, j_first,
-                                                step_limit, io_mode, threads, stream)
-                  : launch_tile_nt<false, false>(a, log_t, n_tiles, m_begin, m_end, j_first,
-                                                 step_limit, io_mode, threads, stream);
+    if (a.vals != nullptr)
+        return launch_tile_p<true>(a, log_t, n_tiles, m_begin, m_end, j_first, step_limit, meld_lo,
+                                   meld_hi, io_mode, threads, stream);
+    return launch_tile_p<false>(a, log_t, n_tiles, m_begin, m_end, j_first, step_limit, meld_lo,
+                                meld_hi, io_mode, threads, stream);
 }
 
 hipError_t launch_bitonic_global(const SortArray &a, uint32_t log_n, uint32_t m, uint32_t b_hi,

@@ -38,10 +38,12 @@ struct SortArray {
 // io_mode: 0 plain, 1 plain with 16-byte aligned arrays (vector I/O),
 // 2 tail workspace, 3 sentinel padding of a single tile.
 constexpr int kIoPlain = 0, kIoPlainVec = 1, kIoTail = 2, kIoSentinel = 3;
+// meld_lo / meld_hi: melded (true) or divergent compare-exchange for the
+// phases k <= 64 / k >= 128.
 hipError_t launch_bitonic_tile(const SortArray &a, uint32_t log_t, uint32_t n_tiles,
                                uint32_t m_begin, uint32_t m_end, uint32_t j_first,
-                               int32_t step_limit, bool melded, int io_mode, int threads,
-                               hipStream_t stream);
+                               int32_t step_limit, bool meld_lo, bool meld_hi, int io_mode,
+                               int threads, hipStream_t stream);
 
 // One streaming pass over all N = 2^log_n elements for the steps
 // j = 2^b_hi .. 2^b_lo of phase k = 2^m (b_hi - b_lo + 1 <= kMaxFusedSteps),
@@ -51,6 +53,18 @@ hipError_t launch_bitonic_global(const SortArray &a, uint32_t log_n, uint32_t m,
                                  uint32_t b_lo, int32_t step_limit, hipStream_t stream);
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t count, hipStream_t stream);
+
+// Divergence probes (probe.hip). Counters are accumulated into out.
+// Region: out[0] mixed waves, out[1] true lanes, out[2] waves.
+hipError_t launch_probe_region(uint32_t n, uint64_t seed, uint64_t thr, unsigned long long *out,
+                               hipStream_t stream);
+// One tile of 2^log_t: out[2(m-1)] mixed comparator-waves of phase 2^m,
+// out[2(m-1)+1] comparator-waves of that phase (over all its steps).
+hipError_t launch_probe_network(uint32_t log_t, unsigned long long *out, hipStream_t stream);
+// Segments: out[0..1] mixed / all comparator-steps of the phases k <= 64,
+// out[2..3] the same for k >= 128.
+hipError_t launch_probe_segments(const uint32_t *off, uint32_t nseg, unsigned long long *out,
+                                 hipStream_t stream);
 
 // Segmented sort (segsort.hip).
 constexpr uint32_t kSegThreads = 1024;

@@ -4,13 +4,16 @@
 
 #include <algorithm>
 #include <cstdarg>
-#include <list>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <list>
 #include <string>
+#include <vector>
 
 #include "../../include/meld.h"
 #include "kernels.h"
+#include "tune.h"
 
 using meld::SortArray;
 
@@ -40,7 +43,19 @@ struct meld_ctx {
     std::list<SegGraph> seg_graphs;
     hipStream_t capture_stream = nullptr;
     bool use_graphs = true;
+    // Tuner: decisions per shape class, scratch for timed trials on copies of
+    // the caller's data, and device counters for the divergence probes.
+    meld::Tuner tuner;
+    uint32_t *tune_buf = nullptr;
+    size_t tune_words = 0;
+    unsigned long long *probe_buf = nullptr;  // kProbeWords counters
+    double theta = 0.5;  // mixed-wave fraction from which the probe favours melding
+    double tie = 0.02;   // trials within 2 % count as ties
 };
+
+namespace {
+constexpr size_t kProbeWords = 64;
+}
 
 namespace {
 
@@ -120,6 +135,91 @@ meld_status dev_alloc(void **p, size_t bytes, const char *what) {
         return fail(MELD_ENOMEM, "cannot allocate %zu bytes of %s", bytes, what);
     }
     return MELD_OK;
+}
+
+meld_status ensure_words(uint32_t **buf, size_t *have, size_t words, const char *what) {
+    if (words <= *have) return MELD_OK;
+    if (*buf != nullptr) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+        (void)hipFree(*buf);
+        *buf = nullptr;
+        *have = 0;
+    }
+    meld_status st = dev_alloc(reinterpret_cast<void **>(buf), words * sizeof(uint32_t), what);
+    if (st == MELD_OK) *have = words;
+    return st;
+}
+
+meld_status ensure_probe(meld_ctx *ctx) {
+    if (ctx->probe_buf != nullptr) return MELD_OK;
+    return dev_alloc(reinterpret_cast<void **>(&ctx->probe_buf),
+                     kProbeWords * sizeof(unsigned long long), "probe counters");
+}
+
+// Runs a probe launcher on zeroed counters and copies `count` of them back.
+template <class Launch>
+meld_status run_probe(meld_ctx *ctx, hipStream_t s, size_t count, unsigned long long *host,
+                      Launch launch) {
+    meld_status st = ensure_probe(ctx);
+    if (st != MELD_OK) return st;
+    hipError_t e = meld::launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->probe_buf), 0u,
+                                         kProbeWords * 2, s);
+    if (e == hipSuccess) e = launch(ctx->probe_buf);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(host, ctx->probe_buf, count * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "divergence probe");
+    return MELD_OK;
+}
+
+// Median milliseconds of `reps` runs of run() on stream s, each preceded by
+// an untimed prep().
+template <class Prep, class Run>
+meld_status time_median(hipStream_t s, int reps, Prep prep, Run run, double *ms_out) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        if (a) (void)hipEventDestroy(a);
+        return fail(MELD_EHIP, "hipEventCreate failed");
+    }
+    std::vector<float> t;
+    meld_status st = MELD_OK;
+    for (int r = 0; r < reps && st == MELD_OK; ++r) {
+        st = prep();
+        if (st != MELD_OK) break;
+        (void)hipEventRecord(a, s);
+        st = run();
+        (void)hipEventRecord(b, s);
+        if (st != MELD_OK) break;
+        if (hipEventSynchronize(b) != hipSuccess) {
+            st = fail(MELD_EHIP, "hipEventSynchronize failed");
+            break;
+        }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, a, b);
+        t.push_back(ms);
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (st != MELD_OK) return st;
+    std::sort(t.begin(), t.end());
+    *ms_out = t.empty() ? 0.0 : t[t.size() / 2];
+    return MELD_OK;
+}
+
+bool capturing(hipStream_t s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
+std::string fmt(const char *f, ...) {
+    char buf[256];
+    va_list ap;
+    va_start(ap, f);
+    vsnprintf(buf, sizeof buf, f, ap);
+    va_end(ap);
+    return buf;
 }
 
 // Scratch of the segmented sort for up to nseg segments.
@@ -244,14 +344,20 @@ int tile_threads(uint32_t log_t) {
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
 
+// How a single-array sort runs: the tile size and the form per stage.
+struct SortPlan {
+    uint32_t log_t;
+    bool lo, hi;
+};
+
+uint32_t max_log_tile(bool pairs) { return pairs ? meld::kMaxLogTilePairs : meld::kMaxLogTileKeys; }
+
 // Enqueues the whole network (or its first step_limit steps) on keys[0..n).
 meld_status sort_impl(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n,
-                      meld_variant variant, int64_t step_limit, hipStream_t stream) {
+                      const SortPlan &plan, int64_t step_limit, hipStream_t stream) {
     const bool pairs = payload != nullptr;
     const uint32_t log_n = log2_ceil(n);
     const size_t big_n = (size_t)1 << log_n;
-    const uint32_t max_log_t = pairs ? meld::kMaxLogTilePairs : meld::kMaxLogTileKeys;
-    const bool melded = use_melded(variant);
 
     SortArray a{keys, payload, nullptr, nullptr, (uint32_t)n};
     int64_t left = step_limit;  // < 0: unlimited
@@ -263,15 +369,15 @@ meld_status sort_impl(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n
     };
 
     hipError_t e;
-    if (log_n <= max_log_t) {
+    if (log_n <= plan.log_t) {
         // One tile holds everything; positions >= n are sentinels in LDS.
         const uint32_t log_t = std::max<uint32_t>(log_n, 1);
         const int io = big_n > n ? meld::kIoSentinel
                        : (aligned16(keys) && (!pairs || aligned16(payload))) ? meld::kIoPlainVec
                                                                              : meld::kIoPlain;
         e = meld::launch_bitonic_tile(a, log_t, 1, 1, log_t, 0,
-                                      take((uint64_t)log_t * (log_t + 1) / 2), melded, io,
-                                      tile_threads(log_t), stream);
+                                      take((uint64_t)log_t * (log_t + 1) / 2), plan.lo, plan.hi,
+                                      io, tile_threads(log_t), stream);
         if (e != hipSuccess) return hip_fail(e, "bitonic tile launch");
         return MELD_OK;
     }
@@ -286,15 +392,15 @@ meld_status sort_impl(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n
         if (e != hipSuccess) return hip_fail(e, "fill launch");
     }
 
-    const uint32_t log_t = max_log_t;
+    const uint32_t log_t = plan.log_t;
     const uint32_t n_tiles = (uint32_t)(big_n >> log_t);
     const int threads = tile_threads(log_t);
     const int io = a.tk != nullptr ? meld::kIoTail
                    : (aligned16(keys) && (!pairs || aligned16(payload))) ? meld::kIoPlainVec
                                                                          : meld::kIoPlain;
     e = meld::launch_bitonic_tile(a, log_t, n_tiles, 1, log_t, 0,
-                                  take((uint64_t)log_t * (log_t + 1) / 2), melded, io, threads,
-                                  stream);
+                                  take((uint64_t)log_t * (log_t + 1) / 2), plan.lo, plan.hi, io,
+                                  threads, stream);
     if (e != hipSuccess) return hip_fail(e, "bitonic tile launch");
 
     for (uint32_t m = log_t + 1; m <= log_n; ++m) {
@@ -312,10 +418,234 @@ meld_status sort_impl(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n
             b_hi = b_lo - 1;
         }
         // Steps j = 2^(log_t-1) .. 1 of phase m in LDS tiles.
-        e = meld::launch_bitonic_tile(a, log_t, n_tiles, m, m, log_t - 1, take(log_t), melded,
-                                      io, threads, stream);
+        e = meld::launch_bitonic_tile(a, log_t, n_tiles, m, m, log_t - 1, take(log_t), plan.lo,
+                                      plan.hi, io, threads, stream);
         if (e != hipSuccess) return hip_fail(e, "bitonic merge launch");
     }
+    return MELD_OK;
+}
+
+SortPlan fixed_plan(bool pairs, meld_variant v) {
+    const bool m = use_melded(v);
+    return SortPlan{max_log_tile(pairs), m, m};
+}
+
+// Probe of one tile's network: mixed-wave fraction of the phases k <= 64 and
+// k >= 128.
+meld_status probe_network(meld_ctx *ctx, uint32_t log_t, hipStream_t s, double *mixed_lo,
+                          double *mixed_hi) {
+    unsigned long long c[2 * 16] = {0};
+    meld_status st = run_probe(ctx, s, 2 * log_t, c, [&](unsigned long long *out) {
+        return meld::launch_probe_network(log_t, out, s);
+    });
+    if (st != MELD_OK) return st;
+    unsigned long long ml = 0, al = 0, mh = 0, ah = 0;
+    for (uint32_t m = 1; m <= log_t; ++m) {
+        (m <= 6 ? ml : mh) += c[2 * (m - 1)];
+        (m <= 6 ? al : ah) += c[2 * (m - 1) + 1];
+    }
+    *mixed_lo = al ? (double)ml / (double)al : 0.0;
+    *mixed_hi = ah ? (double)mh / (double)ah : 0.0;
+    return MELD_OK;
+}
+
+// MELD_AUTO for a sort: the tuned plan of this shape class, timing the
+// candidates (tile size x form per stage) on a scratch copy the first time.
+meld_status auto_sort_plan(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n,
+                           hipStream_t s, SortPlan *out) {
+    const bool pairs = payload != nullptr;
+    const uint32_t log_n = log2_ceil(n);
+    const std::string key = fmt("n=%u pairs=%d", log_n, pairs ? 1 : 0);
+    if (const meld::TuneEntry *e = ctx->tuner.find("sort", key)) {
+        *out = SortPlan{(uint32_t)e->log_t, e->lo != 0, e->hi != 0};
+        return MELD_OK;
+    }
+    const uint32_t max_t = max_log_tile(pairs);
+    *out = SortPlan{max_t, true, true};
+    if (capturing(s)) return MELD_OK;  // no timing inside a capture; untuned default
+    std::vector<uint32_t> tiles;
+    if (log_n <= max_t)
+        tiles.push_back(max_t);
+    else
+        for (uint32_t t = max_t - 1; t <= max_t; ++t) tiles.push_back(t);
+    const size_t words = pairs ? 2 * n : n;
+    meld_status st = ensure_words(&ctx->tune_buf, &ctx->tune_words, words, "tuning scratch");
+    if (st != MELD_OK) return st;
+    uint32_t *tk = ctx->tune_buf;
+    uint32_t *tv = pairs ? ctx->tune_buf + n : nullptr;
+    std::vector<SortPlan> cands;
+    std::vector<double> ms;
+    std::vector<int> flo, fhi;
+    for (uint32_t t : tiles)
+        for (int f = 0; f < 4; ++f) cands.push_back(SortPlan{t, (f & 1) != 0, (f & 2) != 0});
+    const int reps = n >= (1u << 24) ? 2 : 3;
+    for (const SortPlan &p : cands) {
+        double t = 0;
+        st = time_median(
+            s, reps,
+            [&]() -> meld_status {
+                hipError_t e = hipMemcpyAsync(tk, keys, n * 4, hipMemcpyDeviceToDevice, s);
+                if (e == hipSuccess && pairs)
+                    e = hipMemcpyAsync(tv, payload, n * 4, hipMemcpyDeviceToDevice, s);
+                return e == hipSuccess ? MELD_OK : hip_fail(e, "tuning copy");
+            },
+            [&]() { return sort_impl(ctx, tk, tv, n, p, -1, s); }, &t);
+        if (st != MELD_OK) return st;
+        ms.push_back(t);
+        flo.push_back(p.lo);
+        fhi.push_back(p.hi);
+    }
+    double mixed_lo = 0, mixed_hi = 0;
+    st = probe_network(ctx, std::min(log_n, max_t), s, &mixed_lo, &mixed_hi);
+    if (st != MELD_OK) return st;
+    const int pick = meld::choose((int)cands.size(), ms.data(), flo.data(), fhi.data(), mixed_lo,
+                                  mixed_hi, ctx->theta, ctx->tie);
+    *out = cands[pick];
+    meld::TuneEntry e;
+    e.op = "sort";
+    e.key = key;
+    e.lo = out->lo;
+    e.hi = out->hi;
+    e.log_t = (int)out->log_t;
+    e.form = out->lo ? 1 : 0;
+    e.ms = ms[pick];
+    e.mixed_lo = mixed_lo;
+    e.mixed_hi = mixed_hi;
+    e.trials = (int)cands.size();
+    ctx->tuner.put(e);
+    return MELD_OK;
+}
+
+// MELD_AUTO for a segmented sort: the tuned forms of this shape class, timing
+// the four per-stage combinations on a scratch copy the first time.
+meld_status auto_seg_forms(meld_ctx *ctx, uint32_t *keys, const uint32_t *offsets, size_t nseg,
+                           hipStream_t s, bool *lo, bool *hi) {
+    *lo = *hi = true;
+    if (capturing(s)) {
+        return MELD_OK;
+    }
+    uint32_t total = 0;
+    hipError_t e = hipMemcpyAsync(&total, offsets + nseg, sizeof total, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "reading offsets[nseg]");
+    const std::string key = fmt("nseg=%u total=%u", log2_ceil(nseg), log2_ceil(total));
+    if (const meld::TuneEntry *t = ctx->tuner.find("segsort", key)) {
+        *lo = t->lo != 0;
+        *hi = t->hi != 0;
+        return MELD_OK;
+    }
+    if (total == 0) return MELD_OK;
+    meld_status st = ensure_words(&ctx->tune_buf, &ctx->tune_words, total, "tuning scratch");
+    if (st != MELD_OK) return st;
+    st = ensure_seg(ctx, nseg);
+    if (st != MELD_OK) return st;
+    std::vector<double> ms;
+    std::vector<int> flo, fhi;
+    for (int f = 0; f < 4; ++f) {
+        const bool l = (f & 1) != 0, h = (f & 2) != 0;
+        double t = 0;
+        st = time_median(
+            s, 3,
+            [&]() -> meld_status {
+                hipError_t r = hipMemcpyAsync(ctx->tune_buf, keys, (size_t)total * 4,
+                                              hipMemcpyDeviceToDevice, s);
+                return r == hipSuccess ? MELD_OK : hip_fail(r, "tuning copy");
+            },
+            [&]() -> meld_status {
+                hipError_t r = meld::launch_segmented_sort(
+                    ctx->tune_buf, offsets, (uint32_t)nseg, ctx->seg_state, ctx->seg_cls,
+                    ctx->seg_queue, ctx->seg_pad, ctx->seg_grid, l, h, s);
+                return r == hipSuccess ? MELD_OK : hip_fail(r, "segmented sort launch");
+            },
+            &t);
+        if (st != MELD_OK) return st;
+        ms.push_back(t);
+        flo.push_back(l);
+        fhi.push_back(h);
+    }
+    unsigned long long c[4] = {0};
+    st = run_probe(ctx, s, 4, c, [&](unsigned long long *out) {
+        return meld::launch_probe_segments(offsets, (uint32_t)nseg, out, s);
+    });
+    if (st != MELD_OK) return st;
+    const double mixed_lo = c[1] ? (double)c[0] / (double)c[1] : 0.0;
+    const double mixed_hi = c[3] ? (double)c[2] / (double)c[3] : 0.0;
+    const int pick = meld::choose(4, ms.data(), flo.data(), fhi.data(), mixed_lo, mixed_hi,
+                                  ctx->theta, ctx->tie);
+    *lo = flo[pick] != 0;
+    *hi = fhi[pick] != 0;
+    meld::TuneEntry te;
+    te.op = "segsort";
+    te.key = key;
+    te.lo = *lo;
+    te.hi = *hi;
+    te.form = *lo ? 1 : 0;
+    te.ms = ms[pick];
+    te.mixed_lo = mixed_lo;
+    te.mixed_hi = mixed_hi;
+    te.trials = 4;
+    ctx->tuner.put(te);
+    return MELD_OK;
+}
+
+meld::RegionForm region_form(meld_variant v) {
+    return v == MELD_DIVERGENT        ? meld::RegionForm::kDivergent
+           : v == MELD_MELDED_INPLACE ? meld::RegionForm::kMeldedInPlace
+                                      : meld::RegionForm::kMelded;
+}
+
+// MELD_AUTO for the region: the tuned form of this shape class, timing the
+// three forms on the caller's arrays (the final run overwrites y).
+meld_status auto_region_form(meld_ctx *ctx, const float *x, float *y, size_t n, const float *tab,
+                             size_t tab_len, uint64_t seed, uint64_t thr,
+                             const meld::RegionSide &T, const meld::RegionSide &F, hipStream_t s,
+                             meld::RegionForm *out) {
+    *out = meld::RegionForm::kMelded;
+    const uint32_t p10 = (uint32_t)((thr * 10 + (1ull << 31)) >> 32);
+    const std::string key = fmt("n=%u tab=%u tT=%u tF=%u p10=%u", log2_ceil(n), log2_ceil(tab_len),
+                                T.trips, F.trips, p10);
+    if (const meld::TuneEntry *t = ctx->tuner.find("region", key)) {
+        *out = t->form == 0   ? meld::RegionForm::kDivergent
+               : t->form == 3 ? meld::RegionForm::kMeldedInPlace
+                              : meld::RegionForm::kMelded;
+        return MELD_OK;
+    }
+    if (capturing(s)) return MELD_OK;
+    const meld::RegionForm forms[3] = {meld::RegionForm::kDivergent, meld::RegionForm::kMelded,
+                                       meld::RegionForm::kMeldedInPlace};
+    const int codes[3] = {0, 1, 3};
+    double ms[3];
+    int flo[3], fhi[3];
+    for (int f = 0; f < 3; ++f) {
+        const meld::RegionForm form = forms[f];
+        auto run = [&]() -> meld_status {
+            hipError_t r = meld::launch_region(x, y, (uint32_t)n, tab, (uint32_t)(tab_len - 1),
+                                               seed, thr, T, F, form, s);
+            return r == hipSuccess ? MELD_OK : hip_fail(r, "region launch");
+        };
+        meld_status st = run();  // warm-up
+        if (st != MELD_OK) return st;
+        st = time_median(s, 3, []() { return MELD_OK; }, run, &ms[f]);
+        if (st != MELD_OK) return st;
+        flo[f] = fhi[f] = f == 0 ? 0 : 1;
+    }
+    unsigned long long c[3] = {0};
+    meld_status st = run_probe(ctx, s, 3, c, [&](unsigned long long *o) {
+        return meld::launch_probe_region((uint32_t)n, seed, thr, o, s);
+    });
+    if (st != MELD_OK) return st;
+    const double mixed = c[2] ? (double)c[0] / (double)c[2] : 0.0;
+    const int pick = meld::choose(3, ms, flo, fhi, mixed, mixed, ctx->theta, ctx->tie);
+    *out = forms[pick];
+    meld::TuneEntry te;
+    te.op = "region";
+    te.key = key;
+    te.lo = te.hi = flo[pick];
+    te.form = codes[pick];
+    te.ms = ms[pick];
+    te.mixed_lo = te.mixed_hi = mixed;
+    te.trials = 3;
+    ctx->tuner.put(te);
     return MELD_OK;
 }
 
@@ -339,6 +669,17 @@ meld_status meld_create(int hip_device, meld_ctx **out) {
     meld_ctx *ctx = new (std::nothrow) meld_ctx();
     if (ctx == nullptr) return fail(MELD_ENOMEM, "meld_create: out of host memory");
     ctx->device = hip_device;
+    hipDeviceProp_t prop;
+    int runtime = 0;
+    if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess &&
+        hipRuntimeGetVersion(&runtime) == hipSuccess)
+        ctx->tuner.set_identity(prop.gcnArchName, runtime);
+    if (const char *path = std::getenv("MELD_TUNE_CACHE")) {
+        if (path[0] != '\0' && !ctx->tuner.attach(path)) {
+            delete ctx;
+            return fail(MELD_EINVAL, "meld_create: malformed tuning cache %s", path);
+        }
+    }
     *out = ctx;
     g_err.clear();
     return MELD_OK;
@@ -351,7 +692,8 @@ void meld_destroy(meld_ctx *ctx) {
     drop_seg_graphs(ctx);
     if (ctx->capture_stream != nullptr) (void)hipStreamDestroy(ctx->capture_stream);
     for (void *p : {(void *)ctx->tail, (void *)ctx->seg_state, (void *)ctx->seg_cls,
-                    (void *)ctx->seg_queue, (void *)ctx->seg_pad})
+                    (void *)ctx->seg_queue, (void *)ctx->seg_pad, (void *)ctx->tune_buf,
+                    (void *)ctx->probe_buf})
         if (p != nullptr) (void)hipFree(p);
     delete ctx;
 }
@@ -369,7 +711,13 @@ meld_status meld_sort_u32(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size
     if (payload != nullptr && !is_device_ptr(ctx, payload))
         return fail(MELD_EINVAL, "meld_sort_u32: payload is not a device pointer on device %d",
                     ctx->device);
-    return sort_impl(ctx, keys, payload, n, variant, -1, static_cast<hipStream_t>(stream));
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    SortPlan plan = fixed_plan(payload != nullptr, variant);
+    if (variant == MELD_AUTO) {
+        meld_status st = auto_sort_plan(ctx, keys, payload, n, s, &plan);
+        if (st != MELD_OK) return st;
+    }
+    return sort_impl(ctx, keys, payload, n, plan, -1, s);
 }
 
 meld_status meld_sort_u32_steps(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n,
@@ -383,7 +731,8 @@ meld_status meld_sort_u32_steps(meld_ctx *ctx, uint32_t *keys, uint32_t *payload
     if (!is_device_ptr(ctx, keys) || (payload != nullptr && !is_device_ptr(ctx, payload)))
         return fail(MELD_EINVAL, "meld_sort_u32_steps: arrays must be device pointers");
     if (max_steps < 0) max_steps = -1;
-    return sort_impl(ctx, keys, payload, n, variant, max_steps, static_cast<hipStream_t>(stream));
+    return sort_impl(ctx, keys, payload, n, fixed_plan(payload != nullptr, variant), max_steps,
+                     static_cast<hipStream_t>(stream));
 }
 
 meld_status meld_divergent_region_f32(meld_ctx *ctx, const float *x, float *y, size_t n,
@@ -411,12 +760,14 @@ meld_status meld_divergent_region_f32(meld_ctx *ctx, const float *x, float *y, s
     if (x == y) return fail(MELD_EINVAL, "meld_divergent_region_f32: y aliases x");
     const meld::RegionSide T{side_true.a, side_true.off, side_true.step, side_true.trips};
     const meld::RegionSide F{side_false.a, side_false.off, side_false.step, side_false.trips};
-    const meld::RegionForm form = variant == MELD_DIVERGENT ? meld::RegionForm::kDivergent
-                                  : variant == MELD_MELDED_INPLACE
-                                      ? meld::RegionForm::kMeldedInPlace
-                                      : meld::RegionForm::kMelded;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    meld::RegionForm form = region_form(variant);
+    if (variant == MELD_AUTO) {
+        meld_status st = auto_region_form(ctx, x, y, n, tab, tab_len, seed, thr, T, F, s, &form);
+        if (st != MELD_OK) return st;
+    }
     hipError_t e = meld::launch_region(x, y, (uint32_t)n, tab, (uint32_t)(tab_len - 1), seed, thr,
-                                       T, F, form, static_cast<hipStream_t>(stream));
+                                       T, F, form, s);
     if (e != hipSuccess) return hip_fail(e, "region launch");
     return MELD_OK;
 }
@@ -426,9 +777,19 @@ meld_status meld_segmented_sort_u32(meld_ctx *ctx, uint32_t *keys, const uint32_
     if (ctx == nullptr) return fail(MELD_EINVAL, "meld_segmented_sort_u32: ctx is NULL");
     if ((unsigned)variant > MELD_MELDED_INPLACE)
         return fail(MELD_EINVAL, "meld_segmented_sort_u32: bad variant");
-    const bool m = use_melded(variant);
-    return segmented_impl(ctx, keys, offsets, nseg, m, m, static_cast<hipStream_t>(stream),
-                          "meld_segmented_sort_u32");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    bool lo = use_melded(variant), hi = lo;
+    if (variant == MELD_AUTO && nseg > 0 && nseg < (1ull << 31)) {
+        DeviceGuard g(ctx->device);
+        if (!is_device_ptr(ctx, keys) || !is_device_ptr(ctx, offsets))
+            return fail(MELD_EINVAL,
+                        "meld_segmented_sort_u32: keys and offsets must be device pointers on "
+                        "device %d",
+                        ctx->device);
+        meld_status st = auto_seg_forms(ctx, keys, offsets, nseg, s, &lo, &hi);
+        if (st != MELD_OK) return st;
+    }
+    return segmented_impl(ctx, keys, offsets, nseg, lo, hi, s, "meld_segmented_sort_u32");
 }
 
 meld_status meld_segmented_sort_u32_staged(meld_ctx *ctx, uint32_t *keys, const uint32_t *offsets,
@@ -440,6 +801,80 @@ meld_status meld_segmented_sort_u32_staged(meld_ctx *ctx, uint32_t *keys, const 
     return segmented_impl(ctx, keys, offsets, nseg, use_melded(low_phases),
                           use_melded(high_phases), static_cast<hipStream_t>(stream),
                           "meld_segmented_sort_u32_staged");
+}
+
+meld_status meld_tune(meld_ctx *ctx, const char *cache_path) {
+    if (ctx == nullptr || cache_path == nullptr)
+        return fail(MELD_EINVAL, "meld_tune: ctx and cache_path must not be NULL");
+    if (!ctx->tuner.attach(cache_path))
+        return fail(MELD_EINVAL, "meld_tune: malformed tuning cache %s", cache_path);
+    return MELD_OK;
+}
+
+meld_status meld_plan_describe(meld_ctx *ctx, char *buf, size_t len) {
+    if (ctx == nullptr || buf == nullptr)
+        return fail(MELD_EINVAL, "meld_plan_describe: ctx and buf must not be NULL");
+    const std::string d = ctx->tuner.describe();
+    if (d.size() + 1 > len)
+        return fail(MELD_EINVAL, "meld_plan_describe: buffer too small (need %zu bytes)",
+                    d.size() + 1);
+    std::memcpy(buf, d.c_str(), d.size() + 1);
+    return MELD_OK;
+}
+
+int meld_tune_choose(int n, const double *ms, const int *melded_lo, const int *melded_hi,
+                     double mixed_lo, double mixed_hi, double theta, double tie) {
+    if (n <= 0 || ms == nullptr || melded_lo == nullptr || melded_hi == nullptr) return -1;
+    return meld::choose(n, ms, melded_lo, melded_hi, mixed_lo, mixed_hi, theta, tie);
+}
+
+meld_status meld_probe_region(meld_ctx *ctx, size_t n, uint64_t seed, uint64_t thr,
+                              uint64_t out[3], void *stream) {
+    if (ctx == nullptr || out == nullptr)
+        return fail(MELD_EINVAL, "meld_probe_region: ctx and out must not be NULL");
+    if (n >= (1ull << 32) || thr > (1ull << 32))
+        return fail(MELD_EINVAL, "meld_probe_region: n >= 2^32 or thr > 2^32");
+    DeviceGuard g(ctx->device);
+    unsigned long long c[3] = {0, 0, 0};
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    meld_status st = run_probe(ctx, s, 3, c, [&](unsigned long long *o) {
+        return meld::launch_probe_region((uint32_t)n, seed, thr, o, s);
+    });
+    for (int i = 0; i < 3; ++i) out[i] = c[i];
+    return st;
+}
+
+meld_status meld_probe_network(meld_ctx *ctx, uint32_t log_t, uint64_t *out, void *stream) {
+    if (ctx == nullptr || out == nullptr)
+        return fail(MELD_EINVAL, "meld_probe_network: ctx and out must not be NULL");
+    if (log_t < 1 || log_t > 16) return fail(MELD_EINVAL, "meld_probe_network: log_t not in 1..16");
+    DeviceGuard g(ctx->device);
+    unsigned long long c[32] = {0};
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    meld_status st = run_probe(ctx, s, 2 * log_t, c, [&](unsigned long long *o) {
+        return meld::launch_probe_network(log_t, o, s);
+    });
+    for (uint32_t i = 0; i < 2 * log_t; ++i) out[i] = c[i];
+    return st;
+}
+
+meld_status meld_probe_segments(meld_ctx *ctx, const uint32_t *offsets, size_t nseg,
+                                uint64_t out[4], void *stream) {
+    if (ctx == nullptr || out == nullptr)
+        return fail(MELD_EINVAL, "meld_probe_segments: ctx and out must not be NULL");
+    if (nseg >= (1ull << 31)) return fail(MELD_EINVAL, "meld_probe_segments: nseg >= 2^31");
+    for (int i = 0; i < 4; ++i) out[i] = 0;
+    if (nseg == 0) return MELD_OK;
+    DeviceGuard g(ctx->device);
+    if (!is_device_ptr(ctx, offsets))
+        return fail(MELD_EINVAL, "meld_probe_segments: offsets must be a device pointer");
+    unsigned long long c[4] = {0, 0, 0, 0};
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    meld_status st = run_probe(ctx, s, 4, c, [&](unsigned long long *o) {
+        return meld::launch_probe_segments(offsets, (uint32_t)nseg, o, s);
+    });
+    for (int i = 0; i < 4; ++i) out[i] = c[i];
+    return st;
 }
 
 meld_status meld_set_option(meld_ctx *ctx, meld_option option, int64_t value) {

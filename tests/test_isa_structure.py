@@ -61,7 +61,7 @@ def region_asm(tmp_path_factory):
 @pytest.mark.parametrize("pairs", [False, True])
 def test_bitonic_divergent_sides_hold_lds_ops(bitonic_asm, pairs):
     p = "b1" if pairs else "b0"
-    body = _kernel(bitonic_asm, rf"bitonic_tile_kernelIL{p}ELb0ELi512ELi1E")
+    body = _kernel(bitonic_asm, rf"bitonic_tile_kernelIL{p}ELb0ELb0ELi512ELi1E")
     width = "b64" if pairs else "b32"
     for side in ("ascending\n", "descending\n"):
         blocks = _blocks_after(body, side)
@@ -76,7 +76,7 @@ def test_bitonic_divergent_sides_hold_lds_ops(bitonic_asm, pairs):
 @pytest.mark.parametrize("pairs", [False, True])
 def test_bitonic_melded_has_one_load_store_pair(bitonic_asm, pairs):
     p = "b1" if pairs else "b0"
-    body = _kernel(bitonic_asm, rf"bitonic_tile_kernelIL{p}ELb1ELi512ELi1E")
+    body = _kernel(bitonic_asm, rf"bitonic_tile_kernelIL{p}ELb1ELb1ELi512ELi1E")
     width = "b64" if pairs else "b32"
     assert "; side" not in body
     # the comparator loop: one load pair and one (conditional) store pair
