@@ -41,6 +41,9 @@ def _parse():
     ap.add_argument("--reps", type=int, default=30, help="launches per per-kernel timing")
     ap.add_argument("--no-sort", action="store_true", help="skip the sort measurements")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-seg", action="store_true", help="skip the segmented sort")
+    ap.add_argument("--serve-seconds", type=float, default=2.0,
+                    help="length of the Poisson serving trace (0 skips serving)")
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: a 256 MiB copy, then a few steps")
     return ap.parse_args()
@@ -196,6 +199,14 @@ def main():
     if not args.no_sort:
         sort_info = _bench_sort(torch, np, meld, workloads, dev, args)
 
+    seg_info = None
+    if not args.no_seg:
+        seg_info = _bench_segmented(torch, np, meld, workloads, dev)
+
+    serve_info = None
+    if args.serve_seconds > 0:
+        serve_info = _bench_serving(meld, workloads, args.serve_seconds)
+
     cpu = None
     if not args.no_cpu:
         cpu = _cpu_baseline(np, workloads, x, tab, st, sf, thr)
@@ -236,6 +247,8 @@ def main():
                     "counter-measured HBM bytes per launch",
         },
         "sort": sort_info,
+        "segmented": seg_info,
+        "serving": serve_info,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
@@ -289,6 +302,70 @@ def _bench_sort(torch, np, meld, workloads, dev, args):
                         "speedup": round(d / m, 4),
                         "melded_Gkeys_s": round(n / (m * 1e-3) / 1e9, 3)}
     return res
+
+
+def _time_sorts(torch, np, run, restore, reps):
+    ts = []
+    for _ in range(reps):
+        restore()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        run()
+        e.record()
+        e.synchronize()
+        ts.append(s.elapsed_time(e))
+    return float(np.median(ts))
+
+
+def _bench_segmented(torch, np, meld, workloads, dev):
+    """4096 segments, lengths log-uniform in [2^6, 2^16]: one graph replay per sort."""
+    off = workloads.segment_offsets(SEED, 4096)
+    n = int(off[-1])
+    od = torch.from_numpy(off.view(np.int32)).to(dev)
+    pristine = torch.from_numpy(workloads.keys_u32(SEED, n).view(np.int32)).to(dev)
+    work = torch.empty_like(pristine)
+    forms = {"divergent": ("divergent", "divergent"), "melded": ("melded", "melded"),
+             "melded_low_only": ("melded", "divergent"), "melded_high_only": ("divergent", "melded")}
+    out = {"segments": 4096, "keys": n}
+    for name, (lo, hi) in forms.items():
+        ms = _time_sorts(torch, np, lambda: meld.segmented_sort(work, od, low=lo, high=hi),
+                         lambda: work.copy_(pristine), 7)
+        out[name + "_ms"] = round(ms, 4)
+    work.copy_(pristine)
+    meld.segmented_sort(work, od, variant="auto")  # tunes this shape class once
+    ms = _time_sorts(torch, np, lambda: meld.segmented_sort(work, od, variant="auto"),
+                     lambda: work.copy_(pristine), 7)
+    out["auto_ms"] = round(ms, 4)
+    out["auto_Gkeys_s"] = round(n / (ms * 1e-3) / 1e9, 3)
+    out["speedup_melded"] = round(out["divergent_ms"] / out["melded_ms"], 4)
+    (ml, al), (mh, ah) = meld.probe_segments(od)
+    out["mixed_fraction_low_phases"] = round(ml / al, 4) if al else 0.0
+    out["mixed_fraction_high_phases"] = round(mh / ah, 4) if ah else 0.0
+    out["low_phase_share_of_work"] = round(al / (al + ah), 4)
+    for e in json.loads(meld.plan_describe())["entries"]:
+        if e["op"] == "segsort":
+            out["tuned_plan"] = {"low": "melded" if e["lo"] else "divergent",
+                                 "high": "melded" if e["hi"] else "divergent"}
+    meld.segmented_sort_check(0)
+    return out
+
+
+def _bench_serving(meld, workloads, seconds):
+    """Poisson 2000 req/s, sorts 2^10..2^22 keys and region jobs 2^16..2^20 lanes (p = 0.5)."""
+    from paper_2107_05681_amd import serve
+    trace = workloads.serving_trace(SEED, rate=2000.0, duration_s=seconds)
+    with serve.Server(budget_bytes=8 << 30, slots=8, variant="melded", table_seed=SEED,
+                      table_log2=24) as srv:
+        done = serve.replay(srv, trace, timeout_s=120 + 10 * seconds)
+        st = srv.stats()
+    summ = serve.latency_summary(done)
+    return {"rate_per_s": 2000, "seconds": seconds, "jobs": summ["jobs"],
+            "failed": st["failed"], "p50_ms": round(summ["p50_ms"], 3),
+            "p99_ms": round(summ["p99_ms"], 3), "jobs_per_s": round(summ["jobs_per_s"], 1),
+            "Gkeys_s": round(summ["keys_per_s"] / 1e9, 4),
+            "Glanes_s": round(summ["lanes_per_s"] / 1e9, 4), "launches": st["launches"],
+            "batched_jobs": st["batched_jobs"], "max_concurrent": st["max_concurrent"],
+            "max_inflight_MB": round(st["max_inflight_bytes"] / 1e6, 1), "budget_GB": 8.6}
 
 
 def _cpu_baseline(np, workloads, x, tab, st, sf, thr):

@@ -244,6 +244,93 @@ meld_status meld_plan_describe(meld_ctx *ctx, char *buf, size_t len);
 int meld_tune_choose(int n, const double *ms, const int *melded_lo, const int *melded_hi,
                      double mixed_lo, double mixed_hi, double theta, double tie);
 
+/* ---- Serving ---------------------------------------------------------------
+ * A request loop for sort and region jobs of mixed sizes on one GPU. Jobs
+ * are submitted at any time (non-blocking) and wait in a FIFO. A dispatcher
+ * thread admits the head of the queue as soon as a slot (a stream with its
+ * own library context, so concurrent jobs never share scratch) and enough of
+ * the device-memory budget are free: strict FIFO, a job larger than the
+ * budget is rejected at submit. Continuous batching: the small sort jobs
+ * (<= 65536 keys) standing one after the other at the head of the queue are
+ * packed into one segmented-sort launch; larger sorts and region jobs run one
+ * per slot, and the slots overlap on the device. Inputs are generated on the
+ * device from each job's seed (sort keys H(seed,1,i) >> 32; region x
+ * (H(seed,2,i) >> 40) * 2^-24, over one resident table). A job's result stays
+ * in the budget until meld_server_release. Every result is bit-identical to
+ * the same job run alone. */
+
+typedef struct meld_server meld_server;
+
+typedef enum { MELD_JOB_SORT = 0, MELD_JOB_REGION = 1 } meld_job_kind;
+
+typedef struct {
+    int kind;                 /* meld_job_kind */
+    size_t n;                 /* keys (sort) or lanes (region), 1 .. 2^31 - 1 */
+    uint64_t seed;            /* input stream seed (and the region's branch seed) */
+    uint64_t thr;             /* region: branch threshold in [0, 2^32] */
+    meld_side side_true;      /* region sides */
+    meld_side side_false;
+} meld_job;
+
+typedef struct {
+    uint64_t job_id;
+    meld_status status;       /* MELD_EHIP if its launch failed */
+    int kind;
+    size_t n;
+    double submit_s, start_s, done_s;  /* seconds since the server was created */
+    const void *result_dev;   /* device u32[n] sorted keys or f32[n] y; NULL on failure;
+                                 valid until meld_server_release(job_id) */
+    int batched;              /* jobs in the launch this one ran in */
+} meld_completion;
+
+typedef struct {
+    uint64_t submitted, rejected, completed, failed, launches, batched_jobs;
+    size_t budget_bytes, inflight_bytes, max_inflight_bytes, pending;
+    int slots, max_concurrent;
+} meld_server_stats;
+
+/* Creates a server on HIP device hip_device: an arena of mem_budget_bytes for
+ * job buffers, `slots` streams (1..64), the forms to run (variant), and a
+ * resident region table of 2^table_log2 entries generated from table_seed.
+ * Errors: MELD_EINVAL for bad arguments, MELD_ENOMEM if the arena or table
+ * cannot be allocated (message in meld_server_last_error()). */
+meld_status meld_server_create(int hip_device, size_t mem_budget_bytes, int slots,
+                               meld_variant variant, uint64_t table_seed, uint32_t table_log2,
+                               meld_server **out);
+
+/* The same scheduler over a simulated device (host only, no GPU calls): a
+ * unit finishes ns_per_item nanoseconds per key or lane after its launch;
+ * jobs whose ids are listed in fail_ids complete with MELD_EHIP. For tests of
+ * admission, batching, fairness and failure isolation. */
+meld_status meld_server_create_simulated(size_t mem_budget_bytes, int slots, double ns_per_item,
+                                         const uint64_t *fail_ids, size_t n_fail,
+                                         meld_server **out);
+
+/* Queues a job; returns its id. MELD_ENOMEM if it needs more than the whole
+ * budget (sort: 4n bytes; region: 8n bytes, each rounded up to 256). */
+meld_status meld_server_submit(meld_server *srv, const meld_job *job, uint64_t *job_id);
+
+/* Moves up to cap completions into out (completion order). */
+meld_status meld_server_poll(meld_server *srv, meld_completion *out, size_t cap, size_t *n_out);
+
+/* Frees a completed job's result (its budget share returns to the pool). */
+meld_status meld_server_release(meld_server *srv, uint64_t job_id);
+
+/* Copies the first `bytes` of a completed job's result to host memory
+ * (synchronous). MELD_EUNSUPPORTED on a simulated server. */
+meld_status meld_server_read(meld_server *srv, uint64_t job_id, void *host_dst, size_t bytes);
+
+/* Waits until no job is queued or running (completed results stay). */
+meld_status meld_server_drain(meld_server *srv, double timeout_s);
+
+meld_status meld_server_stats_get(meld_server *srv, meld_server_stats *out);
+
+/* Message of the last failed server call on this host thread. */
+const char *meld_server_last_error(void);
+
+/* Stops the dispatcher (running work is waited for) and frees everything. */
+void meld_server_destroy(meld_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -32,7 +32,10 @@ EXPORTS = ("meld_version", "meld_create", "meld_destroy", "meld_last_error", "me
            "meld_sort_u32_steps", "meld_segmented_sort_u32", "meld_segmented_sort_u32_staged",
            "meld_segmented_sort_check", "meld_set_option", "meld_probe_region",
            "meld_probe_network", "meld_probe_segments", "meld_tune", "meld_plan_describe",
-           "meld_tune_choose",
+           "meld_tune_choose", "meld_server_create", "meld_server_create_simulated",
+           "meld_server_submit", "meld_server_poll", "meld_server_release", "meld_server_read",
+           "meld_server_drain", "meld_server_stats_get", "meld_server_last_error",
+           "meld_server_destroy",
            "meld_divergent_region_f32")
 
 

@@ -54,6 +54,14 @@ hipError_t launch_bitonic_global(const SortArray &a, uint32_t log_n, uint32_t m,
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t count, hipStream_t stream);
 
+// Seeded inputs generated on the device (gen.hip).
+hipError_t launch_gen_keys(uint32_t *keys, uint32_t n, uint64_t seed, hipStream_t s);
+hipError_t launch_gen_keys_segments(uint32_t *keys, const uint32_t *offsets,
+                                    const uint64_t *seeds, uint32_t nseg, uint32_t max_len,
+                                    hipStream_t s);
+hipError_t launch_gen_x(float *x, uint32_t n, uint64_t seed, hipStream_t s);
+hipError_t launch_gen_tab(float *tab, uint32_t m, uint64_t seed, hipStream_t s);
+
 // Divergence probes (probe.hip). Counters are accumulated into out.
 // Region: out[0] mixed waves, out[1] true lanes, out[2] waves.
 hipError_t launch_probe_region(uint32_t n, uint64_t seed, uint64_t thr, unsigned long long *out,

@@ -1,0 +1,102 @@
+"""Host-only tests of the serving scheduler over the simulated executor."""
+import os
+
+import pytest
+
+
+def _serve():
+    import paper_2107_05681_amd as meld
+    if not os.path.exists(meld.LIB_PATH):
+        from paper_2107_05681_amd import build
+        build.build()
+    from paper_2107_05681_amd import serve
+    return meld, serve
+
+
+def _sort(n, seed=1):
+    return dict(kind=0, n=n, seed=seed)
+
+
+def _region(n, seed=1):
+    return dict(kind=1, n=n, seed=seed, thr=1 << 31,
+                side_true=dict(a=0.5, off=0, step=3, trips=4),
+                side_false=dict(a=0.75, off=64, step=5, trips=4))
+
+
+def test_budget_is_never_exceeded_and_all_jobs_finish():
+    meld, serve = _serve()
+    trace = []
+    t = 0.0
+    for i in range(200):
+        t += 0.0002
+        n = [1000, 70000, 5000, 100000, 3000][i % 5]
+        job = _region(n // 4, i) if i % 3 == 0 else _sort(n, i)
+        job["arrival_s"] = t
+        trace.append(job)
+    budget = 1 << 20
+    with serve.Server(budget_bytes=budget, slots=4, simulated_ns_per_item=20) as srv:
+        done = serve.replay(srv, trace, timeout_s=60)
+        st = srv.stats()
+    assert len(done) == 200 and all(c["status"] == meld.OK for c in done)
+    assert st["max_inflight_bytes"] <= budget
+    assert st["completed"] == 200 and st["rejected"] == 0
+
+
+def test_oversize_job_is_rejected():
+    meld, serve = _serve()
+    with serve.Server(budget_bytes=1024, slots=2, simulated_ns_per_item=1) as srv:
+        with pytest.raises(meld.MeldError) as e:
+            srv.submit(_sort(1000))
+        assert e.value.status == meld.ENOMEM
+        assert srv.stats()["rejected"] == 1
+
+
+def test_fifo_admission_order():
+    meld, serve = _serve()
+    trace = [dict(_region(20000, i), arrival_s=0.0) for i in range(30)]
+    with serve.Server(budget_bytes=1 << 30, slots=3, simulated_ns_per_item=50) as srv:
+        done = serve.replay(srv, trace, timeout_s=60)
+    by_id = sorted(done, key=lambda c: c["job_id"])
+    starts = [c["start_s"] for c in by_id]
+    assert starts == sorted(starts)
+
+
+def test_small_sorts_arriving_together_are_batched():
+    meld, serve = _serve()
+    with serve.Server(budget_bytes=1 << 30, slots=1, simulated_ns_per_item=200) as srv:
+        srv.submit(_region(100000))  # occupies the only slot for ~20 ms
+        ids = [srv.submit(_sort(2000 + i, i)) for i in range(50)]
+        srv.drain(30)
+        comps = srv.poll()
+        st = srv.stats()
+    assert len(comps) == 51
+    assert st["launches"] == 2 and st["batched_jobs"] == 50
+    assert all(c["batched"] == 50 for c in comps if c["job_id"] in ids)
+
+
+def test_memory_bound_admission_serialises():
+    meld, serve = _serve()
+    trace = [dict(_region(5000, i), arrival_s=0.0) for i in range(10)]  # 40 KB each
+    with serve.Server(budget_bytes=64 << 10, slots=4, simulated_ns_per_item=100) as srv:
+        done = serve.replay(srv, trace, timeout_s=60)
+        st = srv.stats()
+    assert len(done) == 10
+    assert st["max_concurrent"] == 1 and st["max_inflight_bytes"] <= 64 << 10
+
+
+def test_injected_failures_are_isolated():
+    meld, serve = _serve()
+    trace = [dict(_region(1000, i), arrival_s=0.0) for i in range(12)]
+    with serve.Server(budget_bytes=1 << 24, slots=2, simulated_ns_per_item=10,
+                      fail_ids=(3, 7)) as srv:
+        done = serve.replay(srv, trace, timeout_s=60)
+    status = {c["job_id"]: c["status"] for c in done}
+    assert status[3] == meld.EHIP and status[7] == meld.EHIP
+    assert all(s == meld.OK for j, s in status.items() if j not in (3, 7))
+
+
+def test_release_of_unknown_job_fails():
+    meld, serve = _serve()
+    with serve.Server(budget_bytes=1 << 20, slots=1, simulated_ns_per_item=1) as srv:
+        with pytest.raises(meld.MeldError):
+            srv.release(12345)

@@ -138,3 +138,35 @@ def region_inputs(seed: int, n: int, tab_log2: int = REGION_TAB_LOG2):
     if tab_log2 != REGION_TAB_LOG2:
         side_f["off"] = 1 << (tab_log2 - 1)
     return x_f32(seed, n), tab_f32(seed, 1 << tab_log2), side_t, side_f
+
+
+def serving_trace(seed: int, rate: float, duration_s: float, sort_log2=(10, 22),
+                  region_log2=(16, 20), p_region: float = 0.5, p_branch: float = 0.5,
+                  tab_log2: int = REGION_TAB_LOG2):
+    """Poisson arrivals of sort and region jobs (a list of dicts, arrival order).
+
+    Job i: gap to the previous arrival -ln(1 - u7) / rate with u7 = uniform(seed, 7, i);
+    kind region iff uniform(seed, 8, i) < p_region; size floor(2^(lo + (hi - lo) u9))
+    with u9 = uniform(seed, 9, i); the job's own seed H(seed, 10, i) drives its input
+    stream (keys or x) and, for a region job, its branch bits and trip counts.
+    """
+    import math
+    jobs, t, i = [], 0.0, 0
+    thr = thr_from_p(p_branch)
+    while True:
+        t += -math.log(1.0 - uniform(seed, 7, i)) / rate
+        if t > duration_s:
+            return jobs
+        region = uniform(seed, 8, i) < p_region
+        lo, hi = region_log2 if region else sort_log2
+        n = int(2.0 ** (lo + (hi - lo) * uniform(seed, 9, i)))
+        js = hash64(seed, 10, i)
+        job = dict(arrival_s=t, kind=1 if region else 0, n=n, seed=js, thr=thr)
+        if region:
+            tt, tf = trips(js)
+            job["side_true"] = dict(SIDE_TRUE, trips=tt)
+            job["side_false"] = dict(SIDE_FALSE, trips=tf)
+            if tab_log2 != REGION_TAB_LOG2:
+                job["side_false"]["off"] = 1 << (tab_log2 - 1)
+        jobs.append(job)
+        i += 1
