@@ -44,8 +44,10 @@ def _parse():
     ap.add_argument("--no-seg", action="store_true", help="skip the segmented sort")
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="length of the Poisson serving trace (0 skips serving)")
-    ap.add_argument("--profile", action="store_true",
-                    help="short run for rocprofv3: a 256 MiB copy, then a few steps")
+    ap.add_argument("--profile", nargs="?", const="region", default=None,
+                    choices=["region", "sort"],
+                    help="short run for rocprofv3: 'region' (a 256 MiB copy, then a few "
+                         "steps) or 'sort' (2^16 keys and the 4096-segment sort, each form)")
     return ap.parse_args()
 
 
@@ -114,6 +116,9 @@ def main():
         for p in PS:
             region(p, "auto")
 
+    if args.profile == "sort":
+        _profile_sorts(torch, np, meld, workloads, dev)
+        return
     if args.profile:
         src = torch.empty(1 << 26, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -302,6 +307,21 @@ def _bench_sort(torch, np, meld, workloads, dev, args):
                         "speedup": round(d / m, 4),
                         "melded_Gkeys_s": round(n / (m * 1e-3) / 1e9, 3)}
     return res
+
+
+def _profile_sorts(torch, np, meld, workloads, dev):
+    """One launch sequence per form: 2^16-key sort, then the 4096-segment sort."""
+    keys = torch.from_numpy(workloads.keys_u32(SEED, 1 << 16).view(np.int32)).to(dev)
+    for v in ("divergent", "melded"):
+        meld.sort(keys.clone(), variant=v)
+    off = workloads.segment_offsets(SEED, 4096)
+    od = torch.from_numpy(off.view(np.int32)).to(dev)
+    seg = torch.from_numpy(workloads.keys_u32(SEED, int(off[-1])).view(np.int32)).to(dev)
+    meld.set_option(0, meld.OPT_USE_GRAPHS, 0)
+    for lo, hi in (("divergent", "divergent"), ("melded", "melded")):
+        meld.segmented_sort(seg.clone(), od, low=lo, high=hi)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_run": "sort"}))
 
 
 def _time_sorts(torch, np, run, restore, reps):

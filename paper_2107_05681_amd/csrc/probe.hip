@@ -14,19 +14,27 @@ namespace {
 
 // Region: waves are lanes [64w, 64w + 64) of [0, n).
 // out[0] += waves whose branch mask is mixed, out[1] += lanes taking the true
-// side, out[2] += waves.
+// side, out[2] += waves. Each wave walks the lane range with a grid stride and
+// adds its totals once (one atomic per wave and counter).
 __global__ __launch_bounds__(256) void probe_region_kernel(uint32_t n, uint64_t bkey,
                                                            uint64_t thr,
                                                            unsigned long long *out) {
-    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
-    const bool valid = i < n;
-    const bool taken = valid && (mix64(bkey + i) >> 32) < thr;
-    const uint64_t mt = __ballot(taken);
-    const uint64_t mv = __ballot(valid);
-    if (__lane_id() == 0 && mv != 0) {
-        atomicAdd(&out[0], (mt != 0 && mt != mv) ? 1ull : 0ull);
-        atomicAdd(&out[1], (unsigned long long)__popcll(mt));
-        atomicAdd(&out[2], 1ull);
+    unsigned long long mixed = 0, ones = 0, waves = 0;
+    const uint32_t stride = gridDim.x * 256;
+    for (uint32_t base = blockIdx.x * 256 + (threadIdx.x & ~63u); base < n; base += stride) {
+        const uint32_t i = base + __lane_id();
+        const bool valid = i < n;
+        const bool taken = valid && (mix64(bkey + i) >> 32) < thr;
+        const uint64_t mt = __ballot(taken);
+        const uint64_t mv = __ballot(valid);
+        mixed += (mt != 0 && mt != mv) ? 1ull : 0ull;
+        ones += (unsigned long long)__popcll(mt);
+        waves += 1;
+    }
+    if (__lane_id() == 0 && waves != 0) {
+        atomicAdd(&out[0], mixed);
+        atomicAdd(&out[1], ones);
+        atomicAdd(&out[2], waves);
     }
 }
 
@@ -110,8 +118,9 @@ __global__ __launch_bounds__(64) void probe_segments_kernel(const uint32_t *__re
 hipError_t launch_probe_region(uint32_t n, uint64_t seed, uint64_t thr, unsigned long long *out,
                                hipStream_t stream) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(probe_region_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, n,
-                       stream_key(seed, 4), thr, out);
+    const uint32_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(probe_region_kernel, dim3(blocks < 2048 ? blocks : 2048), dim3(256), 0,
+                       stream, n, stream_key(seed, 4), thr, out);
     return hipGetLastError();
 }
 
