@@ -45,9 +45,10 @@ def _parse():
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="length of the Poisson serving trace (0 skips serving)")
     ap.add_argument("--profile", nargs="?", const="region", default=None,
-                    choices=["region", "sort"],
+                    choices=["region", "sort", "pairs"],
                     help="short run for rocprofv3: 'region' (a 256 MiB copy, then a few "
-                         "steps) or 'sort' (2^16 keys and the 4096-segment sort, each form)")
+                         "steps), 'sort' (2^16 keys and the 4096-segment sort, each form) "
+                         "or 'pairs' (one 2^28-pair sort per form)")
     return ap.parse_args()
 
 
@@ -118,6 +119,9 @@ def main():
 
     if args.profile == "sort":
         _profile_sorts(torch, np, meld, workloads, dev)
+        return
+    if args.profile == "pairs":
+        _profile_pairs(torch, np, meld, workloads, dev)
         return
     if args.profile:
         src = torch.empty(1 << 26, dtype=torch.float32, device=dev)
@@ -322,6 +326,20 @@ def _profile_sorts(torch, np, meld, workloads, dev):
         meld.segmented_sort(seg.clone(), od, low=lo, high=hi)
     torch.cuda.synchronize()
     print(json.dumps({"profile_run": "sort"}))
+
+
+def _profile_pairs(torch, np, meld, workloads, dev):
+    """One 2^28-pair sort per form."""
+    n = 1 << 28
+    kin = torch.from_numpy(workloads.keys_u32(SEED, n).view(np.int32)).to(dev)
+    pin = torch.arange(n, dtype=torch.int32, device=dev)
+    k, p = torch.empty_like(kin), torch.empty_like(pin)
+    for v in ("divergent", "melded"):
+        k.copy_(kin)
+        p.copy_(pin)
+        meld.sort(k, p, variant=v)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_run": "pairs"}))
 
 
 def _time_sorts(torch, np, run, restore, reps):

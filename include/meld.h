@@ -78,7 +78,13 @@ typedef enum {
      * launches (captured once per keys/offsets/nseg/forms, at most 8 kept);
      * 0: launch them one by one. A stream that is itself being captured
      * always gets the launches directly. */
-    MELD_OPT_USE_GRAPHS = 0
+    MELD_OPT_USE_GRAPHS = 0,
+    /* log2 of the tile of meld_sort_u32 and meld_sort_u32_steps: 0 (default)
+     * lets the library choose (timed under MELD_AUTO, from n otherwise);
+     * 8..14 for keys, 8..13 for pairs, fixes it (a larger value applies to
+     * key-only sorts and is clamped to 13 for pairs). MELD_EINVAL outside
+     * {0} and 8..14. */
+    MELD_OPT_SORT_LOG_TILE = 1
 } meld_option;
 
 /* Sets a context option. MELD_EINVAL for an unknown option. */

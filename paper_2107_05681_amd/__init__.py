@@ -207,6 +207,7 @@ def segmented_sort_check(device: int = 0, stream=None):
 
 
 OPT_USE_GRAPHS = 0
+OPT_SORT_LOG_TILE = 1
 
 
 def set_option(device: int, option: int, value: int) -> None:

@@ -191,6 +191,382 @@ __device__ __forceinline__ void cex_regs(E &x, E &y, bool up) {
     y = up ? mx : mn;
 }
 
+// Merge of one tile in a phase k > tile (steps j = T/2 .. 1; the direction is
+// bit k of the tile's base, the same for the whole tile, so the two forms
+// coincide). Each thread holds 16 elements in registers; a layout names which
+// four element bits form the register index, the remaining bits are the
+// thread index. Steps on register bits run in registers; an LDS transpose
+// (one padding slot per 16 elements against bank conflicts) changes layout.
+//
+//   layout V (B = -1): register bits 0, 1 = element bits 0, 1 and register
+//     bits 2, 3 = element bits L-2, L-1; thread t holds the 16-byte groups
+//     4t and 4t + 2^(L-2) k, so consecutive lanes move consecutive 16 bytes.
+//   window B >= 0: element bits [B, B+4) are the register index.
+//
+// Sequence: load in V, steps L-1 and L-2; windows L-6, L-10, ... (the last one
+// clamped at 0) take the next bits four at a time; back to V to store (vector
+// modes), or to window L-4 (lane-linear elements) for per-element modes.
+constexpr int kMergeE = 16;
+
+template <int L, int B>
+__device__ __forceinline__ uint32_t merge_index(uint32_t t, uint32_t r) {
+    if constexpr (B < 0)
+        return (r & 3u) | (t << 2) | ((r >> 2) << (L - 2));
+    else
+        return (t & ((1u << B) - 1)) | (r << B) | ((t >> B) << (B + 4));
+}
+
+__device__ __forceinline__ uint32_t merge_phys(uint32_t i) { return i + (i >> 4); }
+
+// Base bit of window w >= 1.
+template <int L>
+constexpr int merge_window_base(int w) {
+    return L - 2 - 4 * w > 0 ? L - 2 - 4 * w : 0;
+}
+
+template <int L, int FROM, int TO, typename E>
+__device__ __forceinline__ void merge_transpose(E (&e)[kMergeE], E *s, uint32_t t) {
+#pragma unroll
+    for (int r = 0; r < kMergeE; ++r) s[merge_phys(merge_index<L, FROM>(t, r))] = e[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kMergeE; ++r) e[r] = s[merge_phys(merge_index<L, TO>(t, r))];
+    __syncthreads();
+}
+
+// The step on register bit Q for all 16 registers.
+template <int Q, typename E>
+__device__ __forceinline__ void merge_reg_step(E (&e)[kMergeE], bool up) {
+#pragma unroll
+    for (int r = 0; r < kMergeE; ++r)
+        if ((r & (1 << Q)) == 0) cex_regs(e[r], e[r | (1 << Q)], up);
+}
+
+// Steps on element bits TOP .. B of window B (register bit = element bit - B);
+// the step on element bit i is number L-1-i of the merge (0-based).
+template <int L, int B, int BIT, typename E>
+__device__ __forceinline__ void merge_window_steps(E (&e)[kMergeE], bool up, int32_t nsteps) {
+    if constexpr (BIT >= B) {
+        if (L - 1 - BIT < nsteps) merge_reg_step<BIT - B>(e, up);
+        merge_window_steps<L, B, BIT - 1>(e, up, nsteps);
+    }
+}
+
+// Window w (w >= 1) and the ones after it; PREV is the layout e is in.
+template <int L, int W, int PREV, typename E>
+__device__ __forceinline__ void merge_windows(E (&e)[kMergeE], E *s, uint32_t t, bool up,
+                                              int32_t nsteps) {
+    constexpr int B = merge_window_base<L>(W);
+    constexpr int TOP = W == 1 ? L - 3 : merge_window_base<L>(W - 1) - 1;
+    merge_transpose<L, PREV, B>(e, s, t);
+    merge_window_steps<L, B, TOP>(e, up, nsteps);
+    if constexpr (B > 0) merge_windows<L, W + 1, B>(e, s, t, up, nsteps);
+}
+
+// Runtime layout index: window B (element bits [B, B+4) are the register
+// index) for a B known only at run time.
+__device__ __forceinline__ uint32_t window_tpart(uint32_t t, uint32_t B) {
+    return (t & ((1u << B) - 1)) | ((t >> B) << (B + 4));
+}
+
+// Thread t's 16 elements of the tile at base in layout V. Modes: vector
+// (16-byte groups), sentinel (positions >= n read as the pad value), plain or
+// tail (positions >= n from the tail workspace; a tile wholly below n loads
+// directly).
+template <bool PAIRS, int L>
+__device__ __forceinline__ void regs_load(const SortArray &a, uint32_t base, uint32_t t, int mode,
+                                          typename ElemOf<PAIRS>::type (&e)[kMergeE]) {
+    using E = typename ElemOf<PAIRS>::type;
+    if (mode == kPlainVec) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const uint32_t p = base + merge_index<L, -1>(t, 4 * c);
+            const uint4 k = *reinterpret_cast<const uint4 *>(a.keys + p);
+            if constexpr (PAIRS) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(a.vals + p);
+                e[4 * c + 0] = ((E)k.x << 32) | v.x;
+                e[4 * c + 1] = ((E)k.y << 32) | v.y;
+                e[4 * c + 2] = ((E)k.z << 32) | v.z;
+                e[4 * c + 3] = ((E)k.w << 32) | v.w;
+            } else {
+                e[4 * c + 0] = k.x;
+                e[4 * c + 1] = k.y;
+                e[4 * c + 2] = k.z;
+                e[4 * c + 3] = k.w;
+            }
+        }
+    } else if (mode == kSentinel) {
+#pragma unroll
+        for (int r = 0; r < kMergeE; ++r)
+            e[r] = load_elem<PAIRS, kSentinel>(a, base + merge_index<L, -1>(t, r));
+    } else {
+        const bool below_n = base + (1u << L) <= a.n;  // uniform per workgroup
+#pragma unroll
+        for (int r = 0; r < kMergeE; ++r) {
+            const uint32_t p = base + merge_index<L, -1>(t, r);
+            e[r] = below_n ? load_elem<PAIRS, kPlain>(a, p) : load_elem<PAIRS, kTail>(a, p);
+        }
+    }
+}
+
+// Stores the tile from window 0: through layout V with 16-byte stores, or
+// through window L-4 (consecutive lanes, consecutive elements) per element.
+template <bool PAIRS, int L>
+__device__ __forceinline__ void regs_store(const SortArray &a, typename ElemOf<PAIRS>::type *s,
+                                           uint32_t base, uint32_t t, int mode,
+                                           typename ElemOf<PAIRS>::type (&e)[kMergeE]) {
+    if (mode == kPlainVec) {
+        merge_transpose<L, 0, -1>(e, s, t);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const uint32_t p = base + merge_index<L, -1>(t, 4 * c);
+            if constexpr (PAIRS) {
+                *reinterpret_cast<uint4 *>(a.keys + p) =
+                    make_uint4((uint32_t)(e[4 * c] >> 32), (uint32_t)(e[4 * c + 1] >> 32),
+                               (uint32_t)(e[4 * c + 2] >> 32), (uint32_t)(e[4 * c + 3] >> 32));
+                *reinterpret_cast<uint4 *>(a.vals + p) =
+                    make_uint4((uint32_t)e[4 * c], (uint32_t)e[4 * c + 1],
+                               (uint32_t)e[4 * c + 2], (uint32_t)e[4 * c + 3]);
+            } else {
+                *reinterpret_cast<uint4 *>(a.keys + p) =
+                    make_uint4(e[4 * c], e[4 * c + 1], e[4 * c + 2], e[4 * c + 3]);
+            }
+        }
+        return;
+    }
+    merge_transpose<L, 0, L - 4>(e, s, t);
+    if (mode == kSentinel) {
+#pragma unroll
+        for (int r = 0; r < kMergeE; ++r)
+            store_elem<PAIRS, kSentinel>(a, base + merge_index<L, L - 4>(t, r), e[r]);
+    } else {
+        const bool below_n = base + (1u << L) <= a.n;
+#pragma unroll
+        for (int r = 0; r < kMergeE; ++r) {
+            const uint32_t p = base + merge_index<L, L - 4>(t, r);
+            if (below_n)
+                store_elem<PAIRS, kPlain>(a, p, e[r]);
+            else
+                store_elem<PAIRS, kTail>(a, p, e[r]);
+        }
+    }
+}
+
+template <bool PAIRS, int L>
+__global__ __launch_bounds__(1 << (L - 4)) void bitonic_merge_regs_kernel(SortArray a, uint32_t m,
+                                                                          int mode,
+                                                                          int32_t nsteps) {
+    using E = typename ElemOf<PAIRS>::type;
+    constexpr uint32_t T = 1u << L;
+    extern __shared__ __align__(16) unsigned char smem[];
+    E *s = reinterpret_cast<E *>(smem);
+    const uint32_t t = threadIdx.x;
+    const uint32_t base = blockIdx.x * T;
+    const bool up = ((base >> m) & 1u) == 0;
+
+    E e[kMergeE];
+    regs_load<PAIRS, L>(a, base, t, mode, e);
+    if (0 < nsteps) merge_reg_step<3>(e, up);  // element bit L-1
+    if (1 < nsteps) merge_reg_step<2>(e, up);  // element bit L-2
+    merge_windows<L, 1, -1>(e, s, t, up, nsteps);
+    regs_store<PAIRS, L>(a, s, base, t, mode, e);
+}
+
+// One register step on register bit Q in the two forms of the direction
+// region. Divergent: Figure 1's if/else on the direction, each side with its
+// own compare and conditional swap (the marks keep the sides apart). Melded:
+// both compares, the swap chosen by a select on the direction.
+template <int Q, bool MELDED, typename E>
+__device__ __forceinline__ void reg_step_form(E (&e)[kMergeE], bool up) {
+    if constexpr (MELDED) {
+        merge_reg_step<Q>(e, up);
+    } else {
+        if (up) {
+            MELD_SIDE_MARK("ascending regs");
+#pragma unroll
+            for (int r = 0; r < kMergeE; ++r)
+                if ((r & (1 << Q)) == 0) {
+                    const E x = e[r], y = e[r | (1 << Q)];
+                    if (y < x) {
+                        e[r] = y;
+                        e[r | (1 << Q)] = x;
+                    }
+                }
+        } else {
+            MELD_SIDE_MARK("descending regs");
+#pragma unroll
+            for (int r = 0; r < kMergeE; ++r)
+                if ((r & (1 << Q)) == 0) {
+                    const E x = e[r], y = e[r | (1 << Q)];
+                    if (y > x) {
+                        e[r] = y;
+                        e[r | (1 << Q)] = x;
+                    }
+                }
+        }
+    }
+}
+
+// Steps on register bits hi_q .. 0 of the current window, while steps are left.
+template <bool MELDED, typename E>
+__device__ __forceinline__ void reg_steps(E (&e)[kMergeE], int hi_q, bool up, int32_t &left) {
+    if (hi_q >= 3 && left > 0) {
+        reg_step_form<3, MELDED>(e, up);
+        --left;
+    }
+    if (hi_q >= 2 && left > 0) {
+        reg_step_form<2, MELDED>(e, up);
+        --left;
+    }
+    if (hi_q >= 1 && left > 0) {
+        reg_step_form<1, MELDED>(e, up);
+        --left;
+    }
+    if (left > 0) {
+        reg_step_form<0, MELDED>(e, up);
+        --left;
+    }
+}
+
+// The whole network of a tile of T = 2^L elements (phases k = 2 .. T; the
+// last one's direction is bit L of the tile's base).
+//
+// Phases k <= 64 run as the LDS comparator network, one comparator per lane
+// per iteration (Figure 1's mapping), in form MELD_LO: their direction is a
+// lane bit of the comparator index.
+//
+// Phases k = 2^m >= 128 run in register windows: for phase m the windows
+// have bases m-4, m-8, ... (clamped at 0), each taking four of the steps on
+// bits m-1 .. 0. In window B element bit m (>= B+4) is thread bit m-4, so
+// the direction is the same for all of a thread's elements and, for m <= 9,
+// differs between the lanes of a wave: form MELD_HI decides how that region
+// runs.
+template <bool PAIRS, int L, bool MELD_LO, bool MELD_HI>
+__global__ __launch_bounds__(1 << (L - 4)) void bitonic_sort_regs_kernel(SortArray a, int mode,
+                                                                         int32_t step_limit) {
+    using E = typename ElemOf<PAIRS>::type;
+    constexpr uint32_t NT = 1u << (L - 4);
+    constexpr uint32_t T = 1u << L;
+    extern __shared__ __align__(16) unsigned char smem[];
+    E *s = reinterpret_cast<E *>(smem);
+    const uint32_t t = threadIdx.x;
+    const uint32_t base = blockIdx.x * T;
+
+    E e[kMergeE];
+    regs_load<PAIRS, L>(a, base, t, mode, e);
+#pragma unroll
+    for (int r = 0; r < kMergeE; ++r) s[merge_index<L, -1>(t, r)] = e[r];  // natural order
+    __syncthreads();
+    const int32_t lo_steps =
+        lds_network<E, MELD_LO, MELD_LO, NT, true>(s, T, base, 1, 6, 0, step_limit, t);
+    __syncthreads();
+    int32_t left = step_limit < 0 ? 0x7FFFFFFF : step_limit - lo_steps;
+
+    bool natural = true;  // e's values still sit in s in natural order
+    uint32_t prev = 0;
+    for (uint32_t m = 7; m <= (uint32_t)L; ++m) {
+        const bool up = (((base >> m) | (t >> (m - 4))) & 1u) == 0;
+        for (uint32_t w = 1;; ++w) {
+            const uint32_t B = m > 4 * w ? m - 4 * w : 0;
+            const int hi_q = (int)(m - 4 * (w - 1) - 1 - B);
+            const uint32_t tb = window_tpart(t, B);
+            if (natural) {
+#pragma unroll
+                for (int r = 0; r < kMergeE; ++r) e[r] = s[tb | ((uint32_t)r << B)];
+                __syncthreads();
+                natural = false;
+            } else {
+                const uint32_t tp = window_tpart(t, prev);
+#pragma unroll
+                for (int r = 0; r < kMergeE; ++r) s[merge_phys(tp | ((uint32_t)r << prev))] = e[r];
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < kMergeE; ++r) e[r] = s[merge_phys(tb | ((uint32_t)r << B))];
+                __syncthreads();
+            }
+            reg_steps<MELD_HI>(e, hi_q, up, left);
+            prev = B;
+            if (B == 0) break;
+        }
+    }
+    regs_store<PAIRS, L>(a, s, base, t, mode, e);
+}
+
+template <bool PAIRS, int L>
+size_t regs_lds_bytes() {
+    using E = typename ElemOf<PAIRS>::type;
+    return (size_t)((1u << L) + (1u << L) / 16) * sizeof(E);
+}
+
+template <typename K>
+hipError_t allow_lds(K kern, size_t lds) {
+    if (lds <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <bool PAIRS, int L>
+hipError_t launch_merge_l(const SortArray &a, uint32_t n_tiles, uint32_t m, int32_t nsteps,
+                          int io_mode, hipStream_t stream) {
+    const size_t lds = regs_lds_bytes<PAIRS, L>();
+    auto kern = bitonic_merge_regs_kernel<PAIRS, L>;
+    hipError_t e = allow_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(n_tiles), dim3(1u << (L - 4)), lds, stream, a, m, io_mode,
+                       nsteps);
+    return hipGetLastError();
+}
+
+template <bool PAIRS, int L, bool LO, bool HI>
+hipError_t launch_sort_regs_f(const SortArray &a, uint32_t n_tiles, int32_t step_limit,
+                              int io_mode, hipStream_t stream) {
+    const size_t lds = regs_lds_bytes<PAIRS, L>();
+    auto kern = bitonic_sort_regs_kernel<PAIRS, L, LO, HI>;
+    hipError_t e = allow_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(n_tiles), dim3(1u << (L - 4)), lds, stream, a, io_mode,
+                       step_limit);
+    return hipGetLastError();
+}
+
+template <bool PAIRS, int L>
+hipError_t launch_sort_regs_l(const SortArray &a, uint32_t n_tiles, int32_t step_limit, bool lo,
+                              bool hi, int io_mode, hipStream_t stream) {
+    if (lo)
+        return hi ? launch_sort_regs_f<PAIRS, L, true, true>(a, n_tiles, step_limit, io_mode, stream)
+                  : launch_sort_regs_f<PAIRS, L, true, false>(a, n_tiles, step_limit, io_mode,
+                                                              stream);
+    return hi ? launch_sort_regs_f<PAIRS, L, false, true>(a, n_tiles, step_limit, io_mode, stream)
+              : launch_sort_regs_f<PAIRS, L, false, false>(a, n_tiles, step_limit, io_mode, stream);
+}
+
+#define MELD_REGS_SIZES(X) X(8) X(9) X(10) X(11) X(12) X(13) X(14)
+
+template <bool PAIRS>
+hipError_t launch_merge_p(const SortArray &a, uint32_t log_t, uint32_t n_tiles, uint32_t m,
+                          int32_t nsteps, int io_mode, hipStream_t stream) {
+#define MELD_CASE(L) \
+    case L: return launch_merge_l<PAIRS, L>(a, n_tiles, m, nsteps, io_mode, stream);
+    switch (log_t) {
+        MELD_REGS_SIZES(MELD_CASE)
+        default: return hipErrorInvalidValue;
+    }
+#undef MELD_CASE
+}
+
+template <bool PAIRS>
+hipError_t launch_sort_regs_p(const SortArray &a, uint32_t log_t, uint32_t n_tiles,
+                              int32_t step_limit, bool lo, bool hi, int io_mode,
+                              hipStream_t stream) {
+#define MELD_CASE(L) \
+    case L: return launch_sort_regs_l<PAIRS, L>(a, n_tiles, step_limit, lo, hi, io_mode, stream);
+    switch (log_t) {
+        MELD_REGS_SIZES(MELD_CASE)
+        default: return hipErrorInvalidValue;
+    }
+#undef MELD_CASE
+}
+
 constexpr int kGlobalThreads = 256;
 
 template <bool PAIRS, int R, int MODE>
@@ -346,6 +722,27 @@ hipError_t launch_bitonic_global(const SortArray &a, uint32_t log_n, uint32_t m,
                     : launch_global_p<true, kPlain>(a, log_n, m, b_hi, b_lo, step_limit, stream);
     return tail ? launch_global_p<false, kTail>(a, log_n, m, b_hi, b_lo, step_limit, stream)
                 : launch_global_p<false, kPlain>(a, log_n, m, b_hi, b_lo, step_limit, stream);
+}
+
+hipError_t launch_bitonic_sort_regs(const SortArray &a, uint32_t log_t, uint32_t n_tiles,
+                                    int32_t step_limit, bool meld_lo, bool meld_hi, int io_mode,
+                                    hipStream_t stream) {
+    if (n_tiles == 0 || step_limit == 0) return hipSuccess;
+    if (io_mode == kPlain) io_mode = kTail;  // no tail workspace: every tile is below n
+    if (a.vals != nullptr)
+        return launch_sort_regs_p<true>(a, log_t, n_tiles, step_limit, meld_lo, meld_hi, io_mode,
+                                        stream);
+    return launch_sort_regs_p<false>(a, log_t, n_tiles, step_limit, meld_lo, meld_hi, io_mode,
+                                     stream);
+}
+
+hipError_t launch_bitonic_merge(const SortArray &a, uint32_t log_t, uint32_t n_tiles, uint32_t m,
+                                int32_t step_limit, int io_mode, hipStream_t stream) {
+    if (n_tiles == 0 || step_limit == 0) return hipSuccess;
+    if (io_mode == kPlain) io_mode = kTail;
+    const int32_t nsteps = step_limit < 0 ? (int32_t)log_t : step_limit;
+    if (a.vals != nullptr) return launch_merge_p<true>(a, log_t, n_tiles, m, nsteps, io_mode, stream);
+    return launch_merge_p<false>(a, log_t, n_tiles, m, nsteps, io_mode, stream);
 }
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t count, hipStream_t stream) {

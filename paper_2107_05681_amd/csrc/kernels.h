@@ -45,6 +45,20 @@ hipError_t launch_bitonic_tile(const SortArray &a, uint32_t log_t, uint32_t n_ti
                                int32_t step_limit, bool meld_lo, bool meld_hi, int io_mode,
                                int threads, hipStream_t stream);
 
+// The whole network of every tile of 2^log_t elements (log_t in 8..14):
+// phases k <= 64 as the LDS comparator network in form meld_lo, phases
+// k >= 128 in register windows in form meld_hi. io_mode: plain, vector, tail
+// or sentinel. At most step_limit steps run (negative: all).
+hipError_t launch_bitonic_sort_regs(const SortArray &a, uint32_t log_t, uint32_t n_tiles,
+                                    int32_t step_limit, bool meld_lo, bool meld_hi, int io_mode,
+                                    hipStream_t stream);
+
+// Steps j = 2^(log_t-1) .. 1 of phase k = 2^m > 2^log_t on every tile, in
+// registers with LDS transposes (log_t in 8..14; io_mode plain, vector or
+// tail). At most step_limit steps run (negative: all).
+hipError_t launch_bitonic_merge(const SortArray &a, uint32_t log_t, uint32_t n_tiles, uint32_t m,
+                                int32_t step_limit, int io_mode, hipStream_t stream);
+
 // One streaming pass over all N = 2^log_n elements for the steps
 // j = 2^b_hi .. 2^b_lo of phase k = 2^m (b_hi - b_lo + 1 <= kMaxFusedSteps),
 // all in registers. At most step_limit steps run (negative: all).
@@ -67,8 +81,11 @@ hipError_t launch_gen_tab(float *tab, uint32_t m, uint64_t seed, hipStream_t s);
 hipError_t launch_probe_region(uint32_t n, uint64_t seed, uint64_t thr, unsigned long long *out,
                                hipStream_t stream);
 // One tile of 2^log_t: out[2(m-1)] mixed comparator-waves of phase 2^m,
-// out[2(m-1)+1] comparator-waves of that phase (over all its steps).
-hipError_t launch_probe_network(uint32_t log_t, unsigned long long *out, hipStream_t stream);
+// out[2(m-1)+1] comparator-waves of that phase (over all its steps); regs:
+// phases k >= 128 under the register-window mapping (2^(log_t-4) threads,
+// direction = thread bit m-4).
+hipError_t launch_probe_network(uint32_t log_t, bool regs, unsigned long long *out,
+                                hipStream_t stream);
 // Segments: out[0..1] mixed / all comparator-steps of the phases k <= 64,
 // out[2..3] the same for k >= 128.
 hipError_t launch_probe_segments(const uint32_t *off, uint32_t nseg, unsigned long long *out,

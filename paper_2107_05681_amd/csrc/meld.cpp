@@ -43,6 +43,7 @@ struct meld_ctx {
     std::list<SegGraph> seg_graphs;
     hipStream_t capture_stream = nullptr;
     bool use_graphs = true;
+    uint32_t sort_log_tile = 0;  // 0: chosen per call
     // Tuner: decisions per shape class, scratch for timed trials on copies of
     // the caller's data, and device counters for the divergence probes.
     meld::Tuner tuner;
@@ -334,8 +335,8 @@ meld_status segmented_impl(meld_ctx *ctx, uint32_t *keys, const uint32_t *offset
     return MELD_OK;
 }
 
-// Threads per workgroup for a tile of 2^log_t elements: one comparator per
-// lane per iteration, at most 512 lanes.
+// Threads per workgroup of the LDS-only tile kernel (tiles below 2^8): one
+// comparator per lane per iteration.
 int tile_threads(uint32_t log_t) {
     if (log_t <= 7) return 64;
     if (log_t <= 9) return 256;
@@ -350,7 +351,24 @@ struct SortPlan {
     bool lo, hi;
 };
 
+constexpr uint32_t kMinLogRegsTile = 8;  // smallest tile of the register-window kernels
+
 uint32_t max_log_tile(bool pairs) { return pairs ? meld::kMaxLogTilePairs : meld::kMaxLogTileKeys; }
+
+// Tile size without timing, from a sweep of 2^14 .. 2^28 elements on
+// gfx950: 2^11 while the array is small (more tiles spread over the chip
+// and one tile's sort stays short), larger tiles (fewer streaming passes)
+// from 2^20 elements on.
+uint32_t default_log_tile(bool pairs, uint32_t log_n) {
+    uint32_t t;
+    if (log_n <= 19)
+        t = 11;
+    else if (log_n <= 21)
+        t = 12;
+    else
+        t = pairs ? (log_n <= 25 ? 12 : 13) : 14;
+    return std::max(kMinLogRegsTile, std::min(t, max_log_tile(pairs)));
+}
 
 // Enqueues the whole network (or its first step_limit steps) on keys[0..n).
 meld_status sort_impl(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n,
@@ -370,17 +388,23 @@ meld_status sort_impl(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n
 
     hipError_t e;
     if (log_n <= plan.log_t) {
-        // One tile holds everything; positions >= n are sentinels in LDS.
+        // One tile holds everything; positions >= n are sentinels.
         const uint32_t log_t = std::max<uint32_t>(log_n, 1);
         const int io = big_n > n ? meld::kIoSentinel
                        : (aligned16(keys) && (!pairs || aligned16(payload))) ? meld::kIoPlainVec
                                                                              : meld::kIoPlain;
-        e = meld::launch_bitonic_tile(a, log_t, 1, 1, log_t, 0,
-                                      take((uint64_t)log_t * (log_t + 1) / 2), plan.lo, plan.hi,
-                                      io, tile_threads(log_t), stream);
+        const int32_t steps = take((uint64_t)log_t * (log_t + 1) / 2);
+        if (log_t >= kMinLogRegsTile)
+            e = meld::launch_bitonic_sort_regs(a, log_t, 1, steps, plan.lo, plan.hi, io, stream);
+        else
+            e = meld::launch_bitonic_tile(a, log_t, 1, 1, log_t, 0, steps, plan.lo, plan.hi, io,
+                                          tile_threads(log_t), stream);
         if (e != hipSuccess) return hip_fail(e, "bitonic tile launch");
         return MELD_OK;
     }
+    if (plan.log_t < kMinLogRegsTile || plan.log_t > max_log_tile(pairs))
+        return fail(MELD_EINVAL, "sort: tile 2^%u outside 2^%u .. 2^%u", plan.log_t,
+                    kMinLogRegsTile, max_log_tile(pairs));
 
     if (big_n > n) {
         const size_t pad = big_n - n;
@@ -394,13 +418,11 @@ meld_status sort_impl(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n
 
     const uint32_t log_t = plan.log_t;
     const uint32_t n_tiles = (uint32_t)(big_n >> log_t);
-    const int threads = tile_threads(log_t);
     const int io = a.tk != nullptr ? meld::kIoTail
                    : (aligned16(keys) && (!pairs || aligned16(payload))) ? meld::kIoPlainVec
                                                                          : meld::kIoPlain;
-    e = meld::launch_bitonic_tile(a, log_t, n_tiles, 1, log_t, 0,
-                                  take((uint64_t)log_t * (log_t + 1) / 2), plan.lo, plan.hi, io,
-                                  threads, stream);
+    e = meld::launch_bitonic_sort_regs(a, log_t, n_tiles, take((uint64_t)log_t * (log_t + 1) / 2),
+                                       plan.lo, plan.hi, io, stream);
     if (e != hipSuccess) return hip_fail(e, "bitonic tile launch");
 
     for (uint32_t m = log_t + 1; m <= log_n; ++m) {
@@ -417,17 +439,23 @@ meld_status sort_impl(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n
             if (e != hipSuccess) return hip_fail(e, "bitonic global launch");
             b_hi = b_lo - 1;
         }
-        // Steps j = 2^(log_t-1) .. 1 of phase m in LDS tiles.
-        e = meld::launch_bitonic_tile(a, log_t, n_tiles, m, m, log_t - 1, take(log_t), plan.lo,
-                                      plan.hi, io, threads, stream);
+        // Steps j = 2^(log_t-1) .. 1 of phase m: the direction is uniform per
+        // tile, both forms coincide; registers with LDS transposes.
+        e = meld::launch_bitonic_merge(a, log_t, n_tiles, m, take(log_t), io, stream);
         if (e != hipSuccess) return hip_fail(e, "bitonic merge launch");
     }
     return MELD_OK;
 }
 
-SortPlan fixed_plan(bool pairs, meld_variant v) {
+// The tile the context fixes (MELD_OPT_SORT_LOG_TILE), else the size rule.
+uint32_t plan_log_tile(const meld_ctx *ctx, bool pairs, uint32_t log_n) {
+    if (ctx->sort_log_tile != 0) return std::min(ctx->sort_log_tile, max_log_tile(pairs));
+    return default_log_tile(pairs, log_n);
+}
+
+SortPlan fixed_plan(const meld_ctx *ctx, bool pairs, size_t n, meld_variant v) {
     const bool m = use_melded(v);
-    return SortPlan{max_log_tile(pairs), m, m};
+    return SortPlan{plan_log_tile(ctx, pairs, log2_ceil(n)), m, m};
 }
 
 // Probe of one tile's network: mixed-wave fraction of the phases k <= 64 and
@@ -436,7 +464,7 @@ meld_status probe_network(meld_ctx *ctx, uint32_t log_t, hipStream_t s, double *
                           double *mixed_hi) {
     unsigned long long c[2 * 16] = {0};
     meld_status st = run_probe(ctx, s, 2 * log_t, c, [&](unsigned long long *out) {
-        return meld::launch_probe_network(log_t, out, s);
+        return meld::launch_probe_network(log_t, log_t >= kMinLogRegsTile, out, s);
     });
     if (st != MELD_OK) return st;
     unsigned long long ml = 0, al = 0, mh = 0, ah = 0;
@@ -455,19 +483,30 @@ meld_status auto_sort_plan(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, siz
                            hipStream_t s, SortPlan *out) {
     const bool pairs = payload != nullptr;
     const uint32_t log_n = log2_ceil(n);
-    const std::string key = fmt("n=%u pairs=%d", log_n, pairs ? 1 : 0);
-    if (const meld::TuneEntry *e = ctx->tuner.find("sort", key)) {
-        *out = SortPlan{(uint32_t)e->log_t, e->lo != 0, e->hi != 0};
-        return MELD_OK;
-    }
     const uint32_t max_t = max_log_tile(pairs);
-    *out = SortPlan{max_t, true, true};
+    const uint32_t forced = ctx->sort_log_tile ? std::min(ctx->sort_log_tile, max_t) : 0;
+    const std::string key = forced ? fmt("n=%u pairs=%d t=%u", log_n, pairs ? 1 : 0, forced)
+                                   : fmt("n=%u pairs=%d", log_n, pairs ? 1 : 0);
+    if (const meld::TuneEntry *e = ctx->tuner.find("sort", key)) {
+        const uint32_t t = (uint32_t)e->log_t;
+        if (t >= kMinLogRegsTile && t <= max_t) {
+            *out = SortPlan{t, e->lo != 0, e->hi != 0};
+            return MELD_OK;
+        }
+    }
+    *out = SortPlan{plan_log_tile(ctx, pairs, log_n), true, true};
     if (capturing(s)) return MELD_OK;  // no timing inside a capture; untuned default
+    // Candidate tiles: from one that leaves a few hundred tiles up to the
+    // largest (a single tile when everything fits); the forced one alone.
     std::vector<uint32_t> tiles;
-    if (log_n <= max_t)
-        tiles.push_back(max_t);
-    else
-        for (uint32_t t = max_t - 1; t <= max_t; ++t) tiles.push_back(t);
+    if (forced) {
+        tiles.push_back(forced);
+    } else {
+        const uint32_t hi_t = std::min(max_t, std::max(log_n, kMinLogRegsTile));
+        const int lo_want = std::min<int>((int)max_t - 1, (int)log_n - 10);
+        const uint32_t lo_t = std::min(hi_t, (uint32_t)std::max<int>((int)kMinLogRegsTile, lo_want));
+        for (uint32_t t = lo_t; t <= hi_t; ++t) tiles.push_back(t);
+    }
     const size_t words = pairs ? 2 * n : n;
     meld_status st = ensure_words(&ctx->tune_buf, &ctx->tune_words, words, "tuning scratch");
     if (st != MELD_OK) return st;
@@ -712,7 +751,7 @@ meld_status meld_sort_u32(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size
         return fail(MELD_EINVAL, "meld_sort_u32: payload is not a device pointer on device %d",
                     ctx->device);
     const hipStream_t s = static_cast<hipStream_t>(stream);
-    SortPlan plan = fixed_plan(payload != nullptr, variant);
+    SortPlan plan = fixed_plan(ctx, payload != nullptr, n, variant);
     if (variant == MELD_AUTO) {
         meld_status st = auto_sort_plan(ctx, keys, payload, n, s, &plan);
         if (st != MELD_OK) return st;
@@ -731,8 +770,8 @@ meld_status meld_sort_u32_steps(meld_ctx *ctx, uint32_t *keys, uint32_t *payload
     if (!is_device_ptr(ctx, keys) || (payload != nullptr && !is_device_ptr(ctx, payload)))
         return fail(MELD_EINVAL, "meld_sort_u32_steps: arrays must be device pointers");
     if (max_steps < 0) max_steps = -1;
-    return sort_impl(ctx, keys, payload, n, fixed_plan(payload != nullptr, variant), max_steps,
-                     static_cast<hipStream_t>(stream));
+    return sort_impl(ctx, keys, payload, n, fixed_plan(ctx, payload != nullptr, n, variant),
+                     max_steps, static_cast<hipStream_t>(stream));
 }
 
 meld_status meld_divergent_region_f32(meld_ctx *ctx, const float *x, float *y, size_t n,
@@ -852,7 +891,7 @@ meld_status meld_probe_network(meld_ctx *ctx, uint32_t log_t, uint64_t *out, voi
     unsigned long long c[32] = {0};
     const hipStream_t s = static_cast<hipStream_t>(stream);
     meld_status st = run_probe(ctx, s, 2 * log_t, c, [&](unsigned long long *o) {
-        return meld::launch_probe_network(log_t, o, s);
+        return meld::launch_probe_network(log_t, false, o, s);
     });
     for (uint32_t i = 0; i < 2 * log_t; ++i) out[i] = c[i];
     return st;
@@ -882,6 +921,12 @@ meld_status meld_set_option(meld_ctx *ctx, meld_option option, int64_t value) {
     switch (option) {
         case MELD_OPT_USE_GRAPHS:
             ctx->use_graphs = value != 0;
+            return MELD_OK;
+        case MELD_OPT_SORT_LOG_TILE:
+            if (value != 0 && (value < (int64_t)kMinLogRegsTile || value > meld::kMaxLogTileKeys))
+                return fail(MELD_EINVAL, "meld_set_option: sort tile 2^%lld outside 2^%u .. 2^%d",
+                            (long long)value, kMinLogRegsTile, meld::kMaxLogTileKeys);
+            ctx->sort_log_tile = (uint32_t)value;
             return MELD_OK;
         default:
             return fail(MELD_EINVAL, "meld_set_option: unknown option %d", (int)option);

@@ -44,8 +44,11 @@ __global__ __launch_bounds__(256) void probe_region_kernel(uint32_t n, uint64_t 
 // c = 64 * wave + l for every comparator-wave of the step, evaluates the
 // direction bit m of lo = c with a zero inserted at bit j, and counts the
 // comparator-waves whose direction mask is mixed.
+// With regs set, phases m >= 7 follow the register-window mapping instead:
+// 2^(log_t-4) threads, thread t's direction is its bit m-4, and every step of
+// the phase counts each wave of threads once.
 // out[2*(m-1)] += mixed comparator-waves, out[2*(m-1)+1] += comparator-waves.
-__global__ __launch_bounds__(64) void probe_network_kernel(uint32_t log_t,
+__global__ __launch_bounds__(64) void probe_network_kernel(uint32_t log_t, int regs,
                                                            unsigned long long *out) {
     const uint32_t m = blockIdx.x + 1;     // phase k = 2^m, m = 1 .. log_t
     const uint32_t jb = blockIdx.y;        // step j = 2^jb, jb < m
@@ -54,6 +57,23 @@ __global__ __launch_bounds__(64) void probe_network_kernel(uint32_t log_t,
     const uint32_t half = 1u << (log_t - 1);
     const uint32_t lane = __lane_id();
     unsigned long long mixed = 0, waves = 0;
+    if (regs && m >= 7) {
+        const uint32_t nt = 1u << (log_t - 4);
+        for (uint32_t t0 = 0; t0 < nt; t0 += 64) {
+            const uint32_t t = t0 + lane;
+            const bool active = t < nt;
+            const bool up = active && ((t >> (m - 4)) & 1u) == 0;
+            const uint64_t mu = __ballot(up);
+            const uint64_t ma = __ballot(active);
+            mixed += (mu != 0 && mu != ma) ? 1 : 0;
+            waves += 1;
+        }
+        if (lane == 0) {
+            atomicAdd(&out[2 * (m - 1)], mixed);
+            atomicAdd(&out[2 * (m - 1) + 1], waves);
+        }
+        return;
+    }
     for (uint32_t c0 = 0; c0 < half; c0 += 64) {
         const uint32_t c = c0 + lane;
         const bool active = c < half;
@@ -124,9 +144,11 @@ hipError_t launch_probe_region(uint32_t n, uint64_t seed, uint64_t thr, unsigned
     return hipGetLastError();
 }
 
-hipError_t launch_probe_network(uint32_t log_t, unsigned long long *out, hipStream_t stream) {
+hipError_t launch_probe_network(uint32_t log_t, bool regs, unsigned long long *out,
+                                hipStream_t stream) {
     if (log_t == 0) return hipSuccess;
-    hipLaunchKernelGGL(probe_network_kernel, dim3(log_t, log_t), dim3(64), 0, stream, log_t, out);
+    hipLaunchKernelGGL(probe_network_kernel, dim3(log_t, log_t), dim3(64), 0, stream, log_t,
+                       regs ? 1 : 0, out);
     return hipGetLastError();
 }
 

@@ -148,3 +148,77 @@ def test_sort_rejects_host_pointer():
     st = lib.meld_sort_u32(meld.context(0), ctypes.cast(host, ctypes.c_void_p), None, 64, 1, None)
     assert st == meld.EINVAL
     assert b"device pointer" in lib.meld_last_error()
+
+
+@pytest.fixture
+def tile_option():
+    """Restores the automatic sort tile after a test that forces one."""
+    yield lambda t: meld.set_option(0, meld.OPT_SORT_LOG_TILE, t)
+    meld.set_option(0, meld.OPT_SORT_LOG_TILE, 0)
+
+
+@pytest.mark.parametrize("log_t", [8, 9, 10, 11, 12, 13, 14])
+def test_sort_every_tile_size(log_t, tile_option):
+    _dev()
+    tile_option(log_t)
+    # several tiles with a ragged tail, and one padded tile
+    for n in ((1 << (log_t + 3)) + 17, (1 << log_t) - 5):
+        keys = workloads.keys_u32(100 + log_t, n)
+        ref = oracle.sort_u32(keys)
+        vals = workloads.iota_u32(n)
+        rk, rv = oracle.sort_pairs_u32(keys, vals)
+        for v in VARIANTS:
+            got, _ = _gpu_sort(keys, None, v)
+            assert np.array_equal(got, ref), (log_t, n, v)
+            gk, gv = _gpu_sort(keys, vals, v)
+            assert np.array_equal(gk, rk) and np.array_equal(gv, rv), (log_t, n, v)
+
+
+@pytest.mark.parametrize("log_t,log_n,pairs", [(8, 12, False), (8, 11, True), (11, 13, True)])
+def test_stage_parity_small_tiles(log_t, log_n, pairs, tile_option):
+    # Every step prefix, with tiles forced small so that the register-window
+    # phases, the merges and the streaming passes all take part.
+    _dev()
+    tile_option(log_t)
+    n = 1 << log_n
+    keys = workloads.keys_u32(200 + log_n, n)
+    vals = workloads.iota_u32(n) if pairs else None
+    total = oracle.bitonic_num_steps(n)
+    for s in range(1, total + 1):
+        ref = oracle.bitonic_emulate(keys, vals, max_steps=s)
+        for v in VARIANTS:
+            kd = _to_dev(keys)
+            vd = None if vals is None else _to_dev(vals)
+            meld.sort_steps(kd, vd, max_steps=s, variant=v)
+            torch.cuda.synchronize()
+            if pairs:
+                assert np.array_equal(_to_host(kd), ref[0]) and \
+                    np.array_equal(_to_host(vd), ref[1]), (s, v)
+            else:
+                assert np.array_equal(_to_host(kd), ref), (s, v)
+
+
+@pytest.mark.parametrize("n", [1 << 12, (1 << 15) + 9])
+def test_sort_unaligned_arrays(n):
+    # Views one element into their buffers: not 16-byte aligned, so the
+    # per-element load and store paths run.
+    keys = workloads.keys_u32(300, n)
+    vals = workloads.iota_u32(n)
+    rk, rv = oracle.sort_pairs_u32(keys, vals)
+    for v in VARIANTS:
+        kb = _to_dev(np.concatenate([[0], keys]).astype(np.uint32))
+        vb = _to_dev(np.concatenate([[0], vals]).astype(np.uint32))
+        kd, vd = kb[1:], vb[1:]
+        assert kd.data_ptr() % 16 != 0
+        meld.sort(kd, vd, variant=v)
+        torch.cuda.synchronize()
+        assert np.array_equal(_to_host(kd), rk) and np.array_equal(_to_host(vd), rv), (n, v)
+        assert _to_host(kb)[0] == 0 and _to_host(vb)[0] == 0
+
+
+def test_sort_tile_option_rejects_out_of_range(tile_option):
+    _dev()
+    for bad in (1, 7, 15, -1):
+        with pytest.raises(meld.MeldError):
+            tile_option(bad)
+    tile_option(0)

@@ -104,3 +104,19 @@ def test_region_melded_inplace_has_no_side_blocks(region_asm):
     body = _kernel(region_asm, r"region_melded_inplace_kernel")
     assert "; side" not in body
     assert "v_cndmask_b32" in body and "global_load_dword" in body
+
+
+@pytest.mark.parametrize("pairs", [False, True])
+def test_register_phases_divergent_vs_melded(bitonic_asm, pairs):
+    # Phases k >= 128 of the tile sort run in registers: the divergent form
+    # keeps Figure 1's two sides (one per direction), the melded one has none.
+    p = "b1" if pairs else "b0"
+    div = _kernel(bitonic_asm, rf"bitonic_sort_regs_kernelIL{p}ELi13ELb0ELb0E")
+    mel = _kernel(bitonic_asm, rf"bitonic_sort_regs_kernelIL{p}ELi13ELb1ELb1E")
+    width = "u64" if pairs else "u32"
+    for side in ("ascending regs\n", "descending regs\n"):
+        blocks = _blocks_after(div, side)
+        assert blocks, side
+        assert re.search(rf"v_cmp_[lg]t_{width}", blocks[0]), side
+    assert "; side" not in mel
+    assert re.search(rf"v_cmp_lt_{width}", mel) and "v_cndmask_b32" in mel
