@@ -132,8 +132,9 @@ meld_status meld_sort_u32_steps(meld_ctx *ctx, uint32_t *keys, uint32_t *payload
  * nseg:    number of segments, < 2^31; 0 is a no-op.
  * Runs as one persistent launch after three small planning kernels that
  * build a largest-first work queue on the device; nothing is read back to
- * the host. Scratch: 17 bytes per segment plus 128 KiB per CU, owned by the
- * context.
+ * the host. Scratch: 5 bytes per segment plus 256 KiB per resident
+ * workgroup (one per CU) for staging segments of more than 2^14 keys, owned
+ * by the context.
  * Errors:  MELD_EINVAL for NULL/host pointers. Offsets live on the device
  *          and are not inspected on the host: a segment longer than 65536,
  *          decreasing offsets or offsets[0] != 0 leave the keys untouched
@@ -144,10 +145,12 @@ meld_status meld_segmented_sort_u32(meld_ctx *ctx, uint32_t *keys, const uint32_
                                     size_t nseg, meld_variant variant, void *stream);
 
 /* As meld_segmented_sort_u32, with the form chosen per stage: low_phases for
- * the phases k <= 64, whose direction bit is one of the six lane bits (the
- * direction branch is divergent inside a wave), high_phases for the phases
- * k >= 128 (direction uniform per wave). Used by the tuner and for
- * per-stage measurements. MELD_AUTO counts as MELD_MELDED here. */
+ * the phases k <= 64, run one comparator per lane in LDS, whose direction
+ * bit is one of the lane bits (the direction branch is divergent inside a
+ * wave); high_phases for the phases k >= 128, run 16 keys per lane in
+ * registers, whose direction is a lane bit for k <= 512 and uniform per wave
+ * above. Used by the tuner and for per-stage measurements. MELD_AUTO counts
+ * as MELD_MELDED here. */
 meld_status meld_segmented_sort_u32_staged(meld_ctx *ctx, uint32_t *keys, const uint32_t *offsets,
                                            size_t nseg, meld_variant low_phases,
                                            meld_variant high_phases, void *stream);

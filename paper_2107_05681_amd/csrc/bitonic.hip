@@ -218,10 +218,24 @@ __device__ __forceinline__ uint32_t merge_index(uint32_t t, uint32_t r) {
 
 __device__ __forceinline__ uint32_t merge_phys(uint32_t i) { return i + (i >> 4); }
 
-// Base bit of window w >= 1.
-template <int L>
-constexpr int merge_window_base(int w) {
-    return L - 2 - 4 * w > 0 ? L - 2 - 4 * w : 0;
+// Windows of a pass whose steps stop at element bit SLO: base bit and top
+// step bit of window w >= 1; the last layout is the last window that holds a
+// step (-1, layout V, when V's two steps are all).
+template <int L, int SLO>
+constexpr int window_base(int w) {
+    return L - 2 - 4 * w > SLO ? L - 2 - 4 * w : SLO;
+}
+
+template <int L, int SLO>
+constexpr int window_top(int w) {
+    return w == 1 ? L - 3 : window_base<L, SLO>(w - 1) - 1;
+}
+
+template <int L, int SLO>
+constexpr int last_layout() {
+    int last = -1;
+    for (int w = 1; window_top<L, SLO>(w) >= SLO; ++w) last = window_base<L, SLO>(w);
+    return last;
 }
 
 template <int L, int FROM, int TO, typename E>
@@ -243,7 +257,7 @@ __device__ __forceinline__ void merge_reg_step(E (&e)[kMergeE], bool up) {
 }
 
 // Steps on element bits TOP .. B of window B (register bit = element bit - B);
-// the step on element bit i is number L-1-i of the merge (0-based).
+// the step on element bit i is number L-1-i of the pass (0-based).
 template <int L, int B, int BIT, typename E>
 __device__ __forceinline__ void merge_window_steps(E (&e)[kMergeE], bool up, int32_t nsteps) {
     if constexpr (BIT >= B) {
@@ -252,16 +266,33 @@ __device__ __forceinline__ void merge_window_steps(E (&e)[kMergeE], bool up, int
     }
 }
 
-// Window w (w >= 1) and the ones after it; PREV is the layout e is in.
-template <int L, int W, int PREV, typename E>
+// Window w (w >= 1) and the ones after it, down to step bit SLO; PREV is the
+// layout e is in.
+template <int L, int W, int PREV, int SLO, typename E>
 __device__ __forceinline__ void merge_windows(E (&e)[kMergeE], E *s, uint32_t t, bool up,
                                               int32_t nsteps) {
-    constexpr int B = merge_window_base<L>(W);
-    constexpr int TOP = W == 1 ? L - 3 : merge_window_base<L>(W - 1) - 1;
-    merge_transpose<L, PREV, B>(e, s, t);
-    merge_window_steps<L, B, TOP>(e, up, nsteps);
-    if constexpr (B > 0) merge_windows<L, W + 1, B>(e, s, t, up, nsteps);
+    constexpr int B = window_base<L, SLO>(W);
+    constexpr int TOP = window_top<L, SLO>(W);
+    if constexpr (TOP >= SLO) {
+        merge_transpose<L, PREV, B>(e, s, t);
+        merge_window_steps<L, B, TOP>(e, up, nsteps);
+        merge_windows<L, W + 1, B, SLO>(e, s, t, up, nsteps);
+    }
 }
+
+// Where element i of a tile lives in the array: its low C bits stay, the
+// bits above C move up to start at bit b_lo, and base holds the workgroup's
+// other bits. C = L is a contiguous tile at base.
+template <int L, int C>
+struct TileMap {
+    uint32_t base, b_lo;
+    __device__ __forceinline__ uint32_t operator()(uint32_t i) const {
+        if constexpr (C >= L)
+            return base | i;
+        else
+            return base | (i & ((1u << C) - 1)) | ((i >> C) << b_lo);
+    }
+};
 
 // Runtime layout index: window B (element bits [B, B+4) are the register
 // index) for a B known only at run time.
@@ -269,18 +300,18 @@ __device__ __forceinline__ uint32_t window_tpart(uint32_t t, uint32_t B) {
     return (t & ((1u << B) - 1)) | ((t >> B) << (B + 4));
 }
 
-// Thread t's 16 elements of the tile at base in layout V. Modes: vector
-// (16-byte groups), sentinel (positions >= n read as the pad value), plain or
-// tail (positions >= n from the tail workspace; a tile wholly below n loads
-// directly).
-template <bool PAIRS, int L>
-__device__ __forceinline__ void regs_load(const SortArray &a, uint32_t base, uint32_t t, int mode,
-                                          typename ElemOf<PAIRS>::type (&e)[kMergeE]) {
+// Thread t's 16 elements of a tile in layout V (C >= 2, so each 16-byte
+// group is contiguous in the array). Modes: vector (16-byte groups),
+// sentinel (positions >= n read as the pad value), plain or tail (positions
+// >= n from the tail workspace; a tile wholly below n loads directly).
+template <bool PAIRS, int L, int C>
+__device__ __forceinline__ void regs_load(const SortArray &a, const TileMap<L, C> &map, uint32_t t,
+                                          int mode, typename ElemOf<PAIRS>::type (&e)[kMergeE]) {
     using E = typename ElemOf<PAIRS>::type;
     if (mode == kPlainVec) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            const uint32_t p = base + merge_index<L, -1>(t, 4 * c);
+            const uint32_t p = map(merge_index<L, -1>(t, 4 * c));
             const uint4 k = *reinterpret_cast<const uint4 *>(a.keys + p);
             if constexpr (PAIRS) {
                 const uint4 v = *reinterpret_cast<const uint4 *>(a.vals + p);
@@ -298,28 +329,28 @@ __device__ __forceinline__ void regs_load(const SortArray &a, uint32_t base, uin
     } else if (mode == kSentinel) {
 #pragma unroll
         for (int r = 0; r < kMergeE; ++r)
-            e[r] = load_elem<PAIRS, kSentinel>(a, base + merge_index<L, -1>(t, r));
+            e[r] = load_elem<PAIRS, kSentinel>(a, map(merge_index<L, -1>(t, r)));
     } else {
-        const bool below_n = base + (1u << L) <= a.n;  // uniform per workgroup
+        const bool below_n = map((1u << L) - 1) < a.n;  // the map is increasing
 #pragma unroll
         for (int r = 0; r < kMergeE; ++r) {
-            const uint32_t p = base + merge_index<L, -1>(t, r);
+            const uint32_t p = map(merge_index<L, -1>(t, r));
             e[r] = below_n ? load_elem<PAIRS, kPlain>(a, p) : load_elem<PAIRS, kTail>(a, p);
         }
     }
 }
 
-// Stores the tile from window 0: through layout V with 16-byte stores, or
-// through window L-4 (consecutive lanes, consecutive elements) per element.
-template <bool PAIRS, int L>
+// Stores a tile held in layout FROM: through layout V with 16-byte stores,
+// or through window L-4 (consecutive lanes, consecutive elements) per element.
+template <bool PAIRS, int L, int C, int FROM>
 __device__ __forceinline__ void regs_store(const SortArray &a, typename ElemOf<PAIRS>::type *s,
-                                           uint32_t base, uint32_t t, int mode,
+                                           const TileMap<L, C> &map, uint32_t t, int mode,
                                            typename ElemOf<PAIRS>::type (&e)[kMergeE]) {
     if (mode == kPlainVec) {
-        merge_transpose<L, 0, -1>(e, s, t);
+        if constexpr (FROM != -1) merge_transpose<L, FROM, -1>(e, s, t);
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            const uint32_t p = base + merge_index<L, -1>(t, 4 * c);
+            const uint32_t p = map(merge_index<L, -1>(t, 4 * c));
             if constexpr (PAIRS) {
                 *reinterpret_cast<uint4 *>(a.keys + p) =
                     make_uint4((uint32_t)(e[4 * c] >> 32), (uint32_t)(e[4 * c + 1] >> 32),
@@ -334,16 +365,16 @@ __device__ __forceinline__ void regs_store(const SortArray &a, typename ElemOf<P
         }
         return;
     }
-    merge_transpose<L, 0, L - 4>(e, s, t);
+    merge_transpose<L, FROM, L - 4>(e, s, t);
     if (mode == kSentinel) {
 #pragma unroll
         for (int r = 0; r < kMergeE; ++r)
-            store_elem<PAIRS, kSentinel>(a, base + merge_index<L, L - 4>(t, r), e[r]);
+            store_elem<PAIRS, kSentinel>(a, map(merge_index<L, L - 4>(t, r)), e[r]);
     } else {
-        const bool below_n = base + (1u << L) <= a.n;
+        const bool below_n = map((1u << L) - 1) < a.n;
 #pragma unroll
         for (int r = 0; r < kMergeE; ++r) {
-            const uint32_t p = base + merge_index<L, L - 4>(t, r);
+            const uint32_t p = map(merge_index<L, L - 4>(t, r));
             if (below_n)
                 store_elem<PAIRS, kPlain>(a, p, e[r]);
             else
@@ -352,24 +383,32 @@ __device__ __forceinline__ void regs_store(const SortArray &a, typename ElemOf<P
     }
 }
 
-template <bool PAIRS, int L>
-__global__ __launch_bounds__(1 << (L - 4)) void bitonic_merge_regs_kernel(SortArray a, uint32_t m,
-                                                                          int mode,
-                                                                          int32_t nsteps) {
+// One pass of S steps (on element bits L-1 .. L-S of a tile of 2^L) of
+// phase k = 2^m, whose direction bit m lies above the tile's bits. Tile map
+// with C low bits: workgroup b's bits fill array bits [C, b_lo) and then
+// [b_lo + L - C, ...). Merge tail: S = C = L (contiguous tiles, b_lo = L).
+// Gathered streaming pass: C = L - S, so the steps act on array bits
+// b_lo .. b_lo + S - 1 and each of the 2^S rows is 2^C contiguous elements.
+template <bool PAIRS, int L, int S, int C>
+__global__ __launch_bounds__(1 << (L - 4)) void bitonic_pass_regs_kernel(SortArray a, uint32_t m,
+                                                                         uint32_t b_lo, int mode,
+                                                                         int32_t nsteps) {
     using E = typename ElemOf<PAIRS>::type;
-    constexpr uint32_t T = 1u << L;
     extern __shared__ __align__(16) unsigned char smem[];
     E *s = reinterpret_cast<E *>(smem);
     const uint32_t t = threadIdx.x;
-    const uint32_t base = blockIdx.x * T;
+    const uint32_t b = blockIdx.x;
+    const uint32_t spread = b_lo - C;
+    const uint32_t base = ((b & ((1u << spread) - 1)) << C) | ((b >> spread) << (b_lo + L - C));
+    const TileMap<L, C> map{base, b_lo};
     const bool up = ((base >> m) & 1u) == 0;
 
     E e[kMergeE];
-    regs_load<PAIRS, L>(a, base, t, mode, e);
-    if (0 < nsteps) merge_reg_step<3>(e, up);  // element bit L-1
-    if (1 < nsteps) merge_reg_step<2>(e, up);  // element bit L-2
-    merge_windows<L, 1, -1>(e, s, t, up, nsteps);
-    regs_store<PAIRS, L>(a, s, base, t, mode, e);
+    regs_load<PAIRS, L, C>(a, map, t, mode, e);
+    if (0 < nsteps) merge_reg_step<3>(e, up);                // element bit L-1
+    if (S >= 2 && 1 < nsteps) merge_reg_step<2>(e, up);      // element bit L-2
+    merge_windows<L, 1, -1, L - S>(e, s, t, up, nsteps);
+    regs_store<PAIRS, L, C, last_layout<L, L - S>()>(a, s, map, t, mode, e);
 }
 
 // One register step on register bit Q in the two forms of the direction
@@ -452,13 +491,13 @@ __global__ __launch_bounds__(1 << (L - 4)) void bitonic_sort_regs_kernel(SortArr
     const uint32_t t = threadIdx.x;
     const uint32_t base = blockIdx.x * T;
 
+    const TileMap<L, L> map{base, (uint32_t)L};
     E e[kMergeE];
-    regs_load<PAIRS, L>(a, base, t, mode, e);
+    regs_load<PAIRS, L, L>(a, map, t, mode, e);
 #pragma unroll
     for (int r = 0; r < kMergeE; ++r) s[merge_index<L, -1>(t, r)] = e[r];  // natural order
     __syncthreads();
-    const int32_t lo_steps =
-        lds_network<E, MELD_LO, MELD_LO, NT, true>(s, T, base, 1, 6, 0, step_limit, t);
+    const int32_t lo_steps = lds_network_low<E, MELD_LO, 8>(s, base, 6, t, NT, step_limit);
     __syncthreads();
     int32_t left = step_limit < 0 ? 0x7FFFFFFF : step_limit - lo_steps;
 
@@ -489,7 +528,7 @@ __global__ __launch_bounds__(1 << (L - 4)) void bitonic_sort_regs_kernel(SortArr
             if (B == 0) break;
         }
     }
-    regs_store<PAIRS, L>(a, s, base, t, mode, e);
+    regs_store<PAIRS, L, L, 0>(a, s, map, t, mode, e);
 }
 
 template <bool PAIRS, int L>
@@ -509,11 +548,33 @@ template <bool PAIRS, int L>
 hipError_t launch_merge_l(const SortArray &a, uint32_t n_tiles, uint32_t m, int32_t nsteps,
                           int io_mode, hipStream_t stream) {
     const size_t lds = regs_lds_bytes<PAIRS, L>();
-    auto kern = bitonic_merge_regs_kernel<PAIRS, L>;
+    auto kern = bitonic_pass_regs_kernel<PAIRS, L, L, L>;
     hipError_t e = allow_lds(kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(n_tiles), dim3(1u << (L - 4)), lds, stream, a, m, io_mode,
-                       nsteps);
+    hipLaunchKernelGGL(kern, dim3(n_tiles), dim3(1u << (L - 4)), lds, stream, a, m, (uint32_t)L,
+                       io_mode, nsteps);
+    return hipGetLastError();
+}
+
+// Gathered streaming pass of R steps over the whole array, in tiles of the
+// largest size of the element type (2^13 pairs, 2^14 keys: 64 KiB).
+template <bool PAIRS>
+constexpr int gather_log() {
+    return PAIRS ? kMaxLogTilePairs : kMaxLogTileKeys;
+}
+
+template <bool PAIRS, int R>
+hipError_t launch_gather_r(const SortArray &a, uint32_t log_n, uint32_t m, uint32_t b_lo,
+                           int32_t nsteps, int io_mode, hipStream_t stream) {
+    constexpr int L = gather_log<PAIRS>();
+    constexpr int C = L - R;
+    if (log_n < (uint32_t)L || b_lo < (uint32_t)C || b_lo + R > log_n) return hipErrorInvalidValue;
+    const size_t lds = regs_lds_bytes<PAIRS, L>();
+    auto kern = bitonic_pass_regs_kernel<PAIRS, L, R, C>;
+    hipError_t e = allow_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(1u << (log_n - L)), dim3(1u << (L - 4)), lds, stream, a, m,
+                       b_lo, io_mode, nsteps);
     return hipGetLastError();
 }
 
@@ -734,6 +795,29 @@ hipError_t launch_bitonic_sort_regs(const SortArray &a, uint32_t log_t, uint32_t
                                         stream);
     return launch_sort_regs_p<false>(a, log_t, n_tiles, step_limit, meld_lo, meld_hi, io_mode,
                                      stream);
+}
+
+hipError_t launch_bitonic_gather(const SortArray &a, uint32_t log_n, uint32_t m, uint32_t b_hi,
+                                 uint32_t b_lo, int32_t step_limit, int io_mode,
+                                 hipStream_t stream) {
+    if (step_limit == 0) return hipSuccess;
+    if (io_mode == kPlain) io_mode = kTail;
+    if (io_mode != kTail && io_mode != kPlainVec) return hipErrorInvalidValue;
+    const int32_t r = (int32_t)(b_hi - b_lo + 1);
+    const int32_t nsteps = step_limit < 0 ? r : step_limit;
+    if (a.vals != nullptr) {
+        switch (r) {
+            case 7: return launch_gather_r<true, 7>(a, log_n, m, b_lo, nsteps, io_mode, stream);
+            case 8: return launch_gather_r<true, 8>(a, log_n, m, b_lo, nsteps, io_mode, stream);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    switch (r) {
+        case 7: return launch_gather_r<false, 7>(a, log_n, m, b_lo, nsteps, io_mode, stream);
+        case 8: return launch_gather_r<false, 8>(a, log_n, m, b_lo, nsteps, io_mode, stream);
+        case 9: return launch_gather_r<false, 9>(a, log_n, m, b_lo, nsteps, io_mode, stream);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_bitonic_merge(const SortArray &a, uint32_t log_t, uint32_t n_tiles, uint32_t m,

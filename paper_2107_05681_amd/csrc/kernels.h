@@ -53,6 +53,15 @@ hipError_t launch_bitonic_sort_regs(const SortArray &a, uint32_t log_t, uint32_t
                                     int32_t step_limit, bool meld_lo, bool meld_hi, int io_mode,
                                     hipStream_t stream);
 
+// Steps j = 2^b_hi .. 2^b_lo of phase k = 2^m over all N = 2^log_n elements
+// in one pass through LDS: each workgroup gathers 2^(b_hi-b_lo+1) rows of
+// contiguous elements (b_hi - b_lo + 1 in 7..8 for pairs, 7..9 for keys;
+// rows of at least 32 elements). io_mode plain, vector or tail.
+hipError_t launch_bitonic_gather(const SortArray &a, uint32_t log_n, uint32_t m, uint32_t b_hi,
+                                 uint32_t b_lo, int32_t step_limit, int io_mode,
+                                 hipStream_t stream);
+constexpr uint32_t kMaxGatherStepsPairs = 8, kMaxGatherStepsKeys = 9;
+
 // Steps j = 2^(log_t-1) .. 1 of phase k = 2^m > 2^log_t on every tile, in
 // registers with LDS transposes (log_t in 8..14; io_mode plain, vector or
 // tail). At most step_limit steps run (negative: all).
@@ -93,32 +102,36 @@ hipError_t launch_probe_segments(const uint32_t *off, uint32_t nseg, unsigned lo
 
 // Segmented sort (segsort.hip).
 constexpr uint32_t kSegThreads = 1024;
-constexpr uint32_t kSegLogTile = 15;  // 2^15 keys = 128 KiB of LDS per workgroup
-constexpr uint32_t kSegTile = 1u << kSegLogTile;
+constexpr uint32_t kSegLogChunk = 14;  // 2^14 keys: 16 per lane of a workgroup
+constexpr uint32_t kSegChunk = 1u << kSegLogChunk;
+constexpr uint32_t kSegLdsWords = kSegChunk + kSegChunk / 16;  // padded tile, 68 KiB
+constexpr uint32_t kSegWorkWords = 1u << 16;  // staging of a segment of up to 2^16 keys
 constexpr uint32_t kSegMaxLen = 1u << 16;
 constexpr uint32_t kSegClasses = 17;  // size class ceil(log2(len)) in 0..16
+constexpr uint32_t kSegSmallClassMax = 7;  // up to 128 keys: one wave per segment
 constexpr uint32_t kSegBadFirst = 1, kSegDecreasing = 2, kSegTooLong = 4;
 
 // Device-side work-queue state of one segmented sort.
 struct SegState {
-    uint32_t cnt[kSegClasses];   // segments per size class
-    uint32_t fill[kSegClasses];  // scatter cursors
-    uint32_t base[kSegClasses];  // queue start of each class (largest class first)
-    uint32_t head;               // next work item
-    uint32_t flag;               // invalid-offset bits of this call
-    uint32_t sticky;             // invalid-offset bits since the last check
-    uint32_t n_big;              // segments of more than 128 keys (one item each)
-    uint32_t n_small;            // segments of 2..128 keys (16 per item)
+    uint32_t cnt[kSegClasses];        // segments per size class
+    uint32_t fill[kSegClasses];       // scatter cursors
+    uint32_t base[kSegClasses];       // queue start of each class (largest class first)
+    uint32_t item_base[kSegClasses];  // first work item of each class >= 8
+    uint32_t head;                    // next work item
+    uint32_t flag;                    // invalid-offset bits of this call
+    uint32_t sticky;                  // invalid-offset bits since the last check
+    uint32_t n_big;                   // work items of the classes >= 8
+    uint32_t n_small;                 // segments of 2..128 keys (16 per item)
     uint32_t n_items;
 };
 
-// Persistent grid size: CUs x resident 1024-lane workgroups with 128 KiB LDS.
+// Persistent grid size: CUs x resident 1024-lane workgroups (68 KiB of LDS).
 hipError_t seg_sort_grid(int device, uint32_t *grid);
 
 // Enqueues reset, classify, plan, scatter and the persistent sort. cls holds
-// nseg bytes, queue nseg words, pad grid * kSegTile words.
+// nseg bytes, queue nseg words, work grid * kSegWorkWords words.
 hipError_t launch_segmented_sort(uint32_t *keys, const uint32_t *off, uint32_t nseg,
-                                 SegState *st, uint8_t *cls, uint32_t *queue, uint32_t *pad,
+                                 SegState *st, uint8_t *cls, uint32_t *queue, uint32_t *work,
                                  uint32_t grid, bool meld_lo, bool meld_hi, hipStream_t stream);
 
 // Largest tile (log2 elements) the tile kernel supports for keys / pairs.

@@ -28,7 +28,7 @@ struct meld_ctx {
     uint8_t *seg_cls = nullptr;
     uint32_t *seg_queue = nullptr;
     size_t seg_cap = 0;  // segments the two arrays above hold
-    uint32_t *seg_pad = nullptr;
+    uint32_t *seg_work = nullptr;
     uint32_t seg_grid = 0;
     // Captured segmented-sort sequences (reset, classify, plan, scatter,
     // persistent sort), most recently used first, replayed on the caller's
@@ -233,9 +233,9 @@ meld_status ensure_seg(meld_ctx *ctx, size_t nseg) {
         if (st != MELD_OK) return st;
         if (hipMemset(ctx->seg_state, 0, sizeof(meld::SegState)) != hipSuccess)
             return fail(MELD_EHIP, "hipMemset of segmented sort state failed");
-        st = dev_alloc(reinterpret_cast<void **>(&ctx->seg_pad),
-                       (size_t)ctx->seg_grid * meld::kSegTile * sizeof(uint32_t),
-                       "segmented sort padding");
+        st = dev_alloc(reinterpret_cast<void **>(&ctx->seg_work),
+                       (size_t)ctx->seg_grid * meld::kSegWorkWords * sizeof(uint32_t),
+                       "segmented sort staging");
         if (st != MELD_OK) return st;
     }
     if (nseg > ctx->seg_cap) {
@@ -283,7 +283,7 @@ meld_status seg_graph(meld_ctx *ctx, uint32_t *keys, const uint32_t *offsets, si
     hipError_t e = hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
     hipError_t le = meld::launch_segmented_sort(keys, offsets, (uint32_t)nseg, ctx->seg_state,
-                                                ctx->seg_cls, ctx->seg_queue, ctx->seg_pad,
+                                                ctx->seg_cls, ctx->seg_queue, ctx->seg_work,
                                                 ctx->seg_grid, lo, hi, ctx->capture_stream);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(ctx->capture_stream, &graph);
@@ -322,7 +322,7 @@ meld_status segmented_impl(meld_ctx *ctx, uint32_t *keys, const uint32_t *offset
     if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
     if (!ctx->use_graphs || cs != hipStreamCaptureStatusNone) {
         e = meld::launch_segmented_sort(keys, offsets, (uint32_t)nseg, ctx->seg_state,
-                                        ctx->seg_cls, ctx->seg_queue, ctx->seg_pad, ctx->seg_grid,
+                                        ctx->seg_cls, ctx->seg_queue, ctx->seg_work, ctx->seg_grid,
                                         meld_lo, meld_hi, stream);
         if (e != hipSuccess) return hip_fail(e, "segmented sort launch");
         return MELD_OK;
@@ -368,6 +368,22 @@ uint32_t default_log_tile(bool pairs, uint32_t log_n) {
     else
         t = pairs ? (log_n <= 25 ? 12 : 13) : 14;
     return std::max(kMinLogRegsTile, std::min(t, max_log_tile(pairs)));
+}
+
+// Sizes (high bits first) of the streaming passes of d global steps: the
+// fewest passes of at most max_gather steps, as equal as possible (a gathered
+// pass of 8 pair steps has rows of only 128 bytes and runs slower than one of
+// 7, so 14 steps go as 7 + 7 rather than 8 + 6).
+std::vector<uint32_t> split_passes(uint32_t d, uint32_t max_gather) {
+    const uint32_t n = (d + max_gather - 1) / max_gather;
+    std::vector<uint32_t> sizes;
+    uint32_t left = d;
+    for (uint32_t p = 0; p < n; ++p) {
+        const uint32_t r = (left + (n - p) - 1) / (n - p);
+        sizes.push_back(r);
+        left -= r;
+    }
+    return sizes;
 }
 
 // Enqueues the whole network (or its first step_limit steps) on keys[0..n).
@@ -425,18 +441,32 @@ meld_status sort_impl(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n
                                        plan.lo, plan.hi, io, stream);
     if (e != hipSuccess) return hip_fail(e, "bitonic tile launch");
 
+    const uint32_t max_gather = pairs ? meld::kMaxGatherStepsPairs : meld::kMaxGatherStepsKeys;
+    const uint32_t gather_log = max_log_tile(pairs);
     for (uint32_t m = log_t + 1; m <= log_n; ++m) {
-        // Steps j = 2^(m-1) .. 2^log_t stream through HBM, fused in balanced
-        // groups of at most kMaxFusedSteps.
-        const uint32_t d = m - log_t;
-        const uint32_t passes = (d + meld::kMaxFusedSteps - 1) / meld::kMaxFusedSteps;
+        // Steps j = 2^(m-1) .. 2^log_t stream through HBM in as few passes as
+        // possible: up to kMaxFusedSteps per pass in registers, more (high
+        // bits first) through gathered LDS tiles where their rows fit.
         uint32_t b_hi = m - 1;
-        for (uint32_t p = 0; p < passes; ++p) {
-            const uint32_t remaining = b_hi - log_t + 1;
-            const uint32_t this_r = (remaining + (passes - p) - 1) / (passes - p);
-            const uint32_t b_lo = b_hi + 1 - this_r;
-            e = meld::launch_bitonic_global(a, log_n, m, b_hi, b_lo, take(this_r), stream);
-            if (e != hipSuccess) return hip_fail(e, "bitonic global launch");
+        for (uint32_t r : split_passes(m - log_t, max_gather)) {
+            const uint32_t b_lo = b_hi + 1 - r;
+            const bool gather_fits = log_n >= gather_log && b_lo + r >= gather_log;
+            if (r > meld::kMaxFusedSteps && gather_fits) {
+                e = meld::launch_bitonic_gather(a, log_n, m, b_hi, b_lo, take(r), io, stream);
+                if (e != hipSuccess) return hip_fail(e, "bitonic gather launch");
+            } else {
+                // register passes only (balanced)
+                const uint32_t parts = (r + meld::kMaxFusedSteps - 1) / meld::kMaxFusedSteps;
+                uint32_t hi = b_hi;
+                for (uint32_t p = 0; p < parts; ++p) {
+                    const uint32_t remaining = hi - b_lo + 1;
+                    const uint32_t this_r = (remaining + (parts - p) - 1) / (parts - p);
+                    e = meld::launch_bitonic_global(a, log_n, m, hi, hi + 1 - this_r,
+                                                    take(this_r), stream);
+                    if (e != hipSuccess) return hip_fail(e, "bitonic global launch");
+                    hi -= this_r;
+                }
+            }
             b_hi = b_lo - 1;
         }
         // Steps j = 2^(log_t-1) .. 1 of phase m: the direction is uniform per
@@ -593,7 +623,7 @@ meld_status auto_seg_forms(meld_ctx *ctx, uint32_t *keys, const uint32_t *offset
             [&]() -> meld_status {
                 hipError_t r = meld::launch_segmented_sort(
                     ctx->tune_buf, offsets, (uint32_t)nseg, ctx->seg_state, ctx->seg_cls,
-                    ctx->seg_queue, ctx->seg_pad, ctx->seg_grid, l, h, s);
+                    ctx->seg_queue, ctx->seg_work, ctx->seg_grid, l, h, s);
                 return r == hipSuccess ? MELD_OK : hip_fail(r, "segmented sort launch");
             },
             &t);
@@ -731,7 +761,7 @@ void meld_destroy(meld_ctx *ctx) {
     drop_seg_graphs(ctx);
     if (ctx->capture_stream != nullptr) (void)hipStreamDestroy(ctx->capture_stream);
     for (void *p : {(void *)ctx->tail, (void *)ctx->seg_state, (void *)ctx->seg_cls,
-                    (void *)ctx->seg_queue, (void *)ctx->seg_pad, (void *)ctx->tune_buf,
+                    (void *)ctx->seg_queue, (void *)ctx->seg_work, (void *)ctx->tune_buf,
                     (void *)ctx->probe_buf})
         if (p != nullptr) (void)hipFree(p);
     delete ctx;

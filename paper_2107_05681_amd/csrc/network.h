@@ -111,4 +111,102 @@ __device__ __forceinline__ int32_t lds_network(E *s, uint32_t T, uint32_t base, 
     return steps;
 }
 
+// One step (k = 2^m, j) with ITERS comparators per lane: lane0, lane0 + nt,
+// ... (a tile of 2 * ITERS * nt elements). All loads of a lane's comparators
+// are issued before its first compare, so their LDS latency overlaps.
+//   melded: one load pair per comparator, both compares, a select of the swap
+//     condition on the direction, one conditional store pair;
+//   divergent: Figure 1's if/else. With nt >= 64 the direction of a phase
+//     k <= 64 is a bit of lane0 alone, the same for all of the lane's
+//     comparators, so the branch is taken once per step (the loop is
+//     unswitched) and each side holds its own batched loads, compares and
+//     swap stores; with nt < 64 it stays per comparator.
+template <typename E, bool MELDED, int ITERS>
+__device__ __forceinline__ void lds_step_batched(E *s, uint32_t base, uint32_t m, uint32_t j,
+                                                 uint32_t lane0, uint32_t nt) {
+    uint32_t lo[ITERS];
+#pragma unroll
+    for (int i = 0; i < ITERS; ++i) {
+        const uint32_t c = lane0 + (uint32_t)i * nt;
+        lo[i] = ((c & ~(j - 1)) << 1) | (c & (j - 1));
+    }
+    if constexpr (MELDED) {
+        E a[ITERS], b[ITERS];
+#pragma unroll
+        for (int i = 0; i < ITERS; ++i) {
+            a[i] = s[lo[i]];
+            b[i] = s[lo[i] + j];
+        }
+#pragma unroll
+        for (int i = 0; i < ITERS; ++i) {
+            const bool up = (((base | lo[i]) >> m) & 1u) == 0;
+            const bool lt = b[i] < a[i];
+            const bool gt = b[i] > a[i];
+            if ((up & lt) | (!up & gt)) {
+                s[lo[i]] = b[i];
+                s[lo[i] + j] = a[i];
+            }
+        }
+    } else if (nt >= 64) {
+        const bool up = (((base | lo[0]) >> m) & 1u) == 0;
+        E a[ITERS], b[ITERS];
+        if (up) {
+            MELD_SIDE_MARK("ascending batch");
+#pragma unroll
+            for (int i = 0; i < ITERS; ++i) {
+                a[i] = s[lo[i]];
+                b[i] = s[lo[i] + j];
+            }
+#pragma unroll
+            for (int i = 0; i < ITERS; ++i)
+                if (b[i] < a[i]) {
+                    s[lo[i]] = b[i];
+                    s[lo[i] + j] = a[i];
+                }
+            MELD_SIDE_MARK("ascending batch end");
+        } else {
+            MELD_SIDE_MARK("descending batch");
+#pragma unroll
+            for (int i = 0; i < ITERS; ++i) {
+                a[i] = s[lo[i]];
+                b[i] = s[lo[i] + j];
+            }
+#pragma unroll
+            for (int i = 0; i < ITERS; ++i)
+                if (b[i] > a[i]) {
+                    s[lo[i]] = b[i];
+                    s[lo[i] + j] = a[i];
+                }
+            MELD_SIDE_MARK("descending batch end");
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < ITERS; ++i)
+            cex_divergent(s, lo[i], lo[i] + j, (((base | lo[i]) >> m) & 1u) == 0);
+    }
+}
+
+// Phases k = 2 .. 2^m_end (m_end <= 6) of the network on a tile of
+// 2 * ITERS * nt elements whose comparators are dealt to nt lanes
+// (lane0 < nt), in form MELDED, at most step_limit steps (negative: all);
+// returns the number of steps run. Every step is wave-local: the nt lanes of
+// a team shorter than a wave share one wave, and for nt >= 64 a wave's
+// comparators of one iteration stay inside one 128-element block in every
+// step j <= 32.
+template <typename E, bool MELDED, int ITERS>
+__device__ __forceinline__ int32_t lds_network_low(E *s, uint32_t base, uint32_t m_end,
+                                                   uint32_t lane0, uint32_t nt,
+                                                   int32_t step_limit) {
+    int32_t steps = 0;
+    for (uint32_t m = 1; m <= m_end; ++m) {
+        for (uint32_t j = 1u << (m - 1); j > 0; j >>= 1) {
+            if (steps == step_limit) return steps;
+            ++steps;
+            lds_step_batched<E, MELDED, ITERS>(s, base, m, j, lane0, nt);
+            wave_lds_sync();
+        }
+    }
+    return steps;
+}
+
 }  // namespace meld

@@ -92,8 +92,14 @@ __global__ __launch_bounds__(64) void probe_network_kernel(uint32_t log_t, int r
 
 // Segmented sort: per segment, the comparator-steps of each stage (phases
 // k <= 64 and k >= 128) and how many of them fall in mixed waves, under the
-// segmented kernel's mapping (one wave per segment of <= 128 keys, the whole
-// workgroup's consecutive comparators otherwise).
+// segmented kernel's mapping: one wave per segment of <= 128 keys (64
+// consecutive comparators per wave); for a segment of class c >= 8 (chunks
+// of 2^cm keys, cm = min(c, 14)) a team of nt = 2^(cm-4) lanes, which takes
+// comparators t, t + nt, ... in the phases k <= 64 and holds 16 keys per lane
+// (8 comparators per step, direction = lane bit p-4 in phase 2^p) in the
+// register phases; the steps across chunks are wave-uniform. A team shorter
+// than a wave shares it with teams of the same pattern, so its own nt lanes
+// decide the wave.
 // out[0] += mixed comparator-steps (low stage), out[1] += all (low stage),
 // out[2], out[3]: the same for the high stage.
 __global__ __launch_bounds__(64) void probe_segments_kernel(const uint32_t *__restrict__ off,
@@ -108,19 +114,41 @@ __global__ __launch_bounds__(64) void probe_segments_kernel(const uint32_t *__re
     const uint32_t half = 1u << (log_p - 1);
     const uint32_t lane = __lane_id();
     unsigned long long acc[4] = {0, 0, 0, 0};
+    const uint32_t cm = log_p < kSegLogChunk ? log_p : kSegLogChunk;
+    const uint32_t nt = 1u << (cm - 4);
+    const uint32_t chunks = 1u << (log_p - cm);
     for (uint32_t m = 1; m <= log_p; ++m) {
-        // The direction is bit m-1 of the comparator index in every step of
-        // the phase; the phase has m steps of `half` comparators each.
-        const uint32_t waves = (half + 63) / 64;
+        // mixed comparators of one step of phase 2^m (whole segment)
         unsigned long long mixed_cmp = 0;
-        for (uint32_t w = 0; w < waves; ++w) {
-            const uint32_t c = w * 64 + lane;
-            const bool active = c < half;
-            const uint32_t lo = c << 1;  // step j = 1; bit m of lo is bit m-1 of c
-            const bool up = active && ((lo >> m) & 1u) == 0;
-            const uint64_t mu = __ballot(up);
-            const uint64_t ma = __ballot(active);
-            if (mu != 0 && mu != ma) mixed_cmp += (unsigned long long)__popcll(ma);
+        if (log_p <= kSegSmallClassMax) {
+            // The direction is bit m-1 of the comparator index in every step
+            // of the phase.
+            for (uint32_t w = 0; w < (half + 63) / 64; ++w) {
+                const uint32_t c = w * 64 + lane;
+                const bool active = c < half;
+                const bool up = active && ((c >> (m - 1)) & 1u) == 0;
+                const uint64_t mu = __ballot(up);
+                const uint64_t ma = __ballot(active);
+                if (mu != 0 && mu != ma) mixed_cmp += (unsigned long long)__popcll(ma);
+            }
+        } else if (m <= cm) {
+            const bool low = m <= 6;
+            const uint32_t waves = nt >= 64 ? nt / 64 : 1;
+            const uint32_t iters = low ? (1u << (cm - 1)) / nt : 1;
+            for (uint32_t w = 0; w < waves; ++w) {
+                const uint32_t t = nt >= 64 ? w * 64 + lane : lane;
+                const bool active = t < nt;
+                for (uint32_t i = 0; i < iters; ++i) {
+                    const uint32_t bit = low ? (((t + i * nt) >> (m - 1)) & 1u)
+                                             : ((t >> (m - 4)) & 1u);
+                    const bool up = active && bit == 0;
+                    const uint64_t mu = __ballot(up);
+                    const uint64_t ma = __ballot(active);
+                    if (mu != 0 && mu != ma)
+                        mixed_cmp += (unsigned long long)__popcll(ma) * (low ? 1u : 8u);
+                }
+            }
+            mixed_cmp *= chunks;
         }
         const unsigned long long steps_all = (unsigned long long)m * half;
         const unsigned long long steps_mixed = (unsigned long long)m * mixed_cmp;

@@ -7,25 +7,29 @@
 //                 can be captured in a graph);
 //   2. classify — per segment: validity checks and the size class
 //                 c = ceil(log2(len)) (0 for len <= 1: nothing to do);
-//   3. plan     — queue layout: classes in descending order (largest first),
-//                 segments of more than 128 keys are one work item each,
-//                 shorter ones are bundled 16 to an item (one per wave);
+//   3. plan     — queue layout: classes in descending order (largest first);
+//                 work items: one per segment of class 15..16, 2^(14-c)
+//                 segments of class c = 8..14 per item, 16 segments of
+//                 class <= 7 per item;
 //   4. scatter  — segment ids into the queue;
-//   5. sort     — a persistent grid (one 1024-lane workgroup per CU, 128 KiB
-//                 of LDS each) pulls items from an atomic counter until the
-//                 queue is empty.
+//   5. sort     — a persistent grid of 1024-lane workgroups (68 KiB of LDS
+//                 each) pulls items from an atomic counter until the queue
+//                 is empty.
 // Each segment runs the Figure 1 network on its own (padded) length with
 // the segment-local index giving the direction. Per stage the caller picks
-// the divergent or melded compare-exchange: MELD_LO for phases k <= 64 (the
-// direction differs between the lanes of a wave) and MELD_HI for k >= 128
-// (wave-uniform direction).
+// the divergent or melded compare-exchange: MELD_LO for phases k <= 64 and
+// MELD_HI for k >= 128.
 //
-// A segment of up to 2^15 keys sorts in LDS. A longer one (up to 2^16) sorts
-// its two halves in LDS (phases up to 2^15: the first ascending, the second
-// descending), runs the step j = 2^15 of the last phase through global memory
-// and merges each half in LDS; padding positions past the segment live in a
-// per-workgroup global scratch of 2^15 words. All of it stays inside one
-// workgroup, so no grid-wide synchronisation is needed.
+// Class <= 7 (up to 128 keys): one wave per segment, the comparator network
+// in LDS. Class c = 8..14: a team of 2^(c-4) lanes per segment holding 16
+// keys per lane; phases k <= 64 run as the LDS comparator network (team
+// lanes take comparators in turn), phases k >= 128 in register windows with
+// LDS transposes (the direction is a lane bit for k <= 512). Class 15..16: the
+// whole workgroup sorts the segment's 2^14-key chunks as class 14 (odd chunks
+// descending), runs the steps j >= 2^14 through global memory inside the
+// workgroup and merges each chunk in registers, the segment staged (with its
+// padding) in a per-workgroup scratch of 2^16 words. All of it stays inside
+// one workgroup, so no grid-wide synchronisation is needed.
 #include "device_common.h"
 #include "kernels.h"
 #include "network.h"
@@ -37,7 +41,86 @@ namespace {
 constexpr uint32_t kPad = 0xFFFFFFFFu;
 constexpr uint32_t kWavesPerBlock = kSegThreads / 64;
 constexpr uint32_t kSmallMax = 128;
-constexpr uint32_t kSmallClassMax = 7;  // ceil(log2(128))
+constexpr uint32_t kSmallClassMax = kSegSmallClassMax;
+
+constexpr int kSegE = 16;  // keys per lane in the register phases
+
+// Hides v's value from the optimiser at this point: the LDS and global
+// addresses derived from it are then computed where they are used instead of
+// being hoisted out of the persistent loop (which held ~40 of them live
+// across the whole kernel and forced spills).
+__device__ __forceinline__ void opaque(uint32_t &v) { asm volatile("" : "+v"(v)); }
+
+__device__ __forceinline__ uint32_t padded(uint32_t i) { return i + (i >> 4); }
+
+// Window B: element bits [B, B+4) are the register index, the others the lane.
+__device__ __forceinline__ uint32_t window_tpart(uint32_t t, uint32_t B) {
+    return (t & ((1u << B) - 1)) | ((t >> B) << (B + 4));
+}
+
+__device__ __forceinline__ void cex_regs(uint32_t &x, uint32_t &y, bool up) {
+    const uint32_t mn = x < y ? x : y;
+    const uint32_t mx = x < y ? y : x;
+    x = up ? mn : mx;
+    y = up ? mx : mn;
+}
+
+// One register step on register bit Q: divergent (Figure 1's if/else on the
+// direction, the marks keep the two sides apart) or melded (both compares,
+// the swap chosen by a select).
+template <int Q, bool MELDED>
+__device__ __forceinline__ void seg_reg_step(uint32_t (&e)[kSegE], bool up) {
+    if constexpr (MELDED) {
+#pragma unroll
+        for (int r = 0; r < kSegE; ++r)
+            if ((r & (1 << Q)) == 0) cex_regs(e[r], e[r | (1 << Q)], up);
+    } else {
+        if (up) {
+            MELD_SIDE_MARK("ascending regs");
+#pragma unroll
+            for (int r = 0; r < kSegE; ++r)
+                if ((r & (1 << Q)) == 0) {
+                    const uint32_t x = e[r], y = e[r | (1 << Q)];
+                    if (y < x) {
+                        e[r] = y;
+                        e[r | (1 << Q)] = x;
+                    }
+                }
+        } else {
+            MELD_SIDE_MARK("descending regs");
+#pragma unroll
+            for (int r = 0; r < kSegE; ++r)
+                if ((r & (1 << Q)) == 0) {
+                    const uint32_t x = e[r], y = e[r | (1 << Q)];
+                    if (y > x) {
+                        e[r] = y;
+                        e[r | (1 << Q)] = x;
+                    }
+                }
+        }
+    }
+}
+
+template <bool MELDED>
+__device__ __forceinline__ void seg_reg_steps(uint32_t (&e)[kSegE], int hi_q, bool up,
+                                              int32_t &left) {
+    if (hi_q >= 3 && left > 0) {
+        seg_reg_step<3, MELDED>(e, up);
+        --left;
+    }
+    if (hi_q >= 2 && left > 0) {
+        seg_reg_step<2, MELDED>(e, up);
+        --left;
+    }
+    if (hi_q >= 1 && left > 0) {
+        seg_reg_step<1, MELDED>(e, up);
+        --left;
+    }
+    if (left > 0) {
+        seg_reg_step<0, MELDED>(e, up);
+        --left;
+    }
+}
 
 __device__ __forceinline__ uint32_t ceil_log2(uint32_t v) {
     return v <= 1 ? 0u : 32u - (uint32_t)__clz(v - 1);
@@ -88,20 +171,30 @@ __global__ __launch_bounds__(256) void seg_classify_kernel(const uint32_t *__res
         atomicAdd(&st->cnt[threadIdx.x], lcnt[threadIdx.x]);
 }
 
+// Work items of class c >= 8: one per segment above 2^14 keys, otherwise
+// one per 2^(14-c) segments (one team each).
+__device__ __forceinline__ uint32_t class_items(uint32_t c, uint32_t cnt) {
+    if (c > kSegLogChunk) return cnt;
+    const uint32_t per = 1u << (kSegLogChunk - c);
+    return (cnt + per - 1) / per;
+}
+
 __global__ void seg_plan_kernel(SegState *st) {
     if (threadIdx.x != 0) return;
-    uint32_t pos = 0, n_big = 0, n_small = 0;
+    uint32_t pos = 0, items = 0, n_small = 0;
     for (int c = (int)kSegClasses - 1; c >= 1; --c) {
         st->base[c] = pos;
         pos += st->cnt[c];
-        if ((uint32_t)c > kSmallClassMax)
-            n_big += st->cnt[c];
-        else
+        if ((uint32_t)c > kSmallClassMax) {
+            st->item_base[c] = items;
+            items += class_items((uint32_t)c, st->cnt[c]);
+        } else {
             n_small += st->cnt[c];
+        }
     }
-    st->n_big = n_big;
+    st->n_big = items;
     st->n_small = n_small;
-    st->n_items = n_big + (n_small + kWavesPerBlock - 1) / kWavesPerBlock;
+    st->n_items = items + (n_small + kWavesPerBlock - 1) / kWavesPerBlock;
     st->head = 0;
 }
 
@@ -123,65 +216,171 @@ __global__ __launch_bounds__(256) void seg_scatter_kernel(uint32_t nseg,
     if (c != 0) queue[st->base[c] + lbase[c] + rank] = s;
 }
 
-// Sorts segment [lo, lo + len), 128 < len <= 2^15, padded to 2^m in LDS.
+// Steps of phase k = 2^p on element bits hi_bit .. 0 of a tile held in
+// registers, 16 per lane (lane t of the tile's nt lanes): windows with bases
+// hi_bit-3, hi_bit-7, ... (clamped at 0). cur is the window e is in; natural:
+// e is still only in s, in natural order (the first window reads it there).
+template <bool MELDED>
+__device__ __forceinline__ void phase_windows(uint32_t (&e)[kSegE], uint32_t *s, uint32_t t,
+                                              uint32_t &cur, bool &natural, int hi_bit, bool up) {
+    int32_t unlimited = 0x7FFFFFFF;
+#pragma unroll 1
+    for (int top = hi_bit; top >= 0;) {
+        const uint32_t B = top >= 3 ? (uint32_t)(top - 3) : 0u;
+        const uint32_t tb = window_tpart(t, B);
+        if (natural) {
+#pragma unroll
+            for (int r = 0; r < kSegE; ++r) e[r] = s[tb | ((uint32_t)r << B)];
+            __syncthreads();
+            natural = false;
+        } else if (B != cur) {
+            const uint32_t tp = window_tpart(t, cur);
+#pragma unroll
+            for (int r = 0; r < kSegE; ++r) s[padded(tp | ((uint32_t)r << cur))] = e[r];
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < kSegE; ++r) e[r] = s[padded(tb | ((uint32_t)r << B))];
+            __syncthreads();
+        }
+        seg_reg_steps<MELDED>(e, top - (int)B, up, unlimited);
+        cur = B;
+        top = (int)B - 1;
+    }
+}
+
+// Moves e from window cur to window B through the padded LDS tile.
+__device__ __forceinline__ void to_window(uint32_t (&e)[kSegE], uint32_t *s, uint32_t t,
+                                          uint32_t &cur, uint32_t B) {
+    if (B == cur) return;
+    const uint32_t tp = window_tpart(t, cur), tb = window_tpart(t, B);
+#pragma unroll
+    for (int r = 0; r < kSegE; ++r) s[padded(tp | ((uint32_t)r << cur))] = e[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSegE; ++r) e[r] = s[padded(tb | ((uint32_t)r << B))];
+    __syncthreads();
+    cur = B;
+}
+
+// A team of 2^(m-4) lanes (lane t) sorts the 2^m positions cbase + i of a
+// segment (8 <= m <= 14): positions below len come from keys[lo + q], the
+// others are padding. s is the team's own LDS region of 17 * 2^(m-4) words.
+// With work != nullptr every result goes to work[q]; otherwise results
+// below len go to keys and the padding is dropped. The direction of phase p
+// is bit p of cbase + i, so a chunk with bit m of cbase set ends descending.
 template <bool MELD_LO, bool MELD_HI>
-__device__ void sort_in_lds(uint32_t *__restrict__ keys, uint32_t *s, uint32_t lo, uint32_t len,
-                            uint32_t m) {
-    const uint32_t T = 1u << m;
-    const uint32_t tid = threadIdx.x;
-    for (uint32_t p = tid; p < T; p += kSegThreads) s[p] = p < len ? keys[lo + p] : kPad;
+__device__ __forceinline__ void team_sort(uint32_t *__restrict__ keys,
+                                          uint32_t *__restrict__ work, uint32_t *s, uint32_t lo,
+                                          uint32_t len, uint32_t m, uint32_t cbase, uint32_t t) {
+    opaque(t);
+    const uint32_t lt = m - 4;
+    uint32_t e[kSegE];
+#pragma unroll
+    for (int r = 0; r < kSegE; ++r) {
+        const uint32_t q = cbase + (t | ((uint32_t)r << lt));
+        e[r] = q < len ? keys[lo + q] : kPad;
+    }
+#pragma unroll
+    for (int r = 0; r < kSegE; ++r) s[t | ((uint32_t)r << lt)] = e[r];
     __syncthreads();
-    lds_network<uint32_t, MELD_LO, MELD_HI, kSegThreads, true>(s, T, 0, 1, m, 0, -1, tid);
+    lds_network_low<uint32_t, MELD_LO, 8>(s, cbase, 6, t, 1u << lt, -1);
     __syncthreads();
-    for (uint32_t p = tid; p < len; p += kSegThreads) keys[lo + p] = s[p];
+    uint32_t cur = 0;
+    bool natural = true;
+#pragma unroll 1
+    for (uint32_t p = 7; p <= m; ++p) {
+        const bool up = (((cbase >> p) | (t >> (p - 4))) & 1u) == 0;
+        phase_windows<MELD_HI>(e, s, t, cur, natural, (int)p - 1, up);
+    }
+    to_window(e, s, t, cur, lt);
+    if (work != nullptr) {
+#pragma unroll
+        for (int r = 0; r < kSegE; ++r) work[cbase + (t | ((uint32_t)r << lt))] = e[r];
+    } else {
+#pragma unroll
+        for (int r = 0; r < kSegE; ++r) {
+            const uint32_t q = cbase + (t | ((uint32_t)r << lt));
+            if (q < len) keys[lo + q] = e[r];
+        }
+    }
+}
+
+// Steps j = 2^(p-1) .. 2^14 of phase 2^p over the 2^m positions of a
+// segment held in the workgroup's scratch (p <= m <= 16, so one or two
+// steps), in registers.
+__device__ void seg_global_steps(uint32_t *__restrict__ work, uint32_t m, uint32_t p,
+                                 uint32_t tid) {
+    __syncthreads();  // the chunks' stores are visible to the workgroup
+    const uint32_t d = p - kSegLogChunk;  // 1 or 2
+    const uint32_t groups = 1u << (m - d);
+#pragma unroll 1
+    for (uint32_t g = tid; g < groups; g += kSegThreads) {
+        const uint32_t base = (g & (kSegChunk - 1)) | ((g >> kSegLogChunk) << p);
+        const bool up = ((base >> p) & 1u) == 0;
+        uint32_t *w = work + base;
+        uint32_t v0 = w[0], v1 = w[kSegChunk];
+        if (d == 1) {
+            cex_regs(v0, v1, up);
+        } else {
+            uint32_t v2 = w[2 * kSegChunk], v3 = w[3 * kSegChunk];
+            cex_regs(v0, v2, up);  // j = 2^15
+            cex_regs(v1, v3, up);
+            cex_regs(v0, v1, up);  // j = 2^14
+            cex_regs(v2, v3, up);
+            w[2 * kSegChunk] = v2;
+            w[3 * kSegChunk] = v3;
+        }
+        w[0] = v0;
+        w[kSegChunk] = v1;
+    }
     __syncthreads();
 }
 
-// Sorts segment [lo, lo + len), 2^15 < len <= 2^16, as two LDS halves.
+// Steps j = 2^13 .. 1 of a phase on chunk cbase of a segment in the
+// workgroup's scratch; the direction is the same for the whole chunk, so
+// both forms coincide. The last phase writes the positions below len to the
+// caller's keys, earlier ones write back to the scratch.
+__device__ void chunk_merge(uint32_t *__restrict__ keys, uint32_t *__restrict__ work, uint32_t *s,
+                            uint32_t lo, uint32_t len, uint32_t cbase, uint32_t t, bool up,
+                            bool last) {
+    opaque(t);
+    constexpr uint32_t lt = kSegLogChunk - 4;
+    uint32_t e[kSegE];
+#pragma unroll
+    for (int r = 0; r < kSegE; ++r) e[r] = work[cbase + (t | ((uint32_t)r << lt))];
+    uint32_t cur = lt;
+    bool natural = false;
+    phase_windows<true>(e, s, t, cur, natural, (int)kSegLogChunk - 1, up);
+    to_window(e, s, t, cur, lt);
+    if (last) {
+#pragma unroll
+        for (int r = 0; r < kSegE; ++r) {
+            const uint32_t q = cbase + (t | ((uint32_t)r << lt));
+            if (q < len) keys[lo + q] = e[r];
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < kSegE; ++r) work[cbase + (t | ((uint32_t)r << lt))] = e[r];
+    }
+}
+
+// A segment of class 15..16 in 2^14-key chunks (the whole workgroup),
+// staged in the workgroup's scratch of 2^16 words.
 template <bool MELD_LO, bool MELD_HI>
-__device__ void sort_two_halves(uint32_t *__restrict__ keys, uint32_t *s,
-                                uint32_t *__restrict__ pad, uint32_t lo, uint32_t len) {
-    constexpr uint32_t T = kSegTile;
-    const uint32_t tid = threadIdx.x;
-    // Position q of the padded segment: the caller's keys below len, the
-    // workgroup's pad scratch above (q - len < 2^16 - len < 2^15).
-    auto at = [&](uint32_t q) -> uint32_t * { return q < len ? keys + lo + q : pad + (q - len); };
-    // Phases 2 .. 2^15 on each half; bit 15 of the index makes the second
-    // half descending.
-    for (uint32_t h = 0; h < 2; ++h) {
-        for (uint32_t p = tid; p < T; p += kSegThreads) {
-            const uint32_t q = h * T + p;
-            s[p] = q < len ? keys[lo + q] : kPad;
+__device__ void sort_chunked(uint32_t *__restrict__ keys, uint32_t *s, uint32_t *__restrict__ work,
+                             uint32_t lo, uint32_t len, uint32_t m, uint32_t tid) {
+    const uint32_t chunks = 1u << (m - kSegLogChunk);
+#pragma unroll 1
+    for (uint32_t h = 0; h < chunks; ++h)
+        team_sort<MELD_LO, MELD_HI>(keys, work, s, lo, len, kSegLogChunk, h << kSegLogChunk, tid);
+#pragma unroll 1
+    for (uint32_t p = kSegLogChunk + 1; p <= m; ++p) {
+        seg_global_steps(work, m, p, tid);
+#pragma unroll 1
+        for (uint32_t h = 0; h < chunks; ++h) {
+            const uint32_t cbase = h << kSegLogChunk;
+            chunk_merge(keys, work, s, lo, len, cbase, tid, ((cbase >> p) & 1u) == 0, p == m);
         }
-        __syncthreads();
-        lds_network<uint32_t, MELD_LO, MELD_HI, kSegThreads, true>(s, T, h * T, 1, kSegLogTile,
-                                                                   0, -1, tid);
-        __syncthreads();
-        for (uint32_t p = tid; p < T; p += kSegThreads) *at(h * T + p) = s[p];
-        __syncthreads();
-    }
-    // Phase 2^16, step j = 2^15: ascending (bit 16 of every index is 0).
-    for (uint32_t i = tid; i < T; i += kSegThreads) {
-        uint32_t *pa = at(i);
-        uint32_t *pb = at(i + T);
-        const uint32_t a = *pa;
-        const uint32_t b = *pb;
-        if (b < a) {
-            *pa = b;
-            *pb = a;
-        }
-    }
-    __syncthreads();
-    // Phase 2^16, steps j = 2^14 .. 1 on each half; padding stays at the end.
-    for (uint32_t h = 0; h < 2; ++h) {
-        for (uint32_t p = tid; p < T; p += kSegThreads) s[p] = *at(h * T + p);
-        __syncthreads();
-        lds_network<uint32_t, MELD_LO, MELD_HI, kSegThreads, true>(
-            s, T, h * T, kSegLogTile + 1, kSegLogTile + 1, kSegLogTile - 1, -1, tid);
-        __syncthreads();
-        for (uint32_t p = tid; p < T && h * T + p < len; p += kSegThreads)
-            keys[lo + h * T + p] = s[p];
-        __syncthreads();
     }
 }
 
@@ -204,14 +403,14 @@ __global__ __launch_bounds__(kSegThreads) void seg_sort_kernel(uint32_t *__restr
                                                                const uint32_t *__restrict__ off,
                                                                const uint32_t *__restrict__ queue,
                                                                SegState *st,
-                                                               uint32_t *__restrict__ pad_all) {
+                                                               uint32_t *__restrict__ work_all) {
     extern __shared__ __align__(16) uint32_t s[];
     __shared__ uint32_t item_sh;
     if (st->flag != 0) return;  // invalid offsets: leave the keys untouched
     const uint32_t n_items = st->n_items;
     const uint32_t n_big = st->n_big;
     const uint32_t n_small = st->n_small;
-    uint32_t *pad = pad_all + (size_t)blockIdx.x * kSegTile;
+    uint32_t *work = work_all + (size_t)blockIdx.x * kSegWorkWords;
     const uint32_t tid = threadIdx.x;
     for (;;) {
         if (tid == 0) item_sh = atomicAdd(&st->head, 1u);
@@ -220,18 +419,37 @@ __global__ __launch_bounds__(kSegThreads) void seg_sort_kernel(uint32_t *__restr
         __syncthreads();
         if (item >= n_items) break;  // every wave of every workgroup reaches this
         if (item < n_big) {
-            const uint32_t seg = queue[item];
-            const uint32_t lo = off[seg];
-            const uint32_t len = off[seg + 1] - lo;
-            const uint32_t m = ceil_log2(len);
-            if (m <= kSegLogTile)
-                sort_in_lds<MELD_LO, MELD_HI>(keys, s, lo, len, m);
-            else
-                sort_two_halves<MELD_LO, MELD_HI>(keys, s, pad, lo, len);
+            // the class whose items hold this one (classes 16 .. 8 in order)
+            uint32_t c = kSmallClassMax + 1;
+            for (uint32_t k = kSegClasses - 1; k > kSmallClassMax; --k) {
+                const uint32_t first = st->item_base[k];
+                if (item >= first && item < first + class_items(k, st->cnt[k])) {
+                    c = k;
+                    break;
+                }
+            }
+            const uint32_t k = item - st->item_base[c];
+            if (c > kSegLogChunk) {
+                const uint32_t seg = queue[st->base[c] + k];
+                const uint32_t lo = off[seg];
+                sort_chunked<MELD_LO, MELD_HI>(keys, s, work, lo, off[seg + 1] - lo, c, tid);
+            } else {
+                const uint32_t lt = c - 4;
+                const uint32_t team = tid >> lt, t = tid & ((1u << lt) - 1);
+                const uint32_t qi = (k << (kSegLogChunk - c)) + team;
+                uint32_t lo = 0, len = 0;  // a team past the class's last segment idles
+                if (qi < st->cnt[c]) {
+                    const uint32_t seg = queue[st->base[c] + qi];
+                    lo = off[seg];
+                    len = off[seg + 1] - lo;
+                }
+                team_sort<MELD_LO, MELD_HI>(keys, nullptr, s + team * (17u << lt), lo, len, c, 0,
+                                            t);
+            }
         } else {
             const uint32_t w = tid >> 6;
-            const uint32_t qi = n_big + (item - n_big) * kWavesPerBlock + w;
-            if (qi < n_big + n_small) {
+            const uint32_t qi = st->base[kSmallClassMax] + (item - n_big) * kWavesPerBlock + w;
+            if (qi < st->base[kSmallClassMax] + n_small) {
                 const uint32_t seg = queue[qi];
                 const uint32_t lo = off[seg];
                 sort_small<MELD_LO, MELD_HI>(keys, s + w * kSmallMax, lo, off[seg + 1] - lo,
@@ -244,9 +462,9 @@ __global__ __launch_bounds__(kSegThreads) void seg_sort_kernel(uint32_t *__restr
 
 template <bool LO, bool HI>
 hipError_t launch_sort_t(uint32_t *keys, const uint32_t *off, const uint32_t *queue, SegState *st,
-                         uint32_t *pad, uint32_t grid, hipStream_t stream) {
+                         uint32_t *work, uint32_t grid, hipStream_t stream) {
     hipLaunchKernelGGL((seg_sort_kernel<LO, HI>), dim3(grid), dim3(kSegThreads),
-                       kSegTile * sizeof(uint32_t), stream, keys, off, queue, st, pad);
+                       kSegLdsWords * sizeof(uint32_t), stream, keys, off, queue, st, work);
     return hipGetLastError();
 }
 
@@ -254,7 +472,7 @@ template <bool LO, bool HI>
 hipError_t allow_big_lds() {
     return hipFuncSetAttribute(reinterpret_cast<const void *>(seg_sort_kernel<LO, HI>),
                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)(kSegTile * sizeof(uint32_t)));
+                               (int)(kSegLdsWords * sizeof(uint32_t)));
 }
 
 }  // namespace
@@ -270,7 +488,7 @@ hipError_t seg_sort_grid(int device, uint32_t *grid) {
         if (r != hipSuccess) return r;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
         &per_cu, reinterpret_cast<const void *>(seg_sort_kernel<true, true>), kSegThreads,
-        kSegTile * sizeof(uint32_t));
+        kSegLdsWords * sizeof(uint32_t));
     if (e != hipSuccess) return e;
     if (per_cu < 1) per_cu = 1;
     *grid = (uint32_t)(cus * per_cu);
@@ -278,7 +496,7 @@ hipError_t seg_sort_grid(int device, uint32_t *grid) {
 }
 
 hipError_t launch_segmented_sort(uint32_t *keys, const uint32_t *off, uint32_t nseg,
-                                 SegState *st, uint8_t *cls, uint32_t *queue, uint32_t *pad,
+                                 SegState *st, uint8_t *cls, uint32_t *queue, uint32_t *work,
                                  uint32_t grid, bool meld_lo, bool meld_hi, hipStream_t stream) {
     if (nseg == 0) return hipSuccess;
     const uint32_t blocks = (nseg + 255) / 256;
@@ -291,10 +509,10 @@ hipError_t launch_segmented_sort(uint32_t *keys, const uint32_t *off, uint32_t n
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (meld_lo)
-        return meld_hi ? launch_sort_t<true, true>(keys, off, queue, st, pad, grid, stream)
-                       : launch_sort_t<true, false>(keys, off, queue, st, pad, grid, stream);
-    return meld_hi ? launch_sort_t<false, true>(keys, off, queue, st, pad, grid, stream)
-                   : launch_sort_t<false, false>(keys, off, queue, st, pad, grid, stream);
+        return meld_hi ? launch_sort_t<true, true>(keys, off, queue, st, work, grid, stream)
+                       : launch_sort_t<true, false>(keys, off, queue, st, work, grid, stream);
+    return meld_hi ? launch_sort_t<false, true>(keys, off, queue, st, work, grid, stream)
+                   : launch_sort_t<false, false>(keys, off, queue, st, work, grid, stream);
 }
 
 }  // namespace meld

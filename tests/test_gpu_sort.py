@@ -222,3 +222,47 @@ def test_sort_tile_option_rejects_out_of_range(tile_option):
         with pytest.raises(meld.MeldError):
             tile_option(bad)
     tile_option(0)
+
+
+@pytest.mark.parametrize("pairs", [False, True])
+def test_gathered_passes_stage_parity(pairs, tile_option):
+    # Tiles of 2^8 in a 2^15 array: the last phase (k = 2^15) has 7
+    # streaming steps and runs them as one gathered LDS pass, the phase before
+    # has 6 (registers). Every step prefix of these two phases is checked.
+    _dev()
+    tile_option(8)
+    log_n = 15
+    n = 1 << log_n
+    keys = workloads.keys_u32(400 + pairs, n)
+    vals = workloads.iota_u32(n) if pairs else None
+    total = oracle.bitonic_num_steps(n)
+    for s in range(total - 15 - 14, total + 1):
+        ref = oracle.bitonic_emulate(keys, vals, max_steps=s)
+        for v in VARIANTS:
+            kd = _to_dev(keys)
+            vd = None if vals is None else _to_dev(vals)
+            meld.sort_steps(kd, vd, max_steps=s, variant=v)
+            torch.cuda.synchronize()
+            if pairs:
+                assert np.array_equal(_to_host(kd), ref[0]) and \
+                    np.array_equal(_to_host(vd), ref[1]), (s, v)
+            else:
+                assert np.array_equal(_to_host(kd), ref), (s, v)
+
+
+@pytest.mark.parametrize("log_t", [8, 9])
+@pytest.mark.parametrize("n", [1 << 17, (1 << 17) - 3, (1 << 18) + 5])
+def test_gathered_passes_full_sort(log_t, n, tile_option):
+    # Small tiles make phases with 7..10 streaming steps, so gathered passes
+    # (and their per-element tail path for ragged n) run.
+    _dev()
+    tile_option(log_t)
+    keys = workloads.keys_u32(500 + log_t, n)
+    vals = workloads.iota_u32(n)
+    ref = oracle.sort_u32(keys)
+    rk, rv = oracle.sort_pairs_u32(keys, vals)
+    for v in VARIANTS:
+        got, _ = _gpu_sort(keys, None, v)
+        assert np.array_equal(got, ref), (log_t, n, v)
+        gk, gv = _gpu_sort(keys, vals, v)
+        assert np.array_equal(gk, rk) and np.array_equal(gv, rv), (log_t, n, v)

@@ -69,20 +69,45 @@ def test_network_probe_matches_brute_force(log_t):
 
 
 def _segments_brute(lengths):
+    # The segmented kernel's lane mapping, written out with numpy: one wave of
+    # 64 consecutive comparators per segment of <= 128 keys; otherwise chunks
+    # of 2^cm keys (cm = min(class, 14)) sorted by a team of nt = 2^(cm-4)
+    # lanes that deals comparators t + i*nt in phases <= 2^6 and holds 16 keys
+    # per lane (direction: lane bit p-4) in the register phases.
     acc = [0, 0, 0, 0]
     for ln in lengths:
         if ln <= 1:
             continue
         log_p = int(np.ceil(np.log2(ln)))
         half = 1 << (log_p - 1)
-        c = np.arange(half)
+        cm = min(log_p, 14)
+        nt = 1 << max(cm - 4, 0)
+        chunks = 1 << (log_p - cm)
         for m in range(1, log_p + 1):
-            up = (((c << 1) >> m) & 1) == 0
             mixed_cmp = 0
-            for w in range(0, half, 64):
-                u = up[w:w + 64]
-                if u.any() and not u.all():
-                    mixed_cmp += u.size
+            if log_p <= 7:
+                c = np.arange(half)
+                up = ((c >> (m - 1)) & 1) == 0
+                for w in range(0, half, 64):
+                    u = up[w:w + 64]
+                    if u.any() and not u.all():
+                        mixed_cmp += u.size
+            elif m <= cm:
+                t = np.arange(nt)
+                if m <= 6:
+                    for i in range((1 << (cm - 1)) // nt):
+                        up = (((t + i * nt) >> (m - 1)) & 1) == 0
+                        for w in range(0, nt, 64):
+                            u = up[w:w + 64]
+                            if u.any() and not u.all():
+                                mixed_cmp += u.size
+                else:
+                    up = ((t >> (m - 4)) & 1) == 0
+                    for w in range(0, nt, 64):
+                        u = up[w:w + 64]
+                        if u.any() and not u.all():
+                            mixed_cmp += 8 * u.size
+                mixed_cmp *= chunks
             stage = 0 if (1 << m) <= 64 else 2
             acc[stage] += m * mixed_cmp
             acc[stage + 1] += m * half
@@ -90,7 +115,8 @@ def _segments_brute(lengths):
 
 
 def test_segments_probe_matches_brute_force():
-    lengths = [0, 1, 2, 3, 64, 65, 100, 128, 129, 300, 1000, 4096, 40000]
+    lengths = [0, 1, 2, 3, 64, 65, 100, 128, 129, 300, 600, 1000, 4096, 16384, 20000, 40000,
+               65536]
     off = np.concatenate([[0], np.cumsum(lengths)]).astype(np.uint32)
     assert meld.probe_segments(_to_dev(off)) == _segments_brute(lengths)
 
@@ -130,7 +156,9 @@ def test_auto_results_match_oracle_and_plans_are_recorded(tmp_path):
     for e in desc["entries"]:
         assert e["trials"] >= 3 and e["ms"] > 0
         if e["op"] == "segsort":
-            assert 0.0 <= e["mixed_lo"] <= 1.0 and e["mixed_hi"] == 0.0
+            # fractions of mixed comparator-steps per stage (the probe itself is
+            # pinned against brute force in test_segments_probe_matches_brute_force)
+            assert 0.0 <= e["mixed_lo"] <= 1.0 and 0.0 <= e["mixed_hi"] <= 1.0
     # the cache file round-trips into a fresh context without re-tuning
     saved = json.load(open(cache))
     assert len(saved["entries"]) == len(desc["entries"])
