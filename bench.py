@@ -128,7 +128,8 @@ def main():
         dst = torch.empty_like(src)
         dst.copy_(src)  # calibration copy: 256 MiB read + 256 MiB written
         for _ in range(3):
-            step()
+            for p in PS:
+                region(p, "melded")
         for p in PS:
             region(p, "divergent")
         for p in PS:
@@ -190,10 +191,31 @@ def main():
                   "speedup": round(same["divergent"] / same["melded"], 4),
                   "speedup_inplace": round(same["divergent"] / same["melded_inplace"], 4)}
 
-    dom = per_p["0.5"]
-    e_t = 0.5 * st["trips"] + 0.5 * sf["trips"]
-    alg_bytes = N_LANES * (8 + 4 * e_t)
-    achieved = alg_bytes / (dom["melded_us"] * 1e-6) / 1e9
+    # Sensitivity: other trip counts of the workload's range (8..32 per side),
+    # p = 0.5, canonical sides.
+    trips_sweep = {}
+    for tt, tf in ((8, 8), (8, 32), (32, 8), (20, 20), (32, 32)):
+        st_t, sf_t = dict(st, trips=tt), dict(sf, trips=tf)
+
+        def region_trips(variant):
+            meld.divergent_region(xd, td, SEED, thr[0.5], st_t, sf_t, variant=variant,
+                                  out=ys[0.5])
+
+        tm = {}
+        for v in ("divergent", "melded"):
+            region_trips(v)
+            tm[v] = float(np.median([_events_time(torch, lambda: region_trips(v), args.reps)
+                                     for _ in range(3)]))
+        trips_sweep[f"{tt},{tf}"] = {"divergent_us": round(tm["divergent"] * 1e3, 2),
+                                     "melded_us": round(tm["melded"] * 1e3, 2),
+                                     "speedup": round(tm["divergent"] / tm["melded"], 4)}
+
+    # Roofline of the dominant kernel over the timed region itself: the step is
+    # one melded launch per p, so its average launch takes ms_per_step / 3.
+    alg_step = sum(N_LANES * (8 + 4 * (p * st["trips"] + (1 - p) * sf["trips"])) for p in PS)
+    alg_bytes = alg_step / len(PS)
+    launch_us = ms_per_step * 1e3 / len(PS)
+    achieved = alg_bytes / (launch_us * 1e-6) / 1e9
 
     # Check the timed outputs of the step once (melded == divergent, bit for bit).
     for p in PS:
@@ -245,8 +267,10 @@ def main():
         },
         "melded_vs_divergent": per_p,
         "same_index_sides": same_index,
+        "trips_sweep_p0.5": trips_sweep,
         "roofline": {
-            "bound": "hbm", "kernel": "region_melded_kernel (p=0.5)",
+            "bound": "hbm", "kernel": "region_melded_kernel (timed step, one launch per p)",
+            "avg_launch_us": round(launch_us, 2),
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": _measured_traffic(),

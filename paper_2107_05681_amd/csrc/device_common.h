@@ -30,4 +30,14 @@ __host__ __device__ __forceinline__ uint64_t stream_key(uint64_t seed, uint64_t 
 // instructions out of the sides). Emits no instruction.
 #define MELD_SIDE_MARK(tag) asm volatile("; side " tag ::: "memory")
 
+// MI355X deals the workgroups of a launch to its 8 XCDs in turn (workgroup w
+// runs on XCD w mod 8), and each XCD has its own L2. This renumbering gives
+// every XCD one contiguous range of logical workgroups, so data that
+// neighbouring workgroups share stays in one L2. A bijection on [0, nb).
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_contiguous_block(uint32_t w, uint32_t nb) {
+    const uint32_t q = nb / kXcds, r = nb % kXcds, x = w % kXcds;
+    return x * q + (x < r ? x : r) + w / kXcds;
+}
+
 }  // namespace meld

@@ -26,7 +26,11 @@
 //
 // Both forms issue the gathers of a batch of consecutive steps before the
 // dependent fmas (the gathers do not depend on acc), and both keep the fma
-// order of the definition, so their results are bit-identical.
+// order of the definition, so their results are bit-identical. Lanes are
+// numbered so that each XCD runs one contiguous range of them: a table entry
+// read by lane i at step k is read again by lane i + step at step k - 1, and
+// with the hardware's round-robin placement such lanes would sit in another
+// XCD's L2 (table traffic 250 -> 135 MB per 2^24 lanes).
 #include "device_common.h"
 #include "kernels.h"
 
@@ -36,50 +40,79 @@ namespace {
 
 constexpr int kRegionThreads = 256;
 
-// Steps of one side. The gathers of B consecutive steps are issued before the
-// B dependent fmas (the gathers do not depend on acc); the last steps%B steps
-// issue their gathers back to back too (guards on the uniform count).
-template <int B, bool GUARDED_TAIL>
-__device__ __forceinline__ float side_steps_t(float acc, uint32_t idx, uint32_t steps, float a,
-                                              uint32_t step, const float *__restrict__ tab,
-                                              uint32_t mask) {
-    uint32_t k = 0;
-    for (; k + B <= steps; k += B) {
-        float g[B];
+// Gathers of G consecutive steps of one side, issued back to back (they do
+// not depend on acc); the fmas that consume them run afterwards.
+template <int G>
+__device__ __forceinline__ void gather_group(float (&g)[G], uint32_t idx, uint32_t step,
+                                             const float *__restrict__ tab, uint32_t mask) {
 #pragma unroll
-        for (int u = 0; u < B; ++u) g[u] = tab[(idx + (uint32_t)u * step) & mask];
+    for (int u = 0; u < G; ++u) g[u] = tab[(idx + (uint32_t)u * step) & mask];
+}
+
+template <int G>
+__device__ __forceinline__ float fma_group(float acc, float a, const float (&g)[G]) {
 #pragma unroll
-        for (int u = 0; u < B; ++u) acc = __builtin_fmaf(acc, a, g[u]);
-        idx += (uint32_t)B * step;
-    }
-    if constexpr (GUARDED_TAIL) {
-        const uint32_t rem = steps - k;
-        if (rem != 0) {
-            float g[B - 1];
-#pragma unroll
-            for (int u = 0; u < B - 1; ++u)
-                if ((uint32_t)u < rem) g[u] = tab[(idx + (uint32_t)u * step) & mask];
-#pragma unroll
-            for (int u = 0; u < B - 1; ++u)
-                if ((uint32_t)u < rem) acc = __builtin_fmaf(acc, a, g[u]);
-        }
-    } else {
-        for (; k < steps; ++k) {
-            acc = __builtin_fmaf(acc, a, tab[idx & mask]);
-            idx += step;
-        }
-    }
+    for (int u = 0; u < G; ++u) acc = __builtin_fmaf(acc, a, g[u]);
     return acc;
 }
 
-// Batch 8 with a guarded tail was the fastest divergent form in a sweep of
-// batch 4..32 at 2^24 lanes (larger batches lengthen the guarded tail).
-constexpr int kBatch = 8;
+// The gathers of a final chunk of c < 16 steps, in groups of 8, 4, 2 and 1 on
+// the bits of c (uniform branches), all issued before any of its fmas.
+struct Chunk {
+    float g8[8], g4[4], g2[2], g1[1];
+};
 
+__device__ __forceinline__ void gather_chunk(Chunk &ch, uint32_t c, uint32_t idx, uint32_t step,
+                                             const float *__restrict__ tab, uint32_t mask) {
+    if (c & 8) {
+        gather_group(ch.g8, idx, step, tab, mask);
+        idx += 8 * step;
+    }
+    if (c & 4) {
+        gather_group(ch.g4, idx, step, tab, mask);
+        idx += 4 * step;
+    }
+    if (c & 2) {
+        gather_group(ch.g2, idx, step, tab, mask);
+        idx += 2 * step;
+    }
+    if (c & 1) gather_group(ch.g1, idx, step, tab, mask);
+}
+
+__device__ __forceinline__ float fma_chunk(float acc, float a, const Chunk &ch, uint32_t c) {
+    if (c & 8) acc = fma_group(acc, a, ch.g8);
+    if (c & 4) acc = fma_group(acc, a, ch.g4);
+    if (c & 2) acc = fma_group(acc, a, ch.g2);
+    if (c & 1) acc = fma_group(acc, a, ch.g1);
+    return acc;
+}
+
+// Batches of 8 steps while at least 16 remain, then the last c < 16 steps as
+// one chunk with all its gathers in flight. From a sweep over trip counts
+// 8..32 on gfx950: batches of 8 beat longer ones for long loops, and a final
+// chunk issued whole beats a guarded remainder (10 trips: 8 + 2 in one chunk
+// ran 1.1-1.2x faster than a batch of 8 followed by a guarded tail).
+constexpr uint32_t kBatch = 8;
+constexpr uint32_t kChunkMax = 2 * kBatch;
+
+// Steps of one side.
 __device__ __forceinline__ float side_steps(float acc, uint32_t idx, uint32_t steps, float a,
                                             uint32_t step, const float *__restrict__ tab,
                                             uint32_t mask) {
-    return side_steps_t<kBatch, true>(acc, idx, steps, a, step, tab, mask);
+    uint32_t k = 0;
+    for (; k + kChunkMax <= steps; k += kBatch) {
+        float g[kBatch];
+        gather_group(g, idx, step, tab, mask);
+        acc = fma_group(acc, a, g);
+        idx += kBatch * step;
+    }
+    const uint32_t c = steps - k;
+    if (c != 0) {
+        Chunk ch;
+        gather_chunk(ch, c, idx, step, tab, mask);
+        acc = fma_chunk(acc, a, ch, c);
+    }
+    return acc;
 }
 
 __device__ __forceinline__ bool branch_taken(uint64_t bkey, uint32_t i, uint64_t thr) {
@@ -89,7 +122,8 @@ __device__ __forceinline__ bool branch_taken(uint64_t bkey, uint32_t i, uint64_t
 __global__ __launch_bounds__(kRegionThreads) void region_divergent_kernel(
     const float *__restrict__ x, float *__restrict__ y, uint32_t n, const float *__restrict__ tab,
     uint32_t mask, uint64_t bkey, uint64_t thr, RegionSide T, RegionSide F) {
-    const uint32_t i = blockIdx.x * kRegionThreads + threadIdx.x;
+    const uint32_t i =
+        xcd_contiguous_block(blockIdx.x, gridDim.x) * kRegionThreads + threadIdx.x;
     if (i >= n) return;
     const bool taken = branch_taken(bkey, i, thr);
     float acc = x[i];
@@ -108,46 +142,37 @@ __global__ __launch_bounds__(kRegionThreads) void region_divergent_kernel(
 // block per side (what unpredication makes of consecutive unaligned
 // instructions), while the index arithmetic, the fma chain and the loop
 // control run once on the whole wave with the multiplier selected per lane.
-template <int B>
+// Same batching as side_steps.
 __device__ __forceinline__ float melded_common_steps(float acc, bool taken, uint32_t idx_t,
                                                      uint32_t idx_f, uint32_t steps, float a,
                                                      uint32_t step_t, uint32_t step_f,
                                                      const float *__restrict__ tab,
                                                      uint32_t mask) {
     uint32_t k = 0;
-    for (; k + B <= steps; k += B) {
-        float g[B];
+    for (; k + kChunkMax <= steps; k += kBatch) {
+        float g[kBatch];
         if (taken) {
             MELD_SIDE_MARK("gathers true");
-#pragma unroll
-            for (int u = 0; u < B; ++u) g[u] = tab[(idx_t + (uint32_t)u * step_t) & mask];
+            gather_group(g, idx_t, step_t, tab, mask);
         } else {
             MELD_SIDE_MARK("gathers false");
-#pragma unroll
-            for (int u = 0; u < B; ++u) g[u] = tab[(idx_f + (uint32_t)u * step_f) & mask];
+            gather_group(g, idx_f, step_f, tab, mask);
         }
-#pragma unroll
-        for (int u = 0; u < B; ++u) acc = __builtin_fmaf(acc, a, g[u]);
-        idx_t += (uint32_t)B * step_t;
-        idx_f += (uint32_t)B * step_f;
+        acc = fma_group(acc, a, g);
+        idx_t += kBatch * step_t;
+        idx_f += kBatch * step_f;
     }
-    const uint32_t rem = steps - k;
-    if (rem != 0) {
-        float g[B - 1];
+    const uint32_t c = steps - k;
+    if (c != 0) {
+        Chunk ch;
         if (taken) {
             MELD_SIDE_MARK("gathers true");
-#pragma unroll
-            for (int u = 0; u < B - 1; ++u)
-                if ((uint32_t)u < rem) g[u] = tab[(idx_t + (uint32_t)u * step_t) & mask];
+            gather_chunk(ch, c, idx_t, step_t, tab, mask);
         } else {
             MELD_SIDE_MARK("gathers false");
-#pragma unroll
-            for (int u = 0; u < B - 1; ++u)
-                if ((uint32_t)u < rem) g[u] = tab[(idx_f + (uint32_t)u * step_f) & mask];
+            gather_chunk(ch, c, idx_f, step_f, tab, mask);
         }
-#pragma unroll
-        for (int u = 0; u < B - 1; ++u)
-            if ((uint32_t)u < rem) acc = __builtin_fmaf(acc, a, g[u]);
+        acc = fma_chunk(acc, a, ch, c);
     }
     return acc;
 }
@@ -171,14 +196,15 @@ __device__ __forceinline__ float longer_side_steps(float acc, uint32_t i, bool t
 __global__ __launch_bounds__(kRegionThreads) void region_melded_kernel(
     const float *__restrict__ x, float *__restrict__ y, uint32_t n, const float *__restrict__ tab,
     uint32_t mask, uint64_t bkey, uint64_t thr, RegionSide T, RegionSide F) {
-    const uint32_t i = blockIdx.x * kRegionThreads + threadIdx.x;
+    const uint32_t i =
+        xcd_contiguous_block(blockIdx.x, gridDim.x) * kRegionThreads + threadIdx.x;
     if (i >= n) return;
     const bool taken = branch_taken(bkey, i, thr);
     const float a = taken ? T.a : F.a;  // differing operand of the aligned fma: a select
     const uint32_t common = T.trips < F.trips ? T.trips : F.trips;
     float acc = x[i];
-    acc = melded_common_steps<kBatch>(acc, taken, i + T.off, i + F.off, common, a,
-                                                 T.step, F.step, tab, mask);
+    acc = melded_common_steps(acc, taken, i + T.off, i + F.off, common, a, T.step, F.step, tab,
+                              mask);
     y[i] = longer_side_steps(acc, i, taken, tab, mask, T, F, common);
 }
 
@@ -191,7 +217,8 @@ __global__ __launch_bounds__(kRegionThreads) void region_melded_kernel(
 __global__ __launch_bounds__(kRegionThreads) void region_melded_inplace_kernel(
     const float *__restrict__ x, float *__restrict__ y, uint32_t n, const float *__restrict__ tab,
     uint32_t mask, uint64_t bkey, uint64_t thr, RegionSide T, RegionSide F) {
-    const uint32_t i = blockIdx.x * kRegionThreads + threadIdx.x;
+    const uint32_t i =
+        xcd_contiguous_block(blockIdx.x, gridDim.x) * kRegionThreads + threadIdx.x;
     if (i >= n) return;
     const bool taken = branch_taken(bkey, i, thr);
     const float a = taken ? T.a : F.a;
