@@ -501,21 +501,22 @@ __global__ __launch_bounds__(1 << (L - 4)) void bitonic_sort_regs_kernel(SortArr
     __syncthreads();
     int32_t left = step_limit < 0 ? 0x7FFFFFFF : step_limit - lo_steps;
 
-    bool natural = true;  // e's values still sit in s in natural order
-    uint32_t prev = 0;
+    // Phase 2^7 starts in window 3 (element bits 3..6), read from the natural
+    // order the comparator network leaves in s.
+    uint32_t prev = 3;
+    {
+        const uint32_t tb = window_tpart(t, prev);
+#pragma unroll
+        for (int r = 0; r < kMergeE; ++r) e[r] = s[tb | ((uint32_t)r << prev)];
+        __syncthreads();
+    }
     for (uint32_t m = 7; m <= (uint32_t)L; ++m) {
         const bool up = (((base >> m) | (t >> (m - 4))) & 1u) == 0;
         for (uint32_t w = 1;; ++w) {
             const uint32_t B = m > 4 * w ? m - 4 * w : 0;
             const int hi_q = (int)(m - 4 * (w - 1) - 1 - B);
-            const uint32_t tb = window_tpart(t, B);
-            if (natural) {
-#pragma unroll
-                for (int r = 0; r < kMergeE; ++r) e[r] = s[tb | ((uint32_t)r << B)];
-                __syncthreads();
-                natural = false;
-            } else {
-                const uint32_t tp = window_tpart(t, prev);
+            if (B != prev) {
+                const uint32_t tp = window_tpart(t, prev), tb = window_tpart(t, B);
 #pragma unroll
                 for (int r = 0; r < kMergeE; ++r) s[merge_phys(tp | ((uint32_t)r << prev))] = e[r];
                 __syncthreads();
@@ -560,7 +561,7 @@ hipError_t launch_merge_l(const SortArray &a, uint32_t n_tiles, uint32_t m, int3
 // largest size of the element type (2^13 pairs, 2^14 keys: 64 KiB).
 template <bool PAIRS>
 constexpr int gather_log() {
-    return PAIRS ? kMaxLogTilePairs : kMaxLogTileKeys;
+    return PAIRS ? kGatherLogPairs : kGatherLogKeys;
 }
 
 template <bool PAIRS, int R>

@@ -137,5 +137,8 @@ hipError_t launch_segmented_sort(uint32_t *keys, const uint32_t *off, uint32_t n
 // Largest tile (log2 elements) the tile kernel supports for keys / pairs.
 constexpr uint32_t kMaxLogTileKeys = 14;
 constexpr uint32_t kMaxLogTilePairs = 13;
+// Tile of the gathered streaming passes: 64 KiB of elements.
+constexpr uint32_t kGatherLogKeys = 14;
+constexpr uint32_t kGatherLogPairs = 13;
 
 }  // namespace meld

@@ -442,7 +442,7 @@ meld_status sort_impl(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n
     if (e != hipSuccess) return hip_fail(e, "bitonic tile launch");
 
     const uint32_t max_gather = pairs ? meld::kMaxGatherStepsPairs : meld::kMaxGatherStepsKeys;
-    const uint32_t gather_log = max_log_tile(pairs);
+    const uint32_t gather_log = pairs ? meld::kGatherLogPairs : meld::kGatherLogKeys;
     for (uint32_t m = log_t + 1; m <= log_n; ++m) {
         // Steps j = 2^(m-1) .. 2^log_t stream through HBM in as few passes as
         // possible: up to kMaxFusedSteps per pass in registers, more (high

@@ -111,9 +111,9 @@ __device__ __forceinline__ int32_t lds_network(E *s, uint32_t T, uint32_t base, 
     return steps;
 }
 
-// One step (k = 2^m, j) with ITERS comparators per lane: lane0, lane0 + nt,
-// ... (a tile of 2 * ITERS * nt elements). All loads of a lane's comparators
-// are issued before its first compare, so their LDS latency overlaps.
+// One group of ITERS comparators of a step (k = 2^m, j) per lane: lane0,
+// lane0 + nt, ... All loads of the group are issued before its first compare,
+// so their LDS latency overlaps.
 //   melded: one load pair per comparator, both compares, a select of the swap
 //     condition on the direction, one conditional store pair;
 //   divergent: Figure 1's if/else. With nt >= 64 the direction of a phase
@@ -122,8 +122,8 @@ __device__ __forceinline__ int32_t lds_network(E *s, uint32_t T, uint32_t base, 
 //     unswitched) and each side holds its own batched loads, compares and
 //     swap stores; with nt < 64 it stays per comparator.
 template <typename E, bool MELDED, int ITERS>
-__device__ __forceinline__ void lds_step_batched(E *s, uint32_t base, uint32_t m, uint32_t j,
-                                                 uint32_t lane0, uint32_t nt) {
+__device__ __forceinline__ void lds_step_group(E *s, uint32_t base, uint32_t m, uint32_t j,
+                                               uint32_t lane0, uint32_t nt) {
     uint32_t lo[ITERS];
 #pragma unroll
     for (int i = 0; i < ITERS; ++i) {
@@ -184,6 +184,19 @@ __device__ __forceinline__ void lds_step_batched(E *s, uint32_t base, uint32_t m
         for (int i = 0; i < ITERS; ++i)
             cex_divergent(s, lo[i], lo[i] + j, (((base | lo[i]) >> m) & 1u) == 0);
     }
+}
+
+// The comparators of a step in groups of at most 4 (bounding the registers a
+// group holds in flight; 4 loads per comparator pair in flight per lane
+// already cover the LDS latency).
+template <typename E, bool MELDED, int ITERS>
+__device__ __forceinline__ void lds_step_batched(E *s, uint32_t base, uint32_t m, uint32_t j,
+                                                 uint32_t lane0, uint32_t nt) {
+    constexpr int G = ITERS < 4 ? ITERS : 4;
+    static_assert(ITERS % G == 0, "comparators per lane must split into groups");
+#pragma unroll
+    for (int h = 0; h < ITERS / G; ++h)
+        lds_step_group<E, MELDED, G>(s, base, m, j, lane0 + (uint32_t)(h * G) * nt, nt);
 }
 
 // Phases k = 2 .. 2^m_end (m_end <= 6) of the network on a tile of

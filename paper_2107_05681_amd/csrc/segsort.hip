@@ -218,23 +218,16 @@ __global__ __launch_bounds__(256) void seg_scatter_kernel(uint32_t nseg,
 
 // Steps of phase k = 2^p on element bits hi_bit .. 0 of a tile held in
 // registers, 16 per lane (lane t of the tile's nt lanes): windows with bases
-// hi_bit-3, hi_bit-7, ... (clamped at 0). cur is the window e is in; natural:
-// e is still only in s, in natural order (the first window reads it there).
+// hi_bit-3, hi_bit-7, ... (clamped at 0). cur is the window e is in.
 template <bool MELDED>
 __device__ __forceinline__ void phase_windows(uint32_t (&e)[kSegE], uint32_t *s, uint32_t t,
-                                              uint32_t &cur, bool &natural, int hi_bit, bool up) {
+                                              uint32_t &cur, int hi_bit, bool up) {
     int32_t unlimited = 0x7FFFFFFF;
 #pragma unroll 1
     for (int top = hi_bit; top >= 0;) {
         const uint32_t B = top >= 3 ? (uint32_t)(top - 3) : 0u;
-        const uint32_t tb = window_tpart(t, B);
-        if (natural) {
-#pragma unroll
-            for (int r = 0; r < kSegE; ++r) e[r] = s[tb | ((uint32_t)r << B)];
-            __syncthreads();
-            natural = false;
-        } else if (B != cur) {
-            const uint32_t tp = window_tpart(t, cur);
+        if (B != cur) {
+            const uint32_t tp = window_tpart(t, cur), tb = window_tpart(t, B);
 #pragma unroll
             for (int r = 0; r < kSegE; ++r) s[padded(tp | ((uint32_t)r << cur))] = e[r];
             __syncthreads();
@@ -285,12 +278,19 @@ __device__ __forceinline__ void team_sort(uint32_t *__restrict__ keys,
     __syncthreads();
     lds_network_low<uint32_t, MELD_LO, 8>(s, cbase, 6, t, 1u << lt, -1);
     __syncthreads();
-    uint32_t cur = 0;
-    bool natural = true;
+    // Phase 2^7 starts in window 3 (element bits 3..6), read from the natural
+    // order the comparator network leaves in s.
+    uint32_t cur = 3;
+    {
+        const uint32_t tb = window_tpart(t, cur);
+#pragma unroll
+        for (int r = 0; r < kSegE; ++r) e[r] = s[tb | ((uint32_t)r << cur)];
+        __syncthreads();
+    }
 #pragma unroll 1
     for (uint32_t p = 7; p <= m; ++p) {
         const bool up = (((cbase >> p) | (t >> (p - 4))) & 1u) == 0;
-        phase_windows<MELD_HI>(e, s, t, cur, natural, (int)p - 1, up);
+        phase_windows<MELD_HI>(e, s, t, cur, (int)p - 1, up);
     }
     to_window(e, s, t, cur, lt);
     if (work != nullptr) {
@@ -349,8 +349,7 @@ __device__ void chunk_merge(uint32_t *__restrict__ keys, uint32_t *__restrict__ 
 #pragma unroll
     for (int r = 0; r < kSegE; ++r) e[r] = work[cbase + (t | ((uint32_t)r << lt))];
     uint32_t cur = lt;
-    bool natural = false;
-    phase_windows<true>(e, s, t, cur, natural, (int)kSegLogChunk - 1, up);
+    phase_windows<true>(e, s, t, cur, (int)kSegLogChunk - 1, up);
     to_window(e, s, t, cur, lt);
     if (last) {
 #pragma unroll
