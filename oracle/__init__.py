@@ -23,6 +23,11 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
+class SideRange(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_float), ("off", ctypes.c_uint32), ("step", ctypes.c_uint32),
+                ("trips_lo", ctypes.c_uint32), ("trips_hi", ctypes.c_uint32)]
+
+
 class Side(ctypes.Structure):
     _fields_ = [("a", ctypes.c_float), ("off", ctypes.c_uint32),
                 ("step", ctypes.c_uint32), ("trips", ctypes.c_uint32)]
@@ -63,6 +68,14 @@ def _load():
         lib.oracle_bitonic_emulate.restype = ctypes.c_int
         lib.oracle_region_f32.argtypes = [vp, vp, u64, sz, vp, sz, u64, u64, Side, Side]
         lib.oracle_region_f32.restype = ctypes.c_int
+        lib.oracle_region3_f32.argtypes = [vp, vp, u64, sz, vp, sz, u64, u64, u64, Side, Side,
+                                           Side]
+        lib.oracle_region3_f32.restype = ctypes.c_int
+        lib.oracle_lane_trips.argtypes = [u64, u64, u32, u32]
+        lib.oracle_lane_trips.restype = u32
+        lib.oracle_region_lanetrips_f32.argtypes = [vp, vp, u64, sz, vp, sz, u64, u64, SideRange,
+                                                    SideRange]
+        lib.oracle_region_lanetrips_f32.restype = ctypes.c_int
         lib.oracle_count_true.argtypes = [u64, u64, u64, sz]
         lib.oracle_count_true.restype = u64
         lib.oracle_mixed_waves.argtypes = [u64, u64, sz, u32]
@@ -149,6 +162,43 @@ def region_f32_into(x: np.ndarray, y: np.ndarray, tab: np.ndarray, seed: int, th
     """Unchecked variant writing into a caller-owned y (used to time the oracle in chunks)."""
     _load().oracle_region_f32(x.ctypes.data, y.ctypes.data, i0, x.size, tab.ctypes.data,
                               tab.size, seed, thr, _side(side_true), _side(side_false))
+
+
+def region3_f32(x, tab, seed: int, thr0: int, thr1: int, s0: dict, s1: dict, s2: dict,
+                i0: int = 0) -> np.ndarray:
+    """Lanes i0 .. i0+len(x)-1 of the three-way region."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    tab = np.ascontiguousarray(tab, dtype=np.float32)
+    y = np.empty_like(x)
+    rc = _load().oracle_region3_f32(x.ctypes.data, y.ctypes.data, i0, x.size, tab.ctypes.data,
+                                    tab.size, seed, thr0, thr1, _side(s0), _side(s1), _side(s2))
+    if rc != 0:
+        raise ValueError("table length must be a power of two and thr0 <= thr1 <= 2^32")
+    return y
+
+
+def _side_range(d) -> "SideRange":
+    return SideRange(float(d["a"]), int(d["off"]), int(d["step"]), int(d["trips_lo"]),
+                     int(d["trips_hi"]))
+
+
+def lane_trips(seed: int, i: int, lo: int, hi: int) -> int:
+    return int(_load().oracle_lane_trips(seed, i, lo, hi))
+
+
+def region_lanetrips_f32(x, tab, seed: int, thr: int, side_true: dict, side_false: dict,
+                         i0: int = 0) -> np.ndarray:
+    """Lanes i0 .. i0+len(x)-1 of the two-sided region with per-lane trip counts
+    (sides given as dicts with a, off, step, trips_lo, trips_hi)."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    tab = np.ascontiguousarray(tab, dtype=np.float32)
+    y = np.empty_like(x)
+    rc = _load().oracle_region_lanetrips_f32(x.ctypes.data, y.ctypes.data, i0, x.size,
+                                             tab.ctypes.data, tab.size, seed, thr,
+                                             _side_range(side_true), _side_range(side_false))
+    if rc != 0:
+        raise ValueError("table length must be a power of two, thr <= 2^32, lo <= hi")
+    return y
 
 
 def count_true(seed: int, thr: int, n: int, i0: int = 0) -> int:

@@ -17,6 +17,11 @@
  *    divergent branch whose sides hold similar instruction sequences; the
  *    melded form must compute the same values). One fused multiply-add per
  *    step, correctly rounded (std::fma).
+ *  - oracle_region3_f32: the three-way variant (Evaluation section,
+ *    synthetic benchmark SB4, an if / else-if / else whose three blocks
+ *    compute alike), lane by lane in the source order.
+ *  - oracle_region_lanetrips_f32: the two-sided region with a trip count
+ *    drawn per lane (a loop whose exit itself diverges inside a wave).
  *  - oracle_mixed_waves: the share of 64-lane waves whose branch mask is
  *    neither all-true nor all-false (Background section: only such waves
  *    pay the IPDOM serialisation).
@@ -148,6 +153,60 @@ int oracle_region_f32(const float *x, float *y, uint64_t i0, size_t n, const flo
             }
         }
         y[j] = acc;
+    }
+    return 0;
+}
+
+// One side's loop, as written in the region's definition.
+static float run_side(float acc, uint64_t i, float a, uint32_t off, uint32_t step,
+                      uint32_t trips, const float *tab, uint32_t mask) {
+    for (uint32_t k = 0; k < trips; ++k) {
+        const uint32_t idx = ((uint32_t)i + off + k * step) & mask;
+        acc = std::fma(acc, a, tab[idx]);
+    }
+    return acc;
+}
+
+// Three-way region: lane i compares h = branch_hash(seed, i) >> 32 with the
+// two thresholds in the order of the if / else-if / else chain.
+int oracle_region3_f32(const float *x, float *y, uint64_t i0, size_t n, const float *tab,
+                       size_t tab_len, uint64_t seed, uint64_t thr0, uint64_t thr1,
+                       oracle_side s0, oracle_side s1, oracle_side s2) {
+    if (!is_pow2(tab_len) || thr0 > thr1 || thr1 > (1ull << 32)) return -1;
+    const uint32_t mask = (uint32_t)(tab_len - 1);
+    for (size_t j = 0; j < n; ++j) {
+        const uint64_t i = i0 + j;
+        const uint64_t h = branch_hash(seed, i) >> 32;
+        float acc = x[j];
+        if (h < thr0)
+            acc = run_side(acc, i, s0.a, s0.off, s0.step, s0.trips, tab, mask);
+        else if (h < thr1)
+            acc = run_side(acc, i, s1.a, s1.off, s1.step, s1.trips, tab, mask);
+        else
+            acc = run_side(acc, i, s2.a, s2.off, s2.step, s2.trips, tab, mask);
+        y[j] = acc;
+    }
+    return 0;
+}
+
+// Per-lane trip count: stream (seed, 11) of the counter generator.
+uint32_t oracle_lane_trips(uint64_t seed, uint64_t i, uint32_t lo, uint32_t hi) {
+    const uint64_t h = mix64(mix64(seed + 11 * kGolden) + i) >> 32;
+    return lo + (uint32_t)(h % ((uint64_t)hi - lo + 1));
+}
+
+int oracle_region_lanetrips_f32(const float *x, float *y, uint64_t i0, size_t n,
+                                const float *tab, size_t tab_len, uint64_t seed, uint64_t thr,
+                                oracle_side_range side_true, oracle_side_range side_false) {
+    if (!is_pow2(tab_len) || thr > (1ull << 32) || side_true.trips_lo > side_true.trips_hi ||
+        side_false.trips_lo > side_false.trips_hi)
+        return -1;
+    const uint32_t mask = (uint32_t)(tab_len - 1);
+    for (size_t j = 0; j < n; ++j) {
+        const uint64_t i = i0 + j;
+        const oracle_side_range &s = branch_true(seed, thr, i) ? side_true : side_false;
+        const uint32_t t = oracle_lane_trips(seed, i, s.trips_lo, s.trips_hi);
+        y[j] = run_side(x[j], i, s.a, s.off, s.step, t, tab, mask);
     }
     return 0;
 }

@@ -42,6 +42,35 @@ int oracle_region_f32(const float *x, float *y, uint64_t i0, size_t n, const flo
                       size_t tab_len, uint64_t seed, uint64_t thr, oracle_side side_true,
                       oracle_side side_false);
 
+/* Three-way region (Evaluation section, synthetic benchmark SB4: an
+ * if / else-if / else whose three blocks compute alike on different data).
+ * Lane i takes side 0 when (branch_hash >> 32) < thr0, side 1 when it is
+ * below thr1, side 2 otherwise (thr0 <= thr1 <= 2^32), then runs that side's
+ * loop as oracle_region_f32 does. */
+int oracle_region3_f32(const float *x, float *y, uint64_t i0, size_t n, const float *tab,
+                       size_t tab_len, uint64_t seed, uint64_t thr0, uint64_t thr1,
+                       oracle_side s0, oracle_side s1, oracle_side s2);
+
+/* A side whose trip count varies per lane within [trips_lo, trips_hi]. */
+typedef struct {
+    float a;
+    uint32_t off;
+    uint32_t step;
+    uint32_t trips_lo;
+    uint32_t trips_hi;
+} oracle_side_range;
+
+/* Trip count of lane i for a side with range [lo, hi]:
+ * lo + ((H(seed, 11, i) >> 32) mod (hi - lo + 1)). */
+uint32_t oracle_lane_trips(uint64_t seed, uint64_t i, uint32_t lo, uint32_t hi);
+
+/* Two-sided loop region whose loops run a per-lane trip count
+ * (oracle_lane_trips with the lane's side range); otherwise as
+ * oracle_region_f32. */
+int oracle_region_lanetrips_f32(const float *x, float *y, uint64_t i0, size_t n,
+                                const float *tab, size_t tab_len, uint64_t seed, uint64_t thr,
+                                oracle_side_range side_true, oracle_side_range side_false);
+
 uint64_t oracle_count_true(uint64_t seed, uint64_t thr, uint64_t i0, size_t n);
 uint64_t oracle_mixed_waves(uint64_t seed, uint64_t thr, size_t n, uint32_t wave);
 double oracle_mixed_fraction_closed_form(double p, uint32_t wave);

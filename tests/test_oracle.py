@@ -354,3 +354,129 @@ def test_mixed_waves_brute_force_small():
             w = bits[b:b + 64]
             mixed += 1 if (any(w) and not all(w)) else 0
         assert oracle.mixed_waves(seed, thr, n) == mixed
+
+
+# ---- three-way region (SB4-like) -------------------------------------------
+
+def _side3(seed, thr0, thr1, i):
+    golden = 0x9E3779B97F4A7C15
+    h = _py_mix64((_py_mix64((seed + 4 * golden) & M64) + i) & M64) >> 32
+    return 0 if h < thr0 else (1 if h < thr1 else 2)
+
+
+def _three_sides(t0, t1, t2, a=(0.5, 0.625, 0.75)):
+    return (dict(a=a[0], off=0, step=1031, trips=t0), dict(a=a[1], off=1 << 8, step=1543, trips=t1),
+            dict(a=a[2], off=1 << 9, step=2053, trips=t2))
+
+
+def test_region3_reduces_to_the_two_way_region():
+    # With one of the three ways empty the chain is the two-sided region.
+    L = 12
+    seed = 29
+    tab = workloads.tab_f32(seed, 1 << L)
+    x = workloads.x_f32(seed, 700)
+    s0, s1, s2 = _three_sides(7, 12, 9)
+    t_lo, t_hi = workloads.thr_from_p(0.3), workloads.thr_from_p(0.7)
+    # thr1 = 2^32: side 2 never taken
+    assert np.array_equal(oracle.region3_f32(x, tab, seed, t_lo, 1 << 32, s0, s1, s2),
+                          oracle.region_f32(x, tab, seed, t_lo, s0, s1))
+    # thr0 = 0: side 0 never taken
+    assert np.array_equal(oracle.region3_f32(x, tab, seed, 0, t_hi, s0, s1, s2),
+                          oracle.region_f32(x, tab, seed, t_hi, s1, s2))
+    # thr0 = thr1: the middle way is never taken (the biased three-way case)
+    assert np.array_equal(oracle.region3_f32(x, tab, seed, t_lo, t_lo, s0, s1, s2),
+                          oracle.region_f32(x, tab, seed, t_lo, s0, s2))
+
+
+def test_region3_trip_count_and_side_selection():
+    # a = 1, tab = 1, x = 0: y is the trip count of the lane's way, exactly;
+    # the way follows the if / else-if / else order of the two thresholds.
+    n = 4096
+    tab = np.ones(1 << 8, dtype=np.float32)
+    x = np.zeros(n, dtype=np.float32)
+    s0, s1, s2 = _three_sides(5, 9, 17, a=(1.0, 1.0, 1.0))
+    seed, thr0, thr1 = 31, workloads.thr_from_p(0.25), workloads.thr_from_p(0.6)
+    y = oracle.region3_f32(x, tab, seed, thr0, thr1, s0, s1, s2)
+    trips = (5.0, 9.0, 17.0)
+    expect = np.array([trips[_side3(seed, thr0, thr1, i)] for i in range(n)], dtype=np.float32)
+    assert np.array_equal(y, expect)
+    counts = [int(np.sum(y == t)) for t in trips]
+    assert counts[0] == oracle.count_true(seed, thr0, n)
+    assert counts[0] + counts[1] == oracle.count_true(seed, thr1, n)
+
+
+def test_region3_index_formula_with_zero_multiplier():
+    L = 12
+    tab = np.arange(1 << L, dtype=np.float32)
+    n = 300
+    x = workloads.x_f32(2, n)
+    s0, s1, s2 = _three_sides(7, 13, 4, a=(0.0, 0.0, 0.0))
+    seed, thr0, thr1 = 3, 1 << 30, 3 << 30
+    i0 = (1 << 32) - 150  # lane indices cross 2^32: index arithmetic wraps modulo 2^32
+    y = oracle.region3_f32(x, tab, seed, thr0, thr1, s0, s1, s2, i0=i0)
+    for j in range(n):
+        i = i0 + j
+        s = (s0, s1, s2)[_side3(seed, thr0, thr1, i)]
+        idx = (i + s["off"] + (s["trips"] - 1) * s["step"]) % (1 << 32) % (1 << L)
+        assert y[j] == np.float32(idx)
+
+
+def test_region3_rejects_bad_thresholds():
+    tab = np.ones(16, dtype=np.float32)
+    x = np.zeros(4, dtype=np.float32)
+    s0, s1, s2 = _three_sides(1, 2, 3)
+    with pytest.raises(ValueError):
+        oracle.region3_f32(x, tab, 1, 5, 4, s0, s1, s2)  # thr0 > thr1
+    with pytest.raises(ValueError):
+        oracle.region3_f32(x, tab, 1, 0, (1 << 32) + 1, s0, s1, s2)
+    with pytest.raises(ValueError):
+        oracle.region3_f32(x, np.ones(12, dtype=np.float32), 1, 0, 1, s0, s1, s2)
+
+
+# ---- per-lane trip counts --------------------------------------------------
+
+def test_lane_trips_is_tag11_stream_and_covers_its_range():
+    golden = 0x9E3779B97F4A7C15
+    seed, lo, hi = 7, 8, 32
+    vals = [oracle.lane_trips(seed, i, lo, hi) for i in range(5000)]
+    for i in (0, 1, 2, 4999):
+        h = _py_mix64((_py_mix64((seed + 11 * golden) & M64) + i) & M64) >> 32
+        assert vals[i] == lo + h % (hi - lo + 1)
+    assert min(vals) == lo and max(vals) == hi
+    assert set(vals) == set(range(lo, hi + 1))
+    # a degenerate range is a constant
+    assert all(oracle.lane_trips(seed, i, 9, 9) == 9 for i in range(50))
+
+
+def _range_sides(loT, hiT, loF, hiF, aT=0.5, aF=0.75):
+    return (dict(a=aT, off=0, step=1031, trips_lo=loT, trips_hi=hiT),
+            dict(a=aF, off=1 << 9, step=2053, trips_lo=loF, trips_hi=hiF))
+
+
+def test_lanetrips_with_fixed_trips_is_the_region():
+    L = 12
+    seed = 41
+    tab = workloads.tab_f32(seed, 1 << L)
+    x = workloads.x_f32(seed, 500)
+    thr = workloads.thr_from_p(0.4)
+    rt, rf = _range_sides(11, 11, 6, 6)
+    st, sf = _sides(11, 6, offF=1 << 9)
+    assert np.array_equal(oracle.region_lanetrips_f32(x, tab, seed, thr, rt, rf),
+                          oracle.region_f32(x, tab, seed, thr, st, sf))
+
+
+def test_lanetrips_counts_per_lane():
+    # a = 1, tab = 1, x = 0: y is the lane's own trip count, drawn in its
+    # side's range.
+    n = 3000
+    tab = np.ones(1 << 8, dtype=np.float32)
+    x = np.zeros(n, dtype=np.float32)
+    rt, rf = _range_sides(8, 16, 20, 32, aT=1.0, aF=1.0)
+    seed, thr = 43, workloads.thr_from_p(0.5)
+    y = oracle.region_lanetrips_f32(x, tab, seed, thr, rt, rf)
+    for i in range(n):
+        s = rt if _taken(seed, thr, i) else rf
+        assert y[i] == np.float32(oracle.lane_trips(seed, i, s["trips_lo"], s["trips_hi"]))
+        assert s["trips_lo"] <= y[i] <= s["trips_hi"]
+    with pytest.raises(ValueError):
+        oracle.region_lanetrips_f32(x, tab, seed, thr, _range_sides(5, 4, 1, 2)[0], rf)

@@ -66,3 +66,14 @@ def test_thr_from_p():
     assert workloads.thr_from_p(0.5) == 1 << 31
     assert workloads.thr_from_p(0.1) == 429496729
     assert workloads.thr_from_p(0.9) == 3865470566
+
+
+def test_way_trips_extend_the_two_sides():
+    for seed in (1, 2, 3, 99):
+        t_true, t_false = workloads.trips(seed)
+        assert workloads.way_trips(seed, 0) == t_true
+        assert workloads.way_trips(seed, 1) == t_false
+        assert all(8 <= workloads.way_trips(seed, w) <= 32 for w in range(3))
+    x, tab, w0, w1, w2 = workloads.region3_inputs(5, 100, tab_log2=12)
+    assert len(x) == 100 and len(tab) == 1 << 12
+    assert (w0["off"], w1["off"], w2["off"]) == (0, 1 << 10, 1 << 11)

@@ -14,7 +14,9 @@ section, "Synthetic Benchmarks"):
 * sort keys: ``H(seed,1,i) >> 32``, uniform u32; payload = original index.
 * region: ``x[i] = (H(seed,2,i) >> 40) * 2^-24``,
   ``tab[m] = 0.5 + (H(seed,3,m) >> 41) * 2^-24`` over a 2^24-entry table,
-  branch threshold ``thr = floor(p * 2^32)``, trip counts ``8 + H(seed,5,s) % 25``.
+  branch threshold ``thr = floor(p * 2^32)``, trip counts ``8 + H(seed,5,s) % 25``
+  for side (way) s; the three-way region uses ways 0, 1, 2 with thresholds
+  thr0 <= thr1; per-lane trip counts are drawn by the method itself (stream 11).
 * segments: lengths log-uniform in ``[2^lo, 2^hi]`` from ``H(seed,6,s)``.
 """
 from __future__ import annotations
@@ -35,6 +37,9 @@ _LIB = os.path.join(_HERE, "libmeldgen.so")
 REGION_TAB_LOG2 = 24
 SIDE_TRUE = dict(a=0.5, off=0, step=1031)
 SIDE_FALSE = dict(a=0.75, off=1 << 23, step=2053)
+# The middle way of the three-way region (if / else-if / else): ways 0, 1, 2
+# are SIDE_TRUE, SIDE_MID, SIDE_FALSE.
+SIDE_MID = dict(a=0.625, off=1 << 22, step=1543)
 
 _lib = None
 
@@ -67,6 +72,8 @@ def _load():
         lib.gen_x_f32.argtypes = [u64, u64, vp, sz]
         lib.gen_tab_f32.argtypes = [u64, vp, sz]
         lib.gen_trips.argtypes = [u64, ctypes.POINTER(u32), ctypes.POINTER(u32)]
+        lib.gen_way_trips.argtypes = [u64, u32]
+        lib.gen_way_trips.restype = u32
         lib.gen_segment_offsets.argtypes = [u64, u32, u32, u32, vp]
         lib.gen_segment_offsets.restype = u64
         lib.gen_uniform.argtypes = [u64, u64, u64]
@@ -115,6 +122,22 @@ def trips(seed: int) -> tuple[int, int]:
     t, f = ctypes.c_uint32(), ctypes.c_uint32()
     _load().gen_trips(seed, ctypes.byref(t), ctypes.byref(f))
     return int(t.value), int(f.value)
+
+
+def way_trips(seed: int, way: int) -> int:
+    """Trip count of way `way` of a multi-way region: 8 + H(seed, 5, way) % 25."""
+    return int(_load().gen_way_trips(seed, way))
+
+
+def region3_inputs(seed: int, n: int, tab_log2: int = REGION_TAB_LOG2):
+    """x, tab and the three ways (dicts with a, off, step, trips) of the three-way region."""
+    ways = [dict(SIDE_TRUE), dict(SIDE_MID), dict(SIDE_FALSE)]
+    for w, d in enumerate(ways):
+        d["trips"] = way_trips(seed, w)
+    if tab_log2 != REGION_TAB_LOG2:
+        ways[1]["off"] = 1 << (tab_log2 - 2)
+        ways[2]["off"] = 1 << (tab_log2 - 1)
+    return x_f32(seed, n), tab_f32(seed, 1 << tab_log2), ways[0], ways[1], ways[2]
 
 
 def segment_offsets(seed: int, nseg: int, lo_log2: int = 6, hi_log2: int = 16) -> np.ndarray:

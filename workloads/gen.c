@@ -76,6 +76,12 @@ void gen_trips(uint64_t seed, uint32_t *t_true, uint32_t *t_false) {
     *t_false = 8u + (uint32_t)(gen_hash(seed, 5, 1) % 25u);
 }
 
+/* Trip count of way s of a multi-way region: 8 + H(seed, 5, s) % 25 (ways 0
+ * and 1 are the two sides of gen_trips). */
+uint32_t gen_way_trips(uint64_t seed, uint32_t s) {
+    return 8u + (uint32_t)(gen_hash(seed, 5, s) % 25u);
+}
+
 /* Segment s has length clamp(floor(2^(lo + (hi - lo) * u)), 2^lo, 2^hi) with
  * u = (H(seed, 6, s) >> 11) * 2^-53 in [0, 1) (log-uniform lengths).
  * offsets has nseg + 1 entries, offsets[0] = 0. Returns the total length. */
