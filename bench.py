@@ -210,6 +210,8 @@ def main():
                                      "melded_us": round(tm["melded"] * 1e3, 2),
                                      "speedup": round(tm["divergent"] / tm["melded"], 4)}
 
+    variants = _bench_region_variants(torch, np, meld, workloads, xd, td, ys[0.5], args)
+
     # Roofline of the dominant kernel over the timed region itself: the step is
     # one melded launch per p, so its average launch takes ms_per_step / 3.
     alg_step = sum(N_LANES * (8 + 4 * (p * st["trips"] + (1 - p) * sf["trips"])) for p in PS)
@@ -268,6 +270,7 @@ def main():
         "melded_vs_divergent": per_p,
         "same_index_sides": same_index,
         "trips_sweep_p0.5": trips_sweep,
+        "region_variants": variants,
         "roofline": {
             "bound": "hbm", "kernel": "region_melded_kernel (timed step, one launch per p)",
             "avg_launch_us": round(launch_us, 2),
@@ -285,6 +288,45 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+
+
+def _bench_region_variants(torch, np, meld, workloads, xd, td, y, args):
+    """NEXT-row variants of the region at 2^24 lanes: the three-way region (SB4
+    pattern) with equal thirds, equal trip counts, and biased (the middle way
+    never taken); the two-sided region with per-lane trip counts in [8, 32]."""
+    w0 = dict(workloads.SIDE_TRUE, trips=workloads.way_trips(SEED, 0))
+    w1 = dict(workloads.SIDE_MID, trips=workloads.way_trips(SEED, 1))
+    w2 = dict(workloads.SIDE_FALSE, trips=workloads.way_trips(SEED, 2))
+    third, two_thirds, half = (workloads.thr_from_p(1 / 3), workloads.thr_from_p(2 / 3),
+                               workloads.thr_from_p(0.5))
+
+    def measure(run):
+        t = {}
+        for v in ("divergent", "melded", "melded_inplace"):
+            run(v)
+            t[v] = float(np.median([_events_time(torch, lambda: run(v), args.reps)
+                                    for _ in range(3)]))
+        return {"divergent_us": round(t["divergent"] * 1e3, 2),
+                "melded_us": round(t["melded"] * 1e3, 2),
+                "melded_inplace_us": round(t["melded_inplace"] * 1e3, 2),
+                "speedup": round(t["divergent"] / t["melded"], 4)}
+
+    out = {}
+    cases = {
+        "three_way_thirds": (third, two_thirds, w0, w1, w2),
+        "three_way_thirds_trips_20": (third, two_thirds, dict(w0, trips=20), dict(w1, trips=20),
+                                      dict(w2, trips=20)),
+        "three_way_biased_middle_never": (half, half, w0, w1, w2),
+    }
+    for name, (t0, t1, a, b, c) in cases.items():
+        out[name] = measure(lambda v: meld.region3(xd, td, SEED, t0, t1, a, b, c, variant=v,
+                                                   out=y))
+        out[name]["trips"] = [a["trips"], b["trips"], c["trips"]]
+    st = dict(workloads.SIDE_TRUE, trips_lo=8, trips_hi=32)
+    sf = dict(workloads.SIDE_FALSE, trips_lo=8, trips_hi=32)
+    out["per_lane_trips_8_32_p0.5"] = measure(
+        lambda v: meld.region_lanetrips(xd, td, SEED, half, st, sf, variant=v, out=y))
+    return out
 
 
 def _bench_sort(torch, np, meld, workloads, dev, args):

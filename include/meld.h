@@ -198,6 +198,56 @@ meld_status meld_divergent_region_f32(meld_ctx *ctx, const float *x, float *y, s
                                       uint64_t thr, meld_side side_true, meld_side side_false,
                                       meld_variant variant, void *stream);
 
+/* Three-way region (the paper's synthetic benchmark SB4, Evaluation section:
+ * an if / else-if / else whose three blocks compute alike on different data;
+ * its melding is region replication, Detailed Design, "Basic block-Region
+ * Melding"). Lane i:
+ *   h   = mix64(mix64(seed + 4*0x9E3779B97F4A7C15) + i) >> 32
+ *   way = h < thr0 ? way0 : (h < thr1 ? way1 : way2)
+ * then the way's loop exactly as meld_divergent_region_f32 runs a side.
+ * The divergent form runs the chain as written; the melded form runs one
+ * loop whose first min(trips) steps are melded across the three ways, the
+ * next ones across the two longest, the rest by the longest way alone
+ * (multiplier selected per lane, each way's gathers in one conditional
+ * block); MELD_MELDED_INPLACE aligns the gathers as well. MELD_AUTO times the
+ * three forms once per shape class.
+ *
+ * Arguments as for meld_divergent_region_f32; thr0 <= thr1 <= 2^32.
+ * Errors:  as meld_divergent_region_f32, plus MELD_EINVAL for thr0 > thr1.
+ */
+meld_status meld_region3_f32(meld_ctx *ctx, const float *x, float *y, size_t n,
+                             const float *tab, size_t tab_len, uint64_t seed, uint64_t thr0,
+                             uint64_t thr1, meld_side way0, meld_side way1, meld_side way2,
+                             meld_variant variant, void *stream);
+
+/* A side whose trip count is drawn per lane in [trips_lo, trips_hi]. */
+typedef struct {
+    float a;
+    uint32_t off;
+    uint32_t step;
+    uint32_t trips_lo;
+    uint32_t trips_hi;
+} meld_side_range;
+
+/* The two-sided loop region with a trip count per lane (the loop exit itself
+ * diverges inside a wave): lane i on side s runs
+ *   s.trips_lo + ((mix64(mix64(seed + 11*0x9E3779B97F4A7C15) + i) >> 32)
+ *                 mod (s.trips_hi - s.trips_lo + 1))
+ * steps, otherwise as meld_divergent_region_f32. The melded form runs one
+ * loop for both sides, each lane leaving after its own count; the divergent
+ * one runs each side's loop in turn. MELD_AUTO times the three forms once per
+ * shape class.
+ *
+ * Arguments as for meld_divergent_region_f32; trips_lo <= trips_hi <= 65536.
+ * Errors:  as meld_divergent_region_f32, plus MELD_EINVAL for a range with
+ *          trips_lo > trips_hi.
+ */
+meld_status meld_region_lanetrips_f32(meld_ctx *ctx, const float *x, float *y, size_t n,
+                                      const float *tab, size_t tab_len, uint64_t seed,
+                                      uint64_t thr, meld_side_range side_true,
+                                      meld_side_range side_false, meld_variant variant,
+                                      void *stream);
+
 /* ---- Divergence probes (synchronous: they wait for `stream`) -----------
  * Only waves whose lanes take both outcomes of a branch pay the IPDOM
  * serialisation (Background section, "GPGPU Architecture"). The probes

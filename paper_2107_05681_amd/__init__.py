@@ -36,7 +36,7 @@ EXPORTS = ("meld_version", "meld_create", "meld_destroy", "meld_last_error", "me
            "meld_server_submit", "meld_server_poll", "meld_server_release", "meld_server_read",
            "meld_server_drain", "meld_server_stats_get", "meld_server_last_error",
            "meld_server_destroy",
-           "meld_divergent_region_f32")
+           "meld_divergent_region_f32", "meld_region3_f32", "meld_region_lanetrips_f32")
 
 
 class MeldError(RuntimeError):
@@ -48,6 +48,11 @@ class MeldError(RuntimeError):
 class Side(ctypes.Structure):
     _fields_ = [("a", ctypes.c_float), ("off", ctypes.c_uint32),
                 ("step", ctypes.c_uint32), ("trips", ctypes.c_uint32)]
+
+
+class SideRange(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_float), ("off", ctypes.c_uint32), ("step", ctypes.c_uint32),
+                ("trips_lo", ctypes.c_uint32), ("trips_hi", ctypes.c_uint32)]
 
 
 _lib = None
@@ -102,6 +107,12 @@ def load_library():
     lib.meld_set_option.argtypes = [vp, st, i64]
     lib.meld_divergent_region_f32.restype = st
     lib.meld_divergent_region_f32.argtypes = [vp, vp, vp, sz, vp, sz, u64, u64, Side, Side, st, vp]
+    lib.meld_region3_f32.restype = st
+    lib.meld_region3_f32.argtypes = [vp, vp, vp, sz, vp, sz, u64, u64, u64, Side, Side, Side, st,
+                                     vp]
+    lib.meld_region_lanetrips_f32.restype = st
+    lib.meld_region_lanetrips_f32.argtypes = [vp, vp, vp, sz, vp, sz, u64, u64, SideRange,
+                                              SideRange, st, vp]
     _lib = lib
     return lib
 
@@ -240,6 +251,47 @@ def divergent_region(x, tab, seed: int, thr: int, side_true, side_false, variant
         context(x.device.index), ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
         x.numel(), ctypes.c_void_p(tab.data_ptr()), tab.numel(), int(seed), int(thr),
         _as_side(side_true), _as_side(side_false), _variant(variant), _stream_of(x, stream)))
+    return out
+
+
+def _region_tensors(x, tab, out):
+    import torch
+    for t, name in ((x, "x"), (tab, "tab")):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 \
+                or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous float32 CUDA tensor")
+    return torch.empty_like(x) if out is None else out
+
+
+def region3(x, tab, seed: int, thr0: int, thr1: int, way0, way1, way2, variant=AUTO, out=None,
+            stream=None):
+    """Three-way region over the lanes of ``x`` (see meld_region3_f32)."""
+    out = _region_tensors(x, tab, out)
+    _check(load_library().meld_region3_f32(
+        context(x.device.index), ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+        x.numel(), ctypes.c_void_p(tab.data_ptr()), tab.numel(), int(seed), int(thr0), int(thr1),
+        _as_side(way0), _as_side(way1), _as_side(way2), _variant(variant),
+        _stream_of(x, stream)))
+    return out
+
+
+def _as_side_range(s) -> SideRange:
+    if isinstance(s, SideRange):
+        return s
+    return SideRange(float(s["a"]), int(s["off"]), int(s["step"]), int(s["trips_lo"]),
+                     int(s["trips_hi"]))
+
+
+def region_lanetrips(x, tab, seed: int, thr: int, side_true, side_false, variant=AUTO,
+                     out=None, stream=None):
+    """Two-sided region with per-lane trip counts (see meld_region_lanetrips_f32); the
+    sides are dicts with a, off, step, trips_lo, trips_hi."""
+    out = _region_tensors(x, tab, out)
+    _check(load_library().meld_region_lanetrips_f32(
+        context(x.device.index), ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+        x.numel(), ctypes.c_void_p(tab.data_ptr()), tab.numel(), int(seed), int(thr),
+        _as_side_range(side_true), _as_side_range(side_false), _variant(variant),
+        _stream_of(x, stream)))
     return out
 
 

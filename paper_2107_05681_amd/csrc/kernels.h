@@ -19,6 +19,25 @@ hipError_t launch_region(const float *x, float *y, uint32_t n, const float *tab,
                          uint64_t seed, uint64_t thr, RegionSide T, RegionSide F, RegionForm form,
                          hipStream_t stream);
 
+// Three-way region (region_variants.hip): way 0 below thr0, way 1 below thr1,
+// way 2 otherwise (thr0 <= thr1 <= 2^32).
+hipError_t launch_region3(const float *x, float *y, uint32_t n, const float *tab, uint32_t mask,
+                          uint64_t seed, uint64_t thr0, uint64_t thr1, RegionSide W0,
+                          RegionSide W1, RegionSide W2, RegionForm form, hipStream_t stream);
+
+// A side whose trip count is drawn per lane in [lo, lo + span].
+struct RegionSideRange {
+    float a;
+    uint32_t off;
+    uint32_t step;
+    uint32_t lo;
+    uint32_t span;
+};
+
+hipError_t launch_region_lanetrips(const float *x, float *y, uint32_t n, const float *tab,
+                                   uint32_t mask, uint64_t seed, uint64_t thr, RegionSideRange T,
+                                   RegionSideRange F, RegionForm form, hipStream_t stream);
+
 // Array with virtual padding: position p < n lives in keys/vals[p], position
 // n <= p < N in the tail workspace tk/tv[p - n] (pre-filled with the
 // sentinel); without a workspace, positions >= n read as the sentinel and

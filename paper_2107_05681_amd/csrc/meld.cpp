@@ -718,6 +718,70 @@ meld_status auto_region_form(meld_ctx *ctx, const float *x, float *y, size_t n, 
     return MELD_OK;
 }
 
+// Checks shared by the region entry points (after which the device is set).
+meld_status check_region_args(const char *name, meld_ctx *ctx, const float *x, const float *y,
+                              size_t n, const float *tab, size_t tab_len, meld_variant variant) {
+    if (ctx == nullptr) return fail(MELD_EINVAL, "%s: ctx is NULL", name);
+    if (n >= (1ull << 32)) return fail(MELD_EINVAL, "%s: n >= 2^32", name);
+    if (tab_len == 0 || (tab_len & (tab_len - 1)) != 0 || tab_len > (1ull << 32))
+        return fail(MELD_EINVAL, "%s: tab_len = %zu is not a power of two <= 2^32", name, tab_len);
+    if ((unsigned)variant > MELD_MELDED_INPLACE) return fail(MELD_EINVAL, "%s: bad variant", name);
+    return MELD_OK;
+}
+
+meld_status check_region_pointers(const char *name, meld_ctx *ctx, const float *x,
+                                  const float *y, const float *tab) {
+    if (!is_device_ptr(ctx, x) || !is_device_ptr(ctx, y) || !is_device_ptr(ctx, tab))
+        return fail(MELD_EINVAL, "%s: x, y and tab must be device pointers on device %d", name,
+                    ctx->device);
+    if (x == y) return fail(MELD_EINVAL, "%s: y aliases x", name);
+    return MELD_OK;
+}
+
+// MELD_AUTO for the region variants: times the three forms once per shape
+// class on the caller's arrays (the final run overwrites y) and keeps the
+// fastest, preferring the melded ones within the tie margin.
+template <typename Launch>
+meld_status auto_timed_form(meld_ctx *ctx, const char *op, const std::string &key, Launch launch,
+                            hipStream_t s, meld::RegionForm *out) {
+    *out = meld::RegionForm::kMelded;
+    if (const meld::TuneEntry *t = ctx->tuner.find(op, key)) {
+        *out = t->form == 0   ? meld::RegionForm::kDivergent
+               : t->form == 3 ? meld::RegionForm::kMeldedInPlace
+                              : meld::RegionForm::kMelded;
+        return MELD_OK;
+    }
+    if (capturing(s)) return MELD_OK;
+    const meld::RegionForm forms[3] = {meld::RegionForm::kDivergent, meld::RegionForm::kMelded,
+                                       meld::RegionForm::kMeldedInPlace};
+    const int codes[3] = {0, 1, 3};
+    double ms[3];
+    int flo[3], fhi[3];
+    for (int f = 0; f < 3; ++f) {
+        auto run = [&]() -> meld_status {
+            hipError_t r = launch(forms[f]);
+            return r == hipSuccess ? MELD_OK : hip_fail(r, "region launch");
+        };
+        meld_status st = run();  // warm-up
+        if (st != MELD_OK) return st;
+        st = time_median(s, 3, []() { return MELD_OK; }, run, &ms[f]);
+        if (st != MELD_OK) return st;
+        flo[f] = fhi[f] = f == 0 ? 0 : 1;
+    }
+    const int pick = meld::choose(3, ms, flo, fhi, 1.0, 1.0, ctx->theta, ctx->tie);
+    *out = forms[pick];
+    meld::TuneEntry te;
+    te.op = op;
+    te.key = key;
+    te.lo = te.hi = flo[pick];
+    te.form = codes[pick];
+    te.ms = ms[pick];
+    te.mixed_lo = te.mixed_hi = 1.0;
+    te.trials = 3;
+    ctx->tuner.put(te);
+    return MELD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -838,6 +902,86 @@ meld_status meld_divergent_region_f32(meld_ctx *ctx, const float *x, float *y, s
     hipError_t e = meld::launch_region(x, y, (uint32_t)n, tab, (uint32_t)(tab_len - 1), seed, thr,
                                        T, F, form, s);
     if (e != hipSuccess) return hip_fail(e, "region launch");
+    return MELD_OK;
+}
+
+meld_status meld_region3_f32(meld_ctx *ctx, const float *x, float *y, size_t n,
+                             const float *tab, size_t tab_len, uint64_t seed, uint64_t thr0,
+                             uint64_t thr1, meld_side way0, meld_side way1, meld_side way2,
+                             meld_variant variant, void *stream) {
+    const char *name = "meld_region3_f32";
+    meld_status st = check_region_args(name, ctx, x, y, n, tab, tab_len, variant);
+    if (st != MELD_OK) return st;
+    if (thr0 > thr1 || thr1 > (1ull << 32))
+        return fail(MELD_EINVAL, "%s: thresholds must satisfy thr0 <= thr1 <= 2^32", name);
+    if (way0.trips > 65536 || way1.trips > 65536 || way2.trips > 65536)
+        return fail(MELD_EINVAL, "%s: trips > 65536", name);
+    if (n == 0) return MELD_OK;
+    DeviceGuard g(ctx->device);
+    st = check_region_pointers(name, ctx, x, y, tab);
+    if (st != MELD_OK) return st;
+    const meld::RegionSide W0{way0.a, way0.off, way0.step, way0.trips};
+    const meld::RegionSide W1{way1.a, way1.off, way1.step, way1.trips};
+    const meld::RegionSide W2{way2.a, way2.off, way2.step, way2.trips};
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    auto launch = [&](meld::RegionForm f) {
+        return meld::launch_region3(x, y, (uint32_t)n, tab, (uint32_t)(tab_len - 1), seed, thr0,
+                                    thr1, W0, W1, W2, f, s);
+    };
+    meld::RegionForm form = region_form(variant);
+    if (variant == MELD_AUTO) {
+        const uint32_t p0 = (uint32_t)((thr0 * 10 + (1ull << 31)) >> 32);
+        const uint32_t p1 = (uint32_t)((thr1 * 10 + (1ull << 31)) >> 32);
+        const std::string key =
+            fmt("n=%u tab=%u t=%u,%u,%u p10=%u,%u", log2_ceil(n), log2_ceil(tab_len), W0.trips,
+                W1.trips, W2.trips, p0, p1);
+        st = auto_timed_form(ctx, "region3", key, launch, s, &form);
+        if (st != MELD_OK) return st;
+    }
+    hipError_t e = launch(form);
+    if (e != hipSuccess) return hip_fail(e, "region3 launch");
+    return MELD_OK;
+}
+
+meld_status meld_region_lanetrips_f32(meld_ctx *ctx, const float *x, float *y, size_t n,
+                                      const float *tab, size_t tab_len, uint64_t seed,
+                                      uint64_t thr, meld_side_range side_true,
+                                      meld_side_range side_false, meld_variant variant,
+                                      void *stream) {
+    const char *name = "meld_region_lanetrips_f32";
+    meld_status st = check_region_args(name, ctx, x, y, n, tab, tab_len, variant);
+    if (st != MELD_OK) return st;
+    if (thr > (1ull << 32)) return fail(MELD_EINVAL, "%s: thr > 2^32", name);
+    for (const meld_side_range *r : {&side_true, &side_false}) {
+        if (r->trips_lo > r->trips_hi)
+            return fail(MELD_EINVAL, "%s: trips_lo > trips_hi", name);
+        if (r->trips_hi > 65536) return fail(MELD_EINVAL, "%s: trips > 65536", name);
+    }
+    if (n == 0) return MELD_OK;
+    DeviceGuard g(ctx->device);
+    st = check_region_pointers(name, ctx, x, y, tab);
+    if (st != MELD_OK) return st;
+    const meld::RegionSideRange T{side_true.a, side_true.off, side_true.step, side_true.trips_lo,
+                                  side_true.trips_hi - side_true.trips_lo};
+    const meld::RegionSideRange F{side_false.a, side_false.off, side_false.step,
+                                  side_false.trips_lo, side_false.trips_hi - side_false.trips_lo};
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    auto launch = [&](meld::RegionForm f) {
+        return meld::launch_region_lanetrips(x, y, (uint32_t)n, tab, (uint32_t)(tab_len - 1), seed,
+                                             thr, T, F, f, s);
+    };
+    meld::RegionForm form = region_form(variant);
+    if (variant == MELD_AUTO) {
+        const uint32_t p10 = (uint32_t)((thr * 10 + (1ull << 31)) >> 32);
+        const std::string key =
+            fmt("n=%u tab=%u T=%u-%u F=%u-%u p10=%u", log2_ceil(n), log2_ceil(tab_len),
+                side_true.trips_lo, side_true.trips_hi, side_false.trips_lo, side_false.trips_hi,
+                p10);
+        st = auto_timed_form(ctx, "region_lanetrips", key, launch, s, &form);
+        if (st != MELD_OK) return st;
+    }
+    hipError_t e = launch(form);
+    if (e != hipSuccess) return hip_fail(e, "region_lanetrips launch");
     return MELD_OK;
 }
 

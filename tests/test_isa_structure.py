@@ -120,3 +120,27 @@ def test_register_phases_divergent_vs_melded(bitonic_asm, pairs):
         assert re.search(rf"v_cmp_[lg]t_{width}", blocks[0]), side
     assert "; side" not in mel
     assert re.search(rf"v_cmp_lt_{width}", mel) and "v_cndmask_b32" in mel
+
+
+@pytest.fixture(scope="module")
+def variants_asm(tmp_path_factory):
+    return _asm("region_variants.hip", tmp_path_factory.mktemp("isa"))
+
+
+def test_region3_divergent_runs_a_loop_per_way(variants_asm):
+    body = _kernel(variants_asm, r"region3_divergent_kernel")
+    for way in ("way 0\n", "way 1\n", "way 2\n"):
+        blocks = _blocks_after(body, way)
+        assert blocks and "global_load_dword" in blocks[0] and "v_fma" in blocks[0], way
+
+
+def test_region3_melded_gathers_per_way_fma_once(variants_asm):
+    body = _kernel(variants_asm, r"region3_melded_kernel")
+    for way in ("gathers way 0", "gathers way 1", "gathers way 2"):
+        assert _blocks_after(body, way), way
+    assert "v_cndmask_b32" in body  # the selected multiplier
+
+
+def test_region3_melded_inplace_has_no_way_blocks(variants_asm):
+    body = _kernel(variants_asm, r"region3_melded_inplace_kernel")
+    assert "; side" not in body
