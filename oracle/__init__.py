@@ -76,6 +76,10 @@ def _load():
         lib.oracle_region_lanetrips_f32.argtypes = [vp, vp, u64, sz, vp, sz, u64, u64, SideRange,
                                                     SideRange]
         lib.oracle_region_lanetrips_f32.restype = ctypes.c_int
+        lib.oracle_oddeven_emulate.argtypes = [vp, sz, i64]
+        lib.oracle_oddeven_emulate.restype = ctypes.c_int
+        lib.oracle_oddeven_num_comparators.argtypes = [sz]
+        lib.oracle_oddeven_num_comparators.restype = u64
         lib.oracle_count_true.argtypes = [u64, u64, u64, sz]
         lib.oracle_count_true.restype = u64
         lib.oracle_mixed_waves.argtypes = [u64, u64, sz, u32]
@@ -199,6 +203,18 @@ def region_lanetrips_f32(x, tab, seed: int, thr: int, side_true: dict, side_fals
     if rc != 0:
         raise ValueError("table length must be a power of two, thr <= 2^32, lo <= hi")
     return y
+
+
+def oddeven_emulate(keys, max_steps: int = -1) -> np.ndarray:
+    """Batcher's odd-even merge network (its first max_steps steps) on a copy of keys."""
+    k = np.array(keys, dtype=np.uint32, copy=True)
+    if _load().oracle_oddeven_emulate(k.ctypes.data, k.size, max_steps) != 0:
+        raise ValueError("length must be a power of two")
+    return k
+
+
+def oddeven_num_comparators(n: int) -> int:
+    return int(_load().oracle_oddeven_num_comparators(n))
 
 
 def count_true(seed: int, thr: int, n: int, i0: int = 0) -> int:

@@ -22,6 +22,12 @@
  *    compute alike), lane by lane in the source order.
  *  - oracle_region_lanetrips_f32: the two-sided region with a trip count
  *    drawn per lane (a loop whose exit itself diverges inside a wave).
+ *  - oracle_oddeven_emulate: Batcher's odd-even merge sorting network, the
+ *    network of the paper's PCM benchmark (Evaluation section), written from
+ *    its definition: for p = 1, 2, 4, ... and k = p, p/2, ..., 1, compare
+ *    a with a + k for every a = j + i, j running over k mod p, k mod p + 2k,
+ *    ... and i over 0 .. k-1, whenever a and a + k lie in the same block of
+ *    2p elements.
  *  - oracle_mixed_waves: the share of 64-lane waves whose branch mask is
  *    neither all-true nor all-false (Background section: only such waves
  *    pay the IPDOM serialisation).
@@ -57,6 +63,26 @@ bool branch_true(uint64_t seed, uint64_t thr, uint64_t i) { return (branch_hash(
 inline uint64_t composite(uint32_t k, uint32_t v) { return ((uint64_t)k << 32) | v; }
 
 bool is_pow2(size_t n) { return n != 0 && (n & (n - 1)) == 0; }
+
+// Batcher's odd-even merge network, step by step. Calls visit(a, a + k) for
+// every comparator of the first max_steps steps (negative: all).
+template <typename Visit>
+void oddeven_network(size_t n, int64_t max_steps, Visit visit) {
+    int64_t steps = 0;
+    for (size_t p = 1; p < n; p <<= 1) {
+        for (size_t k = p; k >= 1; k >>= 1) {
+            if (steps == max_steps) return;
+            ++steps;
+            for (size_t j = k % p; j + k < n; j += 2 * k) {
+                for (size_t i = 0; i < k && i + j + k < n; ++i) {
+                    const size_t a = i + j, b = i + j + k;
+                    if (a / (2 * p) == b / (2 * p)) visit(a, b);
+                }
+            }
+        }
+    }
+}
+
 
 }  // namespace
 
@@ -209,6 +235,21 @@ int oracle_region_lanetrips_f32(const float *x, float *y, uint64_t i0, size_t n,
         y[j] = run_side(x[j], i, s.a, s.off, s.step, t, tab, mask);
     }
     return 0;
+}
+
+int oracle_oddeven_emulate(uint32_t *keys, size_t n_pow2, int64_t max_steps) {
+    if (!is_pow2(n_pow2)) return -1;
+    oddeven_network(n_pow2, max_steps, [&](size_t a, size_t b) {
+        if (keys[b] < keys[a]) std::swap(keys[a], keys[b]);
+    });
+    return 0;
+}
+
+uint64_t oracle_oddeven_num_comparators(size_t n_pow2) {
+    uint64_t c = 0;
+    if (!is_pow2(n_pow2)) return 0;
+    oddeven_network(n_pow2, -1, [&](size_t, size_t) { ++c; });
+    return c;
 }
 
 uint64_t oracle_count_true(uint64_t seed, uint64_t thr, uint64_t i0, size_t n) {

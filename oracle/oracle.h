@@ -71,6 +71,15 @@ int oracle_region_lanetrips_f32(const float *x, float *y, uint64_t i0, size_t n,
                                 const float *tab, size_t tab_len, uint64_t seed, uint64_t thr,
                                 oracle_side_range side_true, oracle_side_range side_false);
 
+/* Batcher's odd-even merge sorting network on a power-of-two array (the
+ * network behind the paper's PCM benchmark, Evaluation section), its first
+ * max_steps steps (negative: all). A step is one (p, k) pair: p = 1, 2, 4, ...
+ * < n, then k = p, p/2, ..., 1; each comparator (a, a + k) of the step keeps
+ * the smaller key at a. Returns -1 if n is not a power of two. */
+int oracle_oddeven_emulate(uint32_t *keys, size_t n_pow2, int64_t max_steps);
+/* Comparators of the whole network on n = 2^t elements. */
+uint64_t oracle_oddeven_num_comparators(size_t n_pow2);
+
 uint64_t oracle_count_true(uint64_t seed, uint64_t thr, uint64_t i0, size_t n);
 uint64_t oracle_mixed_waves(uint64_t seed, uint64_t thr, size_t n, uint32_t wave);
 double oracle_mixed_fraction_closed_form(double p, uint32_t wave);

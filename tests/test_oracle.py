@@ -480,3 +480,47 @@ def test_lanetrips_counts_per_lane():
         assert s["trips_lo"] <= y[i] <= s["trips_hi"]
     with pytest.raises(ValueError):
         oracle.region_lanetrips_f32(x, tab, seed, thr, _range_sides(5, 4, 1, 2)[0], rf)
+
+
+# ---- Batcher's odd-even merge network (PCM) ----------------------------------
+
+def test_oddeven_comparator_count_closed_form():
+    # Knuth, TAOCP vol. 3, 5.3.4: Batcher's odd-even merge sort uses
+    # (t^2 - t + 4) 2^(t-2) - 1 comparators on n = 2^t elements.
+    for t in range(1, 13):
+        expect = ((t * t - t + 4) << t) // 4 - 1
+        assert oracle.oddeven_num_comparators(1 << t) == expect, t
+
+
+@pytest.mark.parametrize("n", [2, 4, 8, 16])
+def test_oddeven_zero_one_principle(n):
+    # Sorting every 0-1 input proves a comparator network sorts (Knuth 5.3.4).
+    v = np.arange(1 << n, dtype=np.uint32)
+    bits = ((v[:, None] >> np.arange(n, dtype=np.uint32)) & 1).astype(np.uint32)
+    for row in bits:
+        out = oracle.oddeven_emulate(row)
+        assert np.all(out[:-1] <= out[1:])
+
+
+def test_oddeven_hand_worked_four_elements():
+    # n = 4: steps (p, k) = (1, 1): (0,1) (2,3); (2, 2): (0,2) (1,3); (2, 1): (1,2).
+    x = np.array([3, 2, 1, 0], np.uint32)
+    assert oracle.oddeven_emulate(x, 1).tolist() == [2, 3, 0, 1]
+    assert oracle.oddeven_emulate(x, 2).tolist() == [0, 1, 2, 3]
+    y = np.array([0, 2, 1, 3], np.uint32)  # only the last comparator (1, 2) acts
+    assert oracle.oddeven_emulate(y, 2).tolist() == [0, 2, 1, 3]
+    assert oracle.oddeven_emulate(y, 3).tolist() == [0, 1, 2, 3]
+
+
+def test_oddeven_sorts_random_and_step_count():
+    for log_n in (5, 10, 13):
+        n = 1 << log_n
+        keys = workloads.keys_u32(50 + log_n, n)
+        steps = log_n * (log_n + 1) // 2
+        out = oracle.oddeven_emulate(keys)
+        assert np.array_equal(out, np.sort(keys))
+        assert np.array_equal(oracle.oddeven_emulate(keys, steps), out)
+        assert np.array_equal(oracle.oddeven_emulate(keys, steps + 7), out)
+        assert not np.array_equal(oracle.oddeven_emulate(keys, steps - 1), out)
+    with pytest.raises(ValueError):
+        oracle.oddeven_emulate(np.zeros(12, np.uint32))
