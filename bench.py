@@ -232,6 +232,10 @@ def main():
     if not args.no_sort:
         sort_info = _bench_sort(torch, np, meld, workloads, dev, args)
 
+    oddeven_info = None
+    if not args.no_sort:
+        oddeven_info = _bench_oddeven(torch, np, meld, workloads, dev)
+
     seg_info = None
     if not args.no_seg:
         seg_info = _bench_segmented(torch, np, meld, workloads, dev)
@@ -283,6 +287,7 @@ def main():
                     "counter-measured HBM bytes per launch",
         },
         "sort": sort_info,
+        "oddeven_buckets": oddeven_info,
         "segmented": seg_info,
         "serving": serve_info,
         "cpu_baseline": cpu,
@@ -327,6 +332,27 @@ def _bench_region_variants(torch, np, meld, workloads, xd, td, y, args):
     out["per_lane_trips_8_32_p0.5"] = measure(
         lambda v: meld.region_lanetrips(xd, td, SEED, half, st, sf, variant=v, out=y))
     return out
+
+
+def _bench_oddeven(torch, np, meld, workloads, dev):
+    """Batcher's odd-even merge network on buckets (the PCM network): 2^28 keys in
+    buckets of 2^13 and 2^10, divergent vs melded."""
+    n = 1 << 28
+    kin = torch.from_numpy(workloads.keys_u32(SEED, n).view(np.int32)).to(dev)
+    k = torch.empty_like(kin)
+    res = {}
+    for log_b in (13, 10):
+        t = {}
+        for v in ("divergent", "melded"):
+            t[v] = _time_sorts(torch, np, lambda: meld.oddeven_sort_buckets(k, log_b, variant=v),
+                               lambda: k.copy_(kin), 4)
+        res[f"buckets_2^{log_b}"] = {"divergent_ms": round(t["divergent"], 3),
+                                     "melded_ms": round(t["melded"], 3),
+                                     "speedup": round(t["divergent"] / t["melded"], 4),
+                                     "melded_Gkeys_s": round(n / (t["melded"] * 1e-3) / 1e9, 3)}
+    del kin, k
+    torch.cuda.empty_cache()
+    return {"keys": n, **res}
 
 
 def _bench_sort(torch, np, meld, workloads, dev, args):

@@ -144,6 +144,26 @@ meld_status meld_sort_u32_steps(meld_ctx *ctx, uint32_t *keys, uint32_t *payload
 meld_status meld_segmented_sort_u32(meld_ctx *ctx, uint32_t *keys, const uint32_t *offsets,
                                     size_t nseg, meld_variant variant, void *stream);
 
+/* Sorts each bucket keys[b 2^log_bucket .. min(n, (b+1) 2^log_bucket))
+ * ascending in place with Batcher's odd-even merge network (the network of
+ * the paper's PCM benchmark, Evaluation section, "Partition and Concurrent
+ * Merge"), running at most max_steps of its log_bucket (log_bucket + 1) / 2
+ * steps per bucket (negative: all). Per element and step the network has a
+ * three-way region (lower end of a comparator, upper end, idle): the
+ * divergent form runs it as an if / else-if with one LDS load per side, the
+ * melded form replicates the idle path into the two aligned sides and runs
+ * one load from a selected address. MELD_AUTO times both forms once per shape
+ * class on a scratch copy.
+ *
+ * keys:       device u32[n], n < 2^31; the last bucket may be ragged (its
+ *             missing positions act as 0xFFFFFFFF and are never written).
+ * log_bucket: 6..14.
+ * Errors:     MELD_EINVAL for NULL/host pointers, log_bucket outside 6..14,
+ *             n >= 2^31. */
+meld_status meld_oddeven_sort_buckets_u32(meld_ctx *ctx, uint32_t *keys, size_t n,
+                                          uint32_t log_bucket, int64_t max_steps,
+                                          meld_variant variant, void *stream);
+
 /* As meld_segmented_sort_u32, with the form chosen per stage: low_phases for
  * the phases k <= 64, run one comparator per lane in LDS, whose direction
  * bit is one of the lane bits (the direction branch is divergent inside a

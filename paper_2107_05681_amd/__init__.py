@@ -36,7 +36,8 @@ EXPORTS = ("meld_version", "meld_create", "meld_destroy", "meld_last_error", "me
            "meld_server_submit", "meld_server_poll", "meld_server_release", "meld_server_read",
            "meld_server_drain", "meld_server_stats_get", "meld_server_last_error",
            "meld_server_destroy",
-           "meld_divergent_region_f32", "meld_region3_f32", "meld_region_lanetrips_f32")
+           "meld_divergent_region_f32", "meld_region3_f32", "meld_region_lanetrips_f32",
+           "meld_oddeven_sort_buckets_u32")
 
 
 class MeldError(RuntimeError):
@@ -107,6 +108,8 @@ def load_library():
     lib.meld_set_option.argtypes = [vp, st, i64]
     lib.meld_divergent_region_f32.restype = st
     lib.meld_divergent_region_f32.argtypes = [vp, vp, vp, sz, vp, sz, u64, u64, Side, Side, st, vp]
+    lib.meld_oddeven_sort_buckets_u32.restype = st
+    lib.meld_oddeven_sort_buckets_u32.argtypes = [vp, vp, sz, ctypes.c_uint32, i64, st, vp]
     lib.meld_region3_f32.restype = st
     lib.meld_region3_f32.argtypes = [vp, vp, vp, sz, vp, sz, u64, u64, u64, Side, Side, Side, st,
                                      vp]
@@ -252,6 +255,16 @@ def divergent_region(x, tab, seed: int, thr: int, side_true, side_false, variant
         x.numel(), ctypes.c_void_p(tab.data_ptr()), tab.numel(), int(seed), int(thr),
         _as_side(side_true), _as_side(side_false), _variant(variant), _stream_of(x, stream)))
     return out
+
+
+def oddeven_sort_buckets(keys, log_bucket: int, max_steps: int = -1, variant=AUTO,
+                         stream=None):
+    """Sorts each bucket of 2^log_bucket keys in place with Batcher's odd-even merge
+    network (see meld_oddeven_sort_buckets_u32)."""
+    _u32_tensor(keys, "keys")
+    _check(load_library().meld_oddeven_sort_buckets_u32(
+        context(keys.device.index), ctypes.c_void_p(keys.data_ptr()), keys.numel(),
+        int(log_bucket), int(max_steps), _variant(variant), _stream_of(keys, stream)))
 
 
 def _region_tensors(x, tab, out):

@@ -153,6 +153,12 @@ hipError_t launch_segmented_sort(uint32_t *keys, const uint32_t *off, uint32_t n
                                  SegState *st, uint8_t *cls, uint32_t *queue, uint32_t *work,
                                  uint32_t grid, bool meld_lo, bool meld_hi, hipStream_t stream);
 
+// Batcher's odd-even merge network on each bucket of 2^log_t keys
+// (oddeven.hip; log_t in 6..14, the last bucket ragged), at most max_steps
+// steps per bucket (negative: all), divergent or melded.
+hipError_t launch_oddeven_buckets(uint32_t *keys, uint32_t n, uint32_t log_t, int32_t max_steps,
+                                  bool melded, hipStream_t stream);
+
 // Largest tile (log2 elements) the tile kernel supports for keys / pairs.
 constexpr uint32_t kMaxLogTileKeys = 14;
 constexpr uint32_t kMaxLogTilePairs = 13;

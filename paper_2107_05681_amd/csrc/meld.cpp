@@ -782,6 +782,53 @@ meld_status auto_timed_form(meld_ctx *ctx, const char *op, const std::string &ke
     return MELD_OK;
 }
 
+// MELD_AUTO for the odd-even bucket sort: the tuned form of this shape
+// class, timing both forms on a scratch copy of the keys the first time.
+meld_status auto_oddeven_form(meld_ctx *ctx, const uint32_t *keys, size_t n, uint32_t log_bucket,
+                              hipStream_t s, bool *melded) {
+    *melded = true;
+    const std::string key = fmt("n=%u b=%u", log2_ceil(n), log_bucket);
+    if (const meld::TuneEntry *t = ctx->tuner.find("oddeven", key)) {
+        *melded = t->form != 0;
+        return MELD_OK;
+    }
+    if (capturing(s)) return MELD_OK;
+    meld_status st = ensure_words(&ctx->tune_buf, &ctx->tune_words, n, "tuning scratch");
+    if (st != MELD_OK) return st;
+    double ms[2];
+    int flo[2], fhi[2];
+    for (int f = 0; f < 2; ++f) {
+        st = time_median(
+            s, 3,
+            [&]() -> meld_status {
+                hipError_t e = hipMemcpyAsync(ctx->tune_buf, keys, n * 4, hipMemcpyDeviceToDevice,
+                                              s);
+                return e == hipSuccess ? MELD_OK : hip_fail(e, "tuning copy");
+            },
+            [&]() -> meld_status {
+                hipError_t e = meld::launch_oddeven_buckets(ctx->tune_buf, (uint32_t)n, log_bucket,
+                                                            -1, f == 1, s);
+                return e == hipSuccess ? MELD_OK : hip_fail(e, "odd-even launch");
+            },
+            &ms[f]);
+        if (st != MELD_OK) return st;
+        flo[f] = fhi[f] = f;
+    }
+    const int pick = meld::choose(2, ms, flo, fhi, 1.0, 1.0, ctx->theta, ctx->tie);
+    *melded = pick == 1;
+    meld::TuneEntry te;
+    te.op = "oddeven";
+    te.key = key;
+    te.lo = te.hi = pick;
+    te.form = pick;
+    te.log_t = (int)log_bucket;
+    te.ms = ms[pick];
+    te.mixed_lo = te.mixed_hi = 1.0;
+    te.trials = 2;
+    ctx->tuner.put(te);
+    return MELD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -851,6 +898,32 @@ meld_status meld_sort_u32(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size
         if (st != MELD_OK) return st;
     }
     return sort_impl(ctx, keys, payload, n, plan, -1, s);
+}
+
+meld_status meld_oddeven_sort_buckets_u32(meld_ctx *ctx, uint32_t *keys, size_t n,
+                                          uint32_t log_bucket, int64_t max_steps,
+                                          meld_variant variant, void *stream) {
+    const char *name = "meld_oddeven_sort_buckets_u32";
+    if (ctx == nullptr) return fail(MELD_EINVAL, "%s: ctx is NULL", name);
+    if (n >= (1ull << 31)) return fail(MELD_EINVAL, "%s: n = %zu >= 2^31", name, n);
+    if (log_bucket < 6 || log_bucket > 14)
+        return fail(MELD_EINVAL, "%s: log_bucket = %u outside 6..14", name, log_bucket);
+    if ((unsigned)variant > MELD_MELDED_INPLACE) return fail(MELD_EINVAL, "%s: bad variant", name);
+    if (n == 0 || max_steps == 0) return MELD_OK;
+    DeviceGuard g(ctx->device);
+    if (!is_device_ptr(ctx, keys))
+        return fail(MELD_EINVAL, "%s: keys is not a device pointer on device %d", name,
+                    ctx->device);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    bool melded = use_melded(variant);
+    if (variant == MELD_AUTO) {
+        meld_status st = auto_oddeven_form(ctx, keys, n, log_bucket, s, &melded);
+        if (st != MELD_OK) return st;
+    }
+    const int32_t limit = max_steps < 0 || max_steps > 0x7FFFFFFF ? -1 : (int32_t)max_steps;
+    hipError_t e = meld::launch_oddeven_buckets(keys, (uint32_t)n, log_bucket, limit, melded, s);
+    if (e != hipSuccess) return hip_fail(e, "odd-even launch");
+    return MELD_OK;
 }
 
 meld_status meld_sort_u32_steps(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n,

@@ -144,3 +144,20 @@ def test_region3_melded_gathers_per_way_fma_once(variants_asm):
 def test_region3_melded_inplace_has_no_way_blocks(variants_asm):
     body = _kernel(variants_asm, r"region3_melded_inplace_kernel")
     assert "; side" not in body
+
+
+@pytest.fixture(scope="module")
+def oddeven_asm(tmp_path_factory):
+    return _asm("oddeven.hip", tmp_path_factory.mktemp("isa"))
+
+
+def test_oddeven_divergent_sides_each_load(oddeven_asm):
+    body = _kernel(oddeven_asm, r"oddeven_bucket_kernelILi8ELi1024ELb0E")
+    for side in ("lower\n", "upper\n"):
+        blocks = _blocks_after(body, side)
+        assert blocks and "ds_read_b32" in blocks[0], side
+
+
+def test_oddeven_melded_has_no_sides(oddeven_asm):
+    body = _kernel(oddeven_asm, r"oddeven_bucket_kernelILi8ELi1024ELb1E")
+    assert "; side" not in body and "ds_read_b32" in body and "v_cndmask_b32" in body
