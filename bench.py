@@ -72,9 +72,12 @@ def _measured_traffic():
     try:
         with open(path) as f:
             rec = json.load(f)
-        with open(os.path.join(ROOT, rec["source"]), "rb") as f:
-            if hashlib.sha1(f.read()).hexdigest() != rec["source_sha1"]:
-                return None
+        h = hashlib.sha1()
+        for src in rec["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest() != rec["sources_sha1"]:
+            return None
         return int(rec["traffic_bytes"])
     except (OSError, KeyError, ValueError):
         return None
