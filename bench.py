@@ -235,9 +235,10 @@ def main():
     if not args.no_sort:
         sort_info = _bench_sort(torch, np, meld, workloads, dev, args)
 
-    oddeven_info = None
+    oddeven_info = merge_info = None
     if not args.no_sort:
         oddeven_info = _bench_oddeven(torch, np, meld, workloads, dev)
+        merge_info = _bench_mergesort(torch, np, meld, workloads, dev)
 
     seg_info = None
     if not args.no_seg:
@@ -291,6 +292,7 @@ def main():
         },
         "sort": sort_info,
         "oddeven_buckets": oddeven_info,
+        "mergesort": merge_info,
         "segmented": seg_info,
         "serving": serve_info,
         "cpu_baseline": cpu,
@@ -356,6 +358,33 @@ def _bench_oddeven(torch, np, meld, workloads, dev):
     del kin, k
     torch.cuda.empty_cache()
     return {"keys": n, **res}
+
+
+def _bench_mergesort(torch, np, meld, workloads, dev):
+    """Bottom-up merge sort (the MS network of the paper): 2^20 keys (the paper's size)
+    and 2^24, divergent vs melded; merge passes alone = total - the run sort."""
+    res = {}
+    for log_n in (20, 24):
+        n = 1 << log_n
+        kin = torch.from_numpy(workloads.keys_u32(SEED, n).view(np.int32)).to(dev)
+        k = torch.empty_like(kin)
+        t = {}
+        for v in ("divergent", "melded"):
+            for passes, tag in ((-1, "all"), (0, "runs")):
+                t[v + tag] = _time_sorts(
+                    torch, np, lambda: meld.merge_sort(k, max_passes=passes, variant=v),
+                    lambda: k.copy_(kin), 7)
+        md, mm = t["divergentall"] - t["divergentruns"], t["meldedall"] - t["meldedruns"]
+        res[f"keys_2^{log_n}"] = {"divergent_ms": round(t["divergentall"], 3),
+                                  "melded_ms": round(t["meldedall"], 3),
+                                  "speedup": round(t["divergentall"] / t["meldedall"], 4),
+                                  "merge_passes_divergent_ms": round(md, 3),
+                                  "merge_passes_melded_ms": round(mm, 3),
+                                  "merge_passes_speedup": round(md / mm, 4) if mm > 0 else None,
+                                  "melded_Gkeys_s": round(n / (t["meldedall"] * 1e-3) / 1e9, 3)}
+        del kin, k
+    torch.cuda.empty_cache()
+    return res
 
 
 def _bench_sort(torch, np, meld, workloads, dev, args):

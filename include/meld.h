@@ -164,6 +164,22 @@ meld_status meld_oddeven_sort_buckets_u32(meld_ctx *ctx, uint32_t *keys, size_t 
                                           uint32_t log_bucket, int64_t max_steps,
                                           meld_variant variant, void *stream);
 
+/* Ascending bottom-up merge sort of keys[0..n) in place (the paper's MS
+ * benchmark, Evaluation section, "Mergesort"): runs of 1024 keys sorted by
+ * the odd-even network, then merge passes that double the run length, at
+ * most max_passes of them (negative: all). A pass merges along the merge path
+ * (Green, McColl and Bader, ICS 2012); per output each lane takes the head of
+ * run A or of run B, a data-dependent branch: the divergent form runs its two
+ * sides (emit, advance, load the next key of that run) as written, the melded
+ * form selects the emitted key and issues one load from a selected address.
+ * Ties take run A first. MELD_AUTO times both forms once per shape class.
+ *
+ * keys:    device u32[n], n < 2^31.
+ * Scratch: a second buffer of n keys, owned by the context.
+ * Errors:  MELD_EINVAL for NULL/host pointers or n >= 2^31. */
+meld_status meld_merge_sort_u32(meld_ctx *ctx, uint32_t *keys, size_t n, int64_t max_passes,
+                                meld_variant variant, void *stream);
+
 /* As meld_segmented_sort_u32, with the form chosen per stage: low_phases for
  * the phases k <= 64, run one comparator per lane in LDS, whose direction
  * bit is one of the lane bits (the direction branch is divergent inside a

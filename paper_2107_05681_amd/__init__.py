@@ -37,7 +37,7 @@ EXPORTS = ("meld_version", "meld_create", "meld_destroy", "meld_last_error", "me
            "meld_server_drain", "meld_server_stats_get", "meld_server_last_error",
            "meld_server_destroy",
            "meld_divergent_region_f32", "meld_region3_f32", "meld_region_lanetrips_f32",
-           "meld_oddeven_sort_buckets_u32")
+           "meld_oddeven_sort_buckets_u32", "meld_merge_sort_u32")
 
 
 class MeldError(RuntimeError):
@@ -108,6 +108,8 @@ def load_library():
     lib.meld_set_option.argtypes = [vp, st, i64]
     lib.meld_divergent_region_f32.restype = st
     lib.meld_divergent_region_f32.argtypes = [vp, vp, vp, sz, vp, sz, u64, u64, Side, Side, st, vp]
+    lib.meld_merge_sort_u32.restype = st
+    lib.meld_merge_sort_u32.argtypes = [vp, vp, sz, i64, st, vp]
     lib.meld_oddeven_sort_buckets_u32.restype = st
     lib.meld_oddeven_sort_buckets_u32.argtypes = [vp, vp, sz, ctypes.c_uint32, i64, st, vp]
     lib.meld_region3_f32.restype = st
@@ -265,6 +267,14 @@ def oddeven_sort_buckets(keys, log_bucket: int, max_steps: int = -1, variant=AUT
     _check(load_library().meld_oddeven_sort_buckets_u32(
         context(keys.device.index), ctypes.c_void_p(keys.data_ptr()), keys.numel(),
         int(log_bucket), int(max_steps), _variant(variant), _stream_of(keys, stream)))
+
+
+def merge_sort(keys, max_passes: int = -1, variant=AUTO, stream=None):
+    """Ascending bottom-up merge sort of ``keys`` in place (see meld_merge_sort_u32)."""
+    _u32_tensor(keys, "keys")
+    _check(load_library().meld_merge_sort_u32(
+        context(keys.device.index), ctypes.c_void_p(keys.data_ptr()), keys.numel(),
+        int(max_passes), _variant(variant), _stream_of(keys, stream)))
 
 
 def _region_tensors(x, tab, out):

@@ -159,6 +159,12 @@ hipError_t launch_segmented_sort(uint32_t *keys, const uint32_t *off, uint32_t n
 hipError_t launch_oddeven_buckets(uint32_t *keys, uint32_t n, uint32_t log_t, int32_t max_steps,
                                   bool melded, hipStream_t stream);
 
+// One merge pass (mergesort.hip): the sorted runs of 2^log_run keys of src
+// merged in pairs into runs of twice that length in dst (the last pair may be
+// ragged); log_run >= 10.
+hipError_t launch_merge_pass(const uint32_t *src, uint32_t *dst, uint32_t n, uint32_t log_run,
+                             bool melded, hipStream_t stream);
+
 // Largest tile (log2 elements) the tile kernel supports for keys / pairs.
 constexpr uint32_t kMaxLogTileKeys = 14;
 constexpr uint32_t kMaxLogTilePairs = 13;

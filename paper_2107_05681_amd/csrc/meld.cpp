@@ -48,6 +48,9 @@ struct meld_ctx {
     // the caller's data, and device counters for the divergence probes.
     meld::Tuner tuner;
     uint32_t *tune_buf = nullptr;
+    // Merge sort: the other buffer of each merge pass.
+    uint32_t *merge_buf = nullptr;
+    size_t merge_words = 0;
     size_t tune_words = 0;
     unsigned long long *probe_buf = nullptr;  // kProbeWords counters
     double theta = 0.5;  // mixed-wave fraction from which the probe favours melding
@@ -782,13 +785,14 @@ meld_status auto_timed_form(meld_ctx *ctx, const char *op, const std::string &ke
     return MELD_OK;
 }
 
-// MELD_AUTO for the odd-even bucket sort: the tuned form of this shape
-// class, timing both forms on a scratch copy of the keys the first time.
-meld_status auto_oddeven_form(meld_ctx *ctx, const uint32_t *keys, size_t n, uint32_t log_bucket,
-                              hipStream_t s, bool *melded) {
+// MELD_AUTO for an in-place keys-only operation with a divergent and a
+// melded form: the tuned form of this shape class, timing both on a scratch
+// copy of the keys the first time. run(keys, melded) enqueues the operation.
+template <typename Run>
+meld_status auto_two_forms(meld_ctx *ctx, const char *op, const std::string &key,
+                           const uint32_t *keys, size_t n, hipStream_t s, Run run, bool *melded) {
     *melded = true;
-    const std::string key = fmt("n=%u b=%u", log2_ceil(n), log_bucket);
-    if (const meld::TuneEntry *t = ctx->tuner.find("oddeven", key)) {
+    if (const meld::TuneEntry *t = ctx->tuner.find(op, key)) {
         *melded = t->form != 0;
         return MELD_OK;
     }
@@ -805,27 +809,49 @@ meld_status auto_oddeven_form(meld_ctx *ctx, const uint32_t *keys, size_t n, uin
                                               s);
                 return e == hipSuccess ? MELD_OK : hip_fail(e, "tuning copy");
             },
-            [&]() -> meld_status {
-                hipError_t e = meld::launch_oddeven_buckets(ctx->tune_buf, (uint32_t)n, log_bucket,
-                                                            -1, f == 1, s);
-                return e == hipSuccess ? MELD_OK : hip_fail(e, "odd-even launch");
-            },
-            &ms[f]);
+            [&]() -> meld_status { return run(ctx->tune_buf, f == 1); }, &ms[f]);
         if (st != MELD_OK) return st;
         flo[f] = fhi[f] = f;
     }
     const int pick = meld::choose(2, ms, flo, fhi, 1.0, 1.0, ctx->theta, ctx->tie);
     *melded = pick == 1;
     meld::TuneEntry te;
-    te.op = "oddeven";
+    te.op = op;
     te.key = key;
     te.lo = te.hi = pick;
     te.form = pick;
-    te.log_t = (int)log_bucket;
     te.ms = ms[pick];
     te.mixed_lo = te.mixed_hi = 1.0;
     te.trials = 2;
     ctx->tuner.put(te);
+    return MELD_OK;
+}
+
+// Bottom-up merge sort: runs of 2^10 by the odd-even network, then up to
+// max_passes merge passes (negative: all) ping-ponging between keys and the
+// context's merge buffer; the result ends in keys.
+constexpr uint32_t kMergeRunLog = 10;
+
+meld_status merge_sort_impl(meld_ctx *ctx, uint32_t *keys, size_t n, int64_t max_passes,
+                            bool melded, hipStream_t s) {
+    hipError_t e = meld::launch_oddeven_buckets(keys, (uint32_t)n, kMergeRunLog, -1, melded, s);
+    if (e != hipSuccess) return hip_fail(e, "odd-even launch");
+    if (n <= (1u << kMergeRunLog) || max_passes == 0) return MELD_OK;
+    meld_status st = ensure_words(&ctx->merge_buf, &ctx->merge_words, n, "merge buffer");
+    if (st != MELD_OK) return st;
+    uint32_t *src = keys, *dst = ctx->merge_buf;
+    int64_t pass = 0;
+    for (uint32_t lr = kMergeRunLog; ((size_t)1 << lr) < n; ++lr) {
+        if (max_passes >= 0 && pass == max_passes) break;
+        e = meld::launch_merge_pass(src, dst, (uint32_t)n, lr, melded, s);
+        if (e != hipSuccess) return hip_fail(e, "merge pass launch");
+        std::swap(src, dst);
+        ++pass;
+    }
+    if (src != keys) {
+        e = hipMemcpyAsync(keys, src, n * 4, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "merge sort copy-back");
+    }
     return MELD_OK;
 }
 
@@ -873,7 +899,7 @@ void meld_destroy(meld_ctx *ctx) {
     if (ctx->capture_stream != nullptr) (void)hipStreamDestroy(ctx->capture_stream);
     for (void *p : {(void *)ctx->tail, (void *)ctx->seg_state, (void *)ctx->seg_cls,
                     (void *)ctx->seg_queue, (void *)ctx->seg_work, (void *)ctx->tune_buf,
-                    (void *)ctx->probe_buf})
+                    (void *)ctx->merge_buf, (void *)ctx->probe_buf})
         if (p != nullptr) (void)hipFree(p);
     delete ctx;
 }
@@ -917,13 +943,40 @@ meld_status meld_oddeven_sort_buckets_u32(meld_ctx *ctx, uint32_t *keys, size_t 
     const hipStream_t s = static_cast<hipStream_t>(stream);
     bool melded = use_melded(variant);
     if (variant == MELD_AUTO) {
-        meld_status st = auto_oddeven_form(ctx, keys, n, log_bucket, s, &melded);
+        auto run = [&](uint32_t *k, bool m) -> meld_status {
+            hipError_t e = meld::launch_oddeven_buckets(k, (uint32_t)n, log_bucket, -1, m, s);
+            return e == hipSuccess ? MELD_OK : hip_fail(e, "odd-even launch");
+        };
+        meld_status st = auto_two_forms(ctx, "oddeven", fmt("n=%u b=%u", log2_ceil(n), log_bucket),
+                                        keys, n, s, run, &melded);
         if (st != MELD_OK) return st;
     }
     const int32_t limit = max_steps < 0 || max_steps > 0x7FFFFFFF ? -1 : (int32_t)max_steps;
     hipError_t e = meld::launch_oddeven_buckets(keys, (uint32_t)n, log_bucket, limit, melded, s);
     if (e != hipSuccess) return hip_fail(e, "odd-even launch");
     return MELD_OK;
+}
+
+meld_status meld_merge_sort_u32(meld_ctx *ctx, uint32_t *keys, size_t n, int64_t max_passes,
+                                meld_variant variant, void *stream) {
+    const char *name = "meld_merge_sort_u32";
+    if (ctx == nullptr) return fail(MELD_EINVAL, "%s: ctx is NULL", name);
+    if (n >= (1ull << 31)) return fail(MELD_EINVAL, "%s: n = %zu >= 2^31", name, n);
+    if ((unsigned)variant > MELD_MELDED_INPLACE) return fail(MELD_EINVAL, "%s: bad variant", name);
+    if (n <= 1) return MELD_OK;
+    DeviceGuard g(ctx->device);
+    if (!is_device_ptr(ctx, keys))
+        return fail(MELD_EINVAL, "%s: keys is not a device pointer on device %d", name,
+                    ctx->device);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    bool melded = use_melded(variant);
+    if (variant == MELD_AUTO) {
+        auto run = [&](uint32_t *k, bool m) { return merge_sort_impl(ctx, k, n, -1, m, s); };
+        meld_status st =
+            auto_two_forms(ctx, "mergesort", fmt("n=%u", log2_ceil(n)), keys, n, s, run, &melded);
+        if (st != MELD_OK) return st;
+    }
+    return merge_sort_impl(ctx, keys, n, max_passes, melded, s);
 }
 
 meld_status meld_sort_u32_steps(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n,

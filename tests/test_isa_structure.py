@@ -161,3 +161,20 @@ def test_oddeven_divergent_sides_each_load(oddeven_asm):
 def test_oddeven_melded_has_no_sides(oddeven_asm):
     body = _kernel(oddeven_asm, r"oddeven_bucket_kernelILi8ELi1024ELb1E")
     assert "; side" not in body and "ds_read_b32" in body and "v_cndmask_b32" in body
+
+
+@pytest.fixture(scope="module")
+def mergesort_asm(tmp_path_factory):
+    return _asm("mergesort.hip", tmp_path_factory.mktemp("isa"))
+
+
+def test_merge_step_divergent_sides_each_load(mergesort_asm):
+    body = _kernel(mergesort_asm, r"merge_pass_kernelILb0E")
+    for side in ("take a\n", "take b\n"):
+        blocks = _blocks_after(body, side)
+        assert blocks and "ds_read_b32" in blocks[0], side
+
+
+def test_merge_step_melded_has_no_sides(mergesort_asm):
+    body = _kernel(mergesort_asm, r"merge_pass_kernelILb1E")
+    assert "; side" not in body and "v_cndmask_b32" in body
