@@ -45,10 +45,11 @@ def _parse():
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="length of the Poisson serving trace (0 skips serving)")
     ap.add_argument("--profile", nargs="?", const="region", default=None,
-                    choices=["region", "sort", "pairs"],
+                    choices=["region", "sort", "pairs", "next"],
                     help="short run for rocprofv3: 'region' (a 256 MiB copy, then a few "
-                         "steps), 'sort' (2^16 keys and the 4096-segment sort, each form) "
-                         "or 'pairs' (one 2^28-pair sort per form)")
+                         "steps), 'sort' (2^16 keys and the 4096-segment sort, each form), "
+                         "'pairs' (one 2^28-pair sort per form) or 'next' (2^24 keys: "
+                         "odd-even buckets of 2^13 and the merge sort, each form)")
     return ap.parse_args()
 
 
@@ -81,6 +82,13 @@ def _measured_traffic():
         return int(rec["traffic_bytes"])
     except (OSError, KeyError, ValueError):
         return None
+
+
+def _dist(np, samples_ms, scale=1e3):
+    """Median, p10 and p90 of timings in ms, scaled (default: to us)."""
+    a = np.asarray(samples_ms, dtype=np.float64) * scale
+    return {"median": round(float(np.median(a)), 2), "p10": round(float(np.percentile(a, 10)), 2),
+            "p90": round(float(np.percentile(a, 90)), 2)}
 
 
 def _mixed_fraction(p, wave=64):
@@ -126,6 +134,9 @@ def main():
     if args.profile == "pairs":
         _profile_pairs(torch, np, meld, workloads, dev)
         return
+    if args.profile == "next":
+        _profile_next(torch, np, meld, workloads, dev)
+        return
     if args.profile:
         src = torch.empty(1 << 26, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -158,7 +169,7 @@ def main():
             region(p, "divergent")
             region(p, "melded")
         td_ms, tm_ms, ti_ms = [], [], []
-        for _ in range(3):
+        for _ in range(7):
             td_ms.append(_events_time(torch, lambda: region(p, "divergent"), args.reps))
             tm_ms.append(_events_time(torch, lambda: region(p, "melded"), args.reps))
             ti_ms.append(_events_time(torch, lambda: region(p, "melded_inplace"), args.reps))
@@ -169,6 +180,7 @@ def main():
         per_p[str(p)] = {
             "divergent_us": round(d * 1e3, 2), "melded_us": round(m * 1e3, 2),
             "speedup": round(d / m, 4),
+            "divergent_us_dist": _dist(np, td_ms), "melded_us_dist": _dist(np, tm_ms),
             "melded_inplace_us": round(mi * 1e3, 2),
             "speedup_inplace": round(d / mi, 4),
             "mixed_wave_fraction": round(_mixed_fraction(p), 5),
@@ -214,6 +226,7 @@ def main():
                                      "speedup": round(tm["divergent"] / tm["melded"], 4)}
 
     variants = _bench_region_variants(torch, np, meld, workloads, xd, td, ys[0.5], args)
+    seeds = _bench_seeds(torch, np, meld, workloads, dev, args)
 
     # Roofline of the dominant kernel over the timed region itself: the step is
     # one melded launch per p, so its average launch takes ms_per_step / 3.
@@ -279,6 +292,7 @@ def main():
         "same_index_sides": same_index,
         "trips_sweep_p0.5": trips_sweep,
         "region_variants": variants,
+        "seeds": seeds,
         "roofline": {
             "bound": "hbm", "kernel": "region_melded_kernel (timed step, one launch per p)",
             "avg_launch_us": round(launch_us, 2),
@@ -298,6 +312,38 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+
+
+def _bench_seeds(torch, np, meld, workloads, dev, args):
+    """The region (2^24 lanes, p = 0.5, each seed's own trip counts and tables)
+    and the 2^16-key sort for seeds 1, 2 and 3: speedup per seed and the median."""
+    region, sort = {}, {}
+    thr = workloads.thr_from_p(0.5)
+    for seed in (1, 2, 3):
+        x, tab, st, sf = workloads.region_inputs(seed, N_LANES)
+        xd, tdv = torch.from_numpy(x).to(dev), torch.from_numpy(tab).to(dev)
+        y = torch.empty_like(xd)
+        t = {}
+        for v in ("divergent", "melded"):
+            run = (lambda v=v: meld.divergent_region(xd, tdv, seed, thr, st, sf, variant=v, out=y))
+            run()
+            t[v] = float(np.median([_events_time(torch, run, args.reps) for _ in range(5)]))
+        region[str(seed)] = {"trips": [st["trips"], sf["trips"]],
+                             "divergent_us": round(t["divergent"] * 1e3, 2),
+                             "melded_us": round(t["melded"] * 1e3, 2),
+                             "speedup": round(t["divergent"] / t["melded"], 4)}
+        kin = torch.from_numpy(workloads.keys_u32(seed, 1 << 16).view(np.int32)).to(dev)
+        k = torch.empty_like(kin)
+        ts = {v: _time_sorts(torch, np, lambda v=v: meld.sort(k, None, variant=v),
+                             lambda: k.copy_(kin), 21) for v in ("divergent", "melded")}
+        sort[str(seed)] = {"divergent_us": round(ts["divergent"] * 1e3, 2),
+                           "melded_us": round(ts["melded"] * 1e3, 2),
+                           "speedup": round(ts["divergent"] / ts["melded"], 4)}
+        del xd, tdv, y, kin, k
+    torch.cuda.empty_cache()
+    med = lambda d: round(float(np.median([v["speedup"] for v in d.values()])), 4)
+    return {"region_p0.5_2^24": {**region, "median_speedup": med(region)},
+            "sort_keys_2^16": {**sort, "median_speedup": med(sort)}}
 
 
 def _bench_region_variants(torch, np, meld, workloads, xd, td, y, args):
@@ -410,9 +456,15 @@ def _bench_sort(torch, np, meld, workloads, dev, args):
             if rep > 0:
                 times[v].append(s.elapsed_time(e))
     d, m = float(np.median(times["divergent"])), float(np.median(times["melded"]))
+    plan = meld.sort_plan(n, pairs=True, variant="melded", device=0)
+    passes = plan["hbm_passes"]
+    moved = 16.0 * n * passes  # 8 B read + 8 B written per pair and pass
     res["pairs_2^28"] = {"divergent_ms": round(d, 3), "melded_ms": round(m, 3),
                          "speedup": round(d / m, 4),
-                         "melded_Gkeys_s": round(n / (m * 1e-3) / 1e9, 3)}
+                         "melded_Gkeys_s": round(n / (m * 1e-3) / 1e9, 3),
+                         "log_tile": plan["log_tile"], "hbm_passes": passes,
+                         "melded_hbm_GBs": round(moved / (m * 1e-3) / 1e9, 1),
+                         "hbm_frac": round(moved / (m * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     del kin, pin, k, p
     torch.cuda.empty_cache()
     # 2^16 keys.
@@ -431,9 +483,23 @@ def _bench_sort(torch, np, meld, workloads, dev, args):
             if rep > 0:
                 times[v].append(s.elapsed_time(e))
     d, m = float(np.median(times["divergent"])), float(np.median(times["melded"]))
+    # the local-sort kernel alone: the network's first t (t + 1) / 2 steps are
+    # exactly that launch
+    plan = meld.sort_plan(n, pairs=False, variant="melded", device=0)
+    local = plan["passes"][0]["steps"]
+    tl = {v: _time_sorts(torch, np, lambda v=v: meld.sort_steps(k, None, local, variant=v),
+                         lambda: k.copy_(kin), 21) for v in ("divergent", "melded")}
     res["keys_2^16"] = {"divergent_us": round(d * 1e3, 2), "melded_us": round(m * 1e3, 2),
                         "speedup": round(d / m, 4),
-                        "melded_Gkeys_s": round(n / (m * 1e-3) / 1e9, 3)}
+                        "melded_Gkeys_s": round(n / (m * 1e-3) / 1e9, 3),
+                        "divergent_us_dist": _dist(np, times["divergent"]),
+                        "melded_us_dist": _dist(np, times["melded"]),
+                        "log_tile": plan["log_tile"], "hbm_passes": plan["hbm_passes"],
+                        "local_sort_kernel": {
+                            "steps": local,
+                            "divergent_us": round(tl["divergent"] * 1e3, 2),
+                            "melded_us": round(tl["melded"] * 1e3, 2),
+                            "speedup": round(tl["divergent"] / tl["melded"], 4)}}
     return res
 
 
@@ -464,6 +530,20 @@ def _profile_pairs(torch, np, meld, workloads, dev):
         meld.sort(k, p, variant=v)
     torch.cuda.synchronize()
     print(json.dumps({"profile_run": "pairs"}))
+
+
+def _profile_next(torch, np, meld, workloads, dev):
+    """2^24 keys (seed 1): odd-even buckets of 2^13, then the merge sort, once per form."""
+    kin = torch.from_numpy(workloads.keys_u32(SEED, 1 << 24).view(np.int32)).to(dev)
+    k = torch.empty_like(kin)
+    for v in ("divergent", "melded"):
+        k.copy_(kin)
+        meld.oddeven_sort_buckets(k, 13, variant=v)
+    for v in ("divergent", "melded"):
+        k.copy_(kin)
+        meld.merge_sort(k, variant=v)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_run": "next"}))
 
 
 def _time_sorts(torch, np, run, restore, reps):
@@ -531,7 +611,9 @@ def _bench_serving(meld, workloads, seconds):
 
 
 def _cpu_baseline(np, workloads, x, tab, st, sf, thr):
-    """The CPU oracle on this host: one whole step (3 x 2^24 lanes), split over threads."""
+    """The CPU oracle on this host: whole steps (3 x 2^24 lanes), lanes split over
+    threads, repeated for at least 1 s of wall time; then one thread on a
+    2^22-lane slice of each p."""
     import oracle
 
     threads = max(1, min(16, os.cpu_count() or 1))
@@ -541,19 +623,31 @@ def _cpu_baseline(np, workloads, x, tab, st, sf, thr):
     def work(p, lo, hi):
         oracle.region_f32_into(x[lo:hi], y[lo:hi], tab, SEED, thr[p], st, sf, lo)
 
+    steps = 0
     t0 = time.perf_counter()
-    for p in PS:
-        ts = [threading.Thread(target=work, args=(p, i * chunk, min(N_LANES, (i + 1) * chunk)))
-              for i in range(threads)]
-        for t in ts:
-            t.start()
-        for t in ts:
-            t.join()
+    while steps < 3 or time.perf_counter() - t0 < 1.0:
+        for p in PS:
+            ts = [threading.Thread(target=work,
+                                   args=(p, i * chunk, min(N_LANES, (i + 1) * chunk)))
+                  for i in range(threads)]
+            for t in ts:
+                t.start()
+            for t in ts:
+                t.join()
+        steps += 1
     dt = time.perf_counter() - t0
-    return {"value": round(len(PS) * N_LANES / dt / 1e9, 4), "unit": "Gkeys/s",
+    one = 1 << 22
+    t1 = time.perf_counter()
+    for p in PS:
+        work(p, 0, one)
+    dt1 = time.perf_counter() - t1
+    return {"value": round(steps * len(PS) * N_LANES / dt / 1e9, 4), "unit": "Gkeys/s",
             "cores": threads, "kind": "oracle",
-            "sample": "one full step (3 x 2^24 lanes, p in {0.1,0.5,0.9}), lanes split over "
-                      f"{threads} host threads; {dt:.2f} s"}
+            "one_thread_value": round(len(PS) * one / dt1 / 1e9, 4),
+            "sample": f"{steps} full steps (3 x 2^24 lanes each, p in {{0.1,0.5,0.9}}), lanes "
+                      f"split over {threads} host threads, {dt:.2f} s wall "
+                      f"(~{dt * threads:.0f} s of CPU work); one_thread_value: one thread over "
+                      f"2^22 lanes per p, {dt1:.2f} s"}
 
 
 if __name__ == "__main__":

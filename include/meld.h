@@ -121,6 +121,27 @@ meld_status meld_sort_u32(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size
 meld_status meld_sort_u32_steps(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n,
                                 int64_t max_steps, meld_variant variant, void *stream);
 
+/* The launches meld_sort_u32 would enqueue for n elements (the network of
+ * the Motivating Example section, Figure 1, split into on-chip and HBM
+ * passes), as JSON in buf (NUL-terminated), without launching anything:
+ *   {"n", "log_n", "pairs", "tuned", "log_tile", "low", "high",
+ *    "hbm_passes", "steps", "passes": [{"kind", "steps", "m", "b_hi", "b_lo"}]}
+ * kind "tile" (everything in one tile), "local" (every tile's phases up to
+ * the tile), "regs" / "gather" (steps j = 2^b_hi .. 2^b_lo of phase 2^m
+ * streamed through HBM in registers / a gathered LDS tile), "merge" (the
+ * steps below the tile of phase 2^m). Every pass reads and writes the whole
+ * array once, so hbm_passes is the number of HBM round trips; steps totals
+ * log_n (log_n + 1) / 2. "tuned" is true when MELD_AUTO found a decision of
+ * the tuner (without timing anything here); an untuned MELD_AUTO describes
+ * the melded default. with_payload: nonzero for (key, payload) pairs.
+ * n <= 1 gives an empty pass list. Host-only: touches no device memory.
+ * ctx may be NULL: the default tile rule, no tuner (a context adds its
+ * MELD_OPT_SORT_LOG_TILE and, for MELD_AUTO, its tuned decisions).
+ * Errors: MELD_EINVAL for NULL buf, n >= 2^31, a bad variant, or len too
+ * small (the message gives the size needed). */
+meld_status meld_sort_plan_describe(meld_ctx *ctx, size_t n, int with_payload,
+                                    meld_variant variant, char *buf, size_t len);
+
 /* Sorts each segment keys[offsets[s] .. offsets[s+1]) ascending in place;
  * no key crosses a segment boundary. This is the per-bucket sort of the
  * paper's bitonic benchmark (Evaluation section, "Bitonic Sort (BIT)": each

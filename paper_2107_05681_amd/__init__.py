@@ -37,7 +37,7 @@ EXPORTS = ("meld_version", "meld_create", "meld_destroy", "meld_last_error", "me
            "meld_server_drain", "meld_server_stats_get", "meld_server_last_error",
            "meld_server_destroy",
            "meld_divergent_region_f32", "meld_region3_f32", "meld_region_lanetrips_f32",
-           "meld_oddeven_sort_buckets_u32", "meld_merge_sort_u32")
+           "meld_oddeven_sort_buckets_u32", "meld_merge_sort_u32", "meld_sort_plan_describe")
 
 
 class MeldError(RuntimeError):
@@ -100,6 +100,8 @@ def load_library():
     lib.meld_tune.argtypes = [vp, ctypes.c_char_p]
     lib.meld_plan_describe.restype = st
     lib.meld_plan_describe.argtypes = [vp, ctypes.c_char_p, sz]
+    lib.meld_sort_plan_describe.restype = st
+    lib.meld_sort_plan_describe.argtypes = [vp, sz, ctypes.c_int, st, ctypes.c_char_p, sz]
     dp, ip = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
     lib.meld_tune_choose.restype = ctypes.c_int
     lib.meld_tune_choose.argtypes = [ctypes.c_int, dp, ip, ip, ctypes.c_double, ctypes.c_double,
@@ -365,6 +367,18 @@ def plan_describe(device: int = 0) -> str:
         if size >= 1 << 26:
             _check(st)
         size *= 4
+
+
+def sort_plan(n: int, pairs: bool = False, variant: str = "auto", device=None) -> dict:
+    """The launches a sort of n elements runs (tile, forms, HBM passes), as a
+    dict; device None: the library's default rule without a context."""
+    import json
+    lib = load_library()
+    ctx = None if device is None else context(device)
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(lib.meld_sort_plan_describe(ctx, n, 1 if pairs else 0, _variant(variant), buf,
+                                       len(buf)))
+    return json.loads(buf.value.decode())
 
 
 def tune_choose(ms, melded_lo, melded_hi, mixed_lo, mixed_hi, theta=0.5, tie=0.02) -> int:

@@ -161,9 +161,15 @@ hipError_t launch_oddeven_buckets(uint32_t *keys, uint32_t n, uint32_t log_t, in
 
 // One merge pass (mergesort.hip): the sorted runs of 2^log_run keys of src
 // merged in pairs into runs of twice that length in dst (the last pair may be
-// ragged); log_run >= 10.
+// ragged); log_run >= 10. cuts: NULL, or scratch of merge_pass_cut_words(n)
+// words; with it, passes of runs of at least 2^kMergeCutLog keys over more
+// than kMergeCutMinTiles tiles of 2048 keys find the tiles' merge-path cuts
+// in a kernel of their own first.
+constexpr uint32_t kMergeCutLog = 11;
+constexpr uint32_t kMergeCutMinTiles = 2048;
+uint32_t merge_pass_cut_words(uint32_t n);
 hipError_t launch_merge_pass(const uint32_t *src, uint32_t *dst, uint32_t n, uint32_t log_run,
-                             bool melded, hipStream_t stream);
+                             bool melded, uint32_t *cuts, hipStream_t stream);
 
 // Largest tile (log2 elements) the tile kernel supports for keys / pairs.
 constexpr uint32_t kMaxLogTileKeys = 14;

@@ -51,6 +51,8 @@ struct meld_ctx {
     // Merge sort: the other buffer of each merge pass.
     uint32_t *merge_buf = nullptr;
     size_t merge_words = 0;
+    uint32_t *merge_cuts = nullptr;  // merge-path cut of every tile of a merge pass
+    size_t merge_cut_words = 0;
     size_t tune_words = 0;
     unsigned long long *probe_buf = nullptr;  // kProbeWords counters
     double theta = 0.5;  // mixed-wave fraction from which the probe favours melding
@@ -389,6 +391,69 @@ std::vector<uint32_t> split_passes(uint32_t d, uint32_t max_gather) {
     return sizes;
 }
 
+// One launch of a single-array sort.
+enum class PassKind { kTile, kLocal, kRegs, kGather, kMerge };
+struct SortPass {
+    PassKind kind;
+    uint32_t m;           // phase 2^m (kRegs, kGather, kMerge)
+    uint32_t b_hi, b_lo;  // steps j = 2^b_hi .. 2^b_lo (kRegs, kGather)
+    uint32_t steps;       // network steps the launch runs
+};
+
+const char *pass_name(PassKind k) {
+    switch (k) {
+        case PassKind::kTile: return "tile";
+        case PassKind::kLocal: return "local";
+        case PassKind::kRegs: return "regs";
+        case PassKind::kGather: return "gather";
+        default: return "merge";
+    }
+}
+
+// The launches of the whole network of N = 2^log_n elements under a plan
+// (log_n > plan.log_t: local sort of every tile, then per phase 2^m above the
+// tile its streaming passes and its merge tail; otherwise a single tile).
+std::vector<SortPass> sort_passes(const SortPlan &plan, bool pairs, uint32_t log_n) {
+    std::vector<SortPass> out;
+    if (log_n <= plan.log_t) {
+        const uint32_t log_t = std::max<uint32_t>(log_n, 1);
+        out.push_back({PassKind::kTile, 0, 0, 0, log_t * (log_t + 1) / 2});
+        return out;
+    }
+    const uint32_t log_t = plan.log_t;
+    out.push_back({PassKind::kLocal, 0, 0, 0, log_t * (log_t + 1) / 2});
+    const uint32_t max_gather = pairs ? meld::kMaxGatherStepsPairs : meld::kMaxGatherStepsKeys;
+    const uint32_t gather_log = pairs ? meld::kGatherLogPairs : meld::kGatherLogKeys;
+    for (uint32_t m = log_t + 1; m <= log_n; ++m) {
+        // Steps j = 2^(m-1) .. 2^log_t stream through HBM in as few passes as
+        // possible: up to kMaxFusedSteps per pass in registers, more (high
+        // bits first) through gathered LDS tiles where their rows fit.
+        uint32_t b_hi = m - 1;
+        for (uint32_t r : split_passes(m - log_t, max_gather)) {
+            const uint32_t b_lo = b_hi + 1 - r;
+            const bool gather_fits = log_n >= gather_log && b_lo + r >= gather_log;
+            if (r > meld::kMaxFusedSteps && gather_fits) {
+                out.push_back({PassKind::kGather, m, b_hi, b_lo, r});
+            } else {
+                // register passes only (balanced)
+                const uint32_t parts = (r + meld::kMaxFusedSteps - 1) / meld::kMaxFusedSteps;
+                uint32_t hi = b_hi;
+                for (uint32_t p = 0; p < parts; ++p) {
+                    const uint32_t remaining = hi - b_lo + 1;
+                    const uint32_t this_r = (remaining + (parts - p) - 1) / (parts - p);
+                    out.push_back({PassKind::kRegs, m, hi, hi + 1 - this_r, this_r});
+                    hi -= this_r;
+                }
+            }
+            b_hi = b_lo - 1;
+        }
+        // Steps j = 2^(log_t-1) .. 1 of phase m: the direction is uniform per
+        // tile, both forms coincide; registers with LDS transposes.
+        out.push_back({PassKind::kMerge, m, 0, 0, log_t});
+    }
+    return out;
+}
+
 // Enqueues the whole network (or its first step_limit steps) on keys[0..n).
 meld_status sort_impl(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n,
                       const SortPlan &plan, int64_t step_limit, hipStream_t stream) {
@@ -405,14 +470,19 @@ meld_status sort_impl(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n
         return (int32_t)s;
     };
 
+    if (log_n > plan.log_t && (plan.log_t < kMinLogRegsTile || plan.log_t > max_log_tile(pairs)))
+        return fail(MELD_EINVAL, "sort: tile 2^%u outside 2^%u .. 2^%u", plan.log_t,
+                    kMinLogRegsTile, max_log_tile(pairs));
+    const std::vector<SortPass> passes = sort_passes(plan, pairs, log_n);
+
     hipError_t e;
-    if (log_n <= plan.log_t) {
+    if (passes[0].kind == PassKind::kTile) {
         // One tile holds everything; positions >= n are sentinels.
         const uint32_t log_t = std::max<uint32_t>(log_n, 1);
         const int io = big_n > n ? meld::kIoSentinel
                        : (aligned16(keys) && (!pairs || aligned16(payload))) ? meld::kIoPlainVec
                                                                              : meld::kIoPlain;
-        const int32_t steps = take((uint64_t)log_t * (log_t + 1) / 2);
+        const int32_t steps = take(passes[0].steps);
         if (log_t >= kMinLogRegsTile)
             e = meld::launch_bitonic_sort_regs(a, log_t, 1, steps, plan.lo, plan.hi, io, stream);
         else
@@ -421,9 +491,6 @@ meld_status sort_impl(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n
         if (e != hipSuccess) return hip_fail(e, "bitonic tile launch");
         return MELD_OK;
     }
-    if (plan.log_t < kMinLogRegsTile || plan.log_t > max_log_tile(pairs))
-        return fail(MELD_EINVAL, "sort: tile 2^%u outside 2^%u .. 2^%u", plan.log_t,
-                    kMinLogRegsTile, max_log_tile(pairs));
 
     if (big_n > n) {
         const size_t pad = big_n - n;
@@ -440,42 +507,27 @@ meld_status sort_impl(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n
     const int io = a.tk != nullptr ? meld::kIoTail
                    : (aligned16(keys) && (!pairs || aligned16(payload))) ? meld::kIoPlainVec
                                                                          : meld::kIoPlain;
-    e = meld::launch_bitonic_sort_regs(a, log_t, n_tiles, take((uint64_t)log_t * (log_t + 1) / 2),
-                                       plan.lo, plan.hi, io, stream);
-    if (e != hipSuccess) return hip_fail(e, "bitonic tile launch");
-
-    const uint32_t max_gather = pairs ? meld::kMaxGatherStepsPairs : meld::kMaxGatherStepsKeys;
-    const uint32_t gather_log = pairs ? meld::kGatherLogPairs : meld::kGatherLogKeys;
-    for (uint32_t m = log_t + 1; m <= log_n; ++m) {
-        // Steps j = 2^(m-1) .. 2^log_t stream through HBM in as few passes as
-        // possible: up to kMaxFusedSteps per pass in registers, more (high
-        // bits first) through gathered LDS tiles where their rows fit.
-        uint32_t b_hi = m - 1;
-        for (uint32_t r : split_passes(m - log_t, max_gather)) {
-            const uint32_t b_lo = b_hi + 1 - r;
-            const bool gather_fits = log_n >= gather_log && b_lo + r >= gather_log;
-            if (r > meld::kMaxFusedSteps && gather_fits) {
-                e = meld::launch_bitonic_gather(a, log_n, m, b_hi, b_lo, take(r), io, stream);
-                if (e != hipSuccess) return hip_fail(e, "bitonic gather launch");
-            } else {
-                // register passes only (balanced)
-                const uint32_t parts = (r + meld::kMaxFusedSteps - 1) / meld::kMaxFusedSteps;
-                uint32_t hi = b_hi;
-                for (uint32_t p = 0; p < parts; ++p) {
-                    const uint32_t remaining = hi - b_lo + 1;
-                    const uint32_t this_r = (remaining + (parts - p) - 1) / (parts - p);
-                    e = meld::launch_bitonic_global(a, log_n, m, hi, hi + 1 - this_r,
-                                                    take(this_r), stream);
-                    if (e != hipSuccess) return hip_fail(e, "bitonic global launch");
-                    hi -= this_r;
-                }
-            }
-            b_hi = b_lo - 1;
+    for (const SortPass &p : passes) {
+        const int32_t steps = take(p.steps);
+        switch (p.kind) {
+            case PassKind::kLocal:
+                e = meld::launch_bitonic_sort_regs(a, log_t, n_tiles, steps, plan.lo, plan.hi, io,
+                                                   stream);
+                break;
+            case PassKind::kGather:
+                e = meld::launch_bitonic_gather(a, log_n, p.m, p.b_hi, p.b_lo, steps, io, stream);
+                break;
+            case PassKind::kRegs:
+                e = meld::launch_bitonic_global(a, log_n, p.m, p.b_hi, p.b_lo, steps, stream);
+                break;
+            case PassKind::kMerge:
+                e = meld::launch_bitonic_merge(a, log_t, n_tiles, p.m, steps, io, stream);
+                break;
+            default:
+                return fail(MELD_EINVAL, "sort: unexpected pass");
         }
-        // Steps j = 2^(log_t-1) .. 1 of phase m: the direction is uniform per
-        // tile, both forms coincide; registers with LDS transposes.
-        e = meld::launch_bitonic_merge(a, log_t, n_tiles, m, take(log_t), io, stream);
-        if (e != hipSuccess) return hip_fail(e, "bitonic merge launch");
+        if (e != hipSuccess)
+            return hip_fail(e, fmt("bitonic %s launch", pass_name(p.kind)).c_str());
     }
     return MELD_OK;
 }
@@ -510,6 +562,26 @@ meld_status probe_network(meld_ctx *ctx, uint32_t log_t, hipStream_t s, double *
     return MELD_OK;
 }
 
+// Tuning-cache key of a sort shape class (array size class, pairs, forced tile).
+std::string sort_tune_key(const meld_ctx *ctx, bool pairs, uint32_t log_n) {
+    const uint32_t forced =
+        ctx->sort_log_tile ? std::min(ctx->sort_log_tile, max_log_tile(pairs)) : 0;
+    return forced ? fmt("n=%u pairs=%d t=%u", log_n, pairs ? 1 : 0, forced)
+                  : fmt("n=%u pairs=%d", log_n, pairs ? 1 : 0);
+}
+
+// The tuned plan of a shape class, if the tuner holds a usable one.
+bool cached_sort_plan(const meld_ctx *ctx, bool pairs, uint32_t log_n, SortPlan *out) {
+    if (const meld::TuneEntry *e = ctx->tuner.find("sort", sort_tune_key(ctx, pairs, log_n))) {
+        const uint32_t t = (uint32_t)e->log_t;
+        if (t >= kMinLogRegsTile && t <= max_log_tile(pairs)) {
+            *out = SortPlan{t, e->lo != 0, e->hi != 0};
+            return true;
+        }
+    }
+    return false;
+}
+
 // MELD_AUTO for a sort: the tuned plan of this shape class, timing the
 // candidates (tile size x form per stage) on a scratch copy the first time.
 meld_status auto_sort_plan(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n,
@@ -518,15 +590,8 @@ meld_status auto_sort_plan(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, siz
     const uint32_t log_n = log2_ceil(n);
     const uint32_t max_t = max_log_tile(pairs);
     const uint32_t forced = ctx->sort_log_tile ? std::min(ctx->sort_log_tile, max_t) : 0;
-    const std::string key = forced ? fmt("n=%u pairs=%d t=%u", log_n, pairs ? 1 : 0, forced)
-                                   : fmt("n=%u pairs=%d", log_n, pairs ? 1 : 0);
-    if (const meld::TuneEntry *e = ctx->tuner.find("sort", key)) {
-        const uint32_t t = (uint32_t)e->log_t;
-        if (t >= kMinLogRegsTile && t <= max_t) {
-            *out = SortPlan{t, e->lo != 0, e->hi != 0};
-            return MELD_OK;
-        }
-    }
+    const std::string key = sort_tune_key(ctx, pairs, log_n);
+    if (cached_sort_plan(ctx, pairs, log_n, out)) return MELD_OK;
     *out = SortPlan{plan_log_tile(ctx, pairs, log_n), true, true};
     if (capturing(s)) return MELD_OK;  // no timing inside a capture; untuned default
     // Candidate tiles: from one that leaves a few hundred tiles up to the
@@ -839,11 +904,14 @@ meld_status merge_sort_impl(meld_ctx *ctx, uint32_t *keys, size_t n, int64_t max
     if (n <= (1u << kMergeRunLog) || max_passes == 0) return MELD_OK;
     meld_status st = ensure_words(&ctx->merge_buf, &ctx->merge_words, n, "merge buffer");
     if (st != MELD_OK) return st;
+    st = ensure_words(&ctx->merge_cuts, &ctx->merge_cut_words,
+                      meld::merge_pass_cut_words((uint32_t)n), "merge cuts");
+    if (st != MELD_OK) return st;
     uint32_t *src = keys, *dst = ctx->merge_buf;
     int64_t pass = 0;
     for (uint32_t lr = kMergeRunLog; ((size_t)1 << lr) < n; ++lr) {
         if (max_passes >= 0 && pass == max_passes) break;
-        e = meld::launch_merge_pass(src, dst, (uint32_t)n, lr, melded, s);
+        e = meld::launch_merge_pass(src, dst, (uint32_t)n, lr, melded, ctx->merge_cuts, s);
         if (e != hipSuccess) return hip_fail(e, "merge pass launch");
         std::swap(src, dst);
         ++pass;
@@ -899,7 +967,7 @@ void meld_destroy(meld_ctx *ctx) {
     if (ctx->capture_stream != nullptr) (void)hipStreamDestroy(ctx->capture_stream);
     for (void *p : {(void *)ctx->tail, (void *)ctx->seg_state, (void *)ctx->seg_cls,
                     (void *)ctx->seg_queue, (void *)ctx->seg_work, (void *)ctx->tune_buf,
-                    (void *)ctx->merge_buf, (void *)ctx->probe_buf})
+                    (void *)ctx->merge_buf, (void *)ctx->merge_cuts, (void *)ctx->probe_buf})
         if (p != nullptr) (void)hipFree(p);
     delete ctx;
 }
@@ -924,6 +992,49 @@ meld_status meld_sort_u32(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size
         if (st != MELD_OK) return st;
     }
     return sort_impl(ctx, keys, payload, n, plan, -1, s);
+}
+
+meld_status meld_sort_plan_describe(meld_ctx *ctx, size_t n, int with_payload,
+                                    meld_variant variant, char *buf, size_t len) {
+    const char *name = "meld_sort_plan_describe";
+    if (buf == nullptr) return fail(MELD_EINVAL, "%s: buf must not be NULL", name);
+    if (n >= (1ull << 31)) return fail(MELD_EINVAL, "%s: n = %zu >= 2^31", name, n);
+    if ((unsigned)variant > MELD_MELDED_INPLACE) return fail(MELD_EINVAL, "%s: bad variant", name);
+    const bool pairs = with_payload != 0;
+    const uint32_t log_n = n <= 1 ? 0 : log2_ceil(n);
+    const bool m = variant == MELD_AUTO || use_melded(variant);
+    SortPlan plan{default_log_tile(pairs, log_n), m, m};
+    bool tuned = false;
+    if (ctx != nullptr) {
+        plan.log_t = plan_log_tile(ctx, pairs, log_n);
+        if (variant == MELD_AUTO) tuned = cached_sort_plan(ctx, pairs, log_n, &plan);
+    }
+    std::string d = fmt("{\"n\": %zu, \"log_n\": %u, \"pairs\": %s, \"tuned\": %s", n, log_n,
+                        pairs ? "true" : "false", tuned ? "true" : "false");
+    uint32_t hbm = 0, steps = 0;
+    std::string list;
+    if (n > 1) {
+        const std::vector<SortPass> passes = sort_passes(plan, pairs, log_n);
+        d += fmt(", \"log_tile\": %u, \"low\": \"%s\", \"high\": \"%s\"",
+                 passes[0].kind == PassKind::kTile ? std::max<uint32_t>(log_n, 1) : plan.log_t,
+                 plan.lo ? "melded" : "divergent", plan.hi ? "melded" : "divergent");
+        for (const SortPass &p : passes) {
+            if (!list.empty()) list += ", ";
+            list += fmt("{\"kind\": \"%s\", \"steps\": %u", pass_name(p.kind), p.steps);
+            if (p.kind != PassKind::kTile && p.kind != PassKind::kLocal)
+                list += fmt(", \"m\": %u", p.m);
+            if (p.kind == PassKind::kRegs || p.kind == PassKind::kGather)
+                list += fmt(", \"b_hi\": %u, \"b_lo\": %u", p.b_hi, p.b_lo);
+            list += "}";
+            steps += p.steps;
+        }
+        hbm = (uint32_t)passes.size();
+    }
+    d += fmt(", \"hbm_passes\": %u, \"steps\": %u, \"passes\": [", hbm, steps) + list + "]}";
+    if (d.size() + 1 > len)
+        return fail(MELD_EINVAL, "%s: buffer too small (need %zu bytes)", name, d.size() + 1);
+    std::memcpy(buf, d.c_str(), d.size() + 1);
+    return MELD_OK;
 }
 
 meld_status meld_oddeven_sort_buckets_u32(meld_ctx *ctx, uint32_t *keys, size_t n,

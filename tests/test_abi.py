@@ -64,3 +64,63 @@ def test_python_binding_rejects_non_cuda_tensors():
                               meld.side(1, 0, 1, 1))
     with pytest.raises(ValueError):
         meld._variant("fastest")
+
+
+def _log2_ceil(n):
+    return max(1, (n - 1).bit_length())
+
+
+@pytest.mark.parametrize("pairs", [False, True])
+@pytest.mark.parametrize("n", [2, 3, 255, 256, 1000, 2048, 2049, 1 << 16, (1 << 20) + 7,
+                               1 << 24, 1 << 26, 1 << 28, (1 << 31) - 1])
+def test_sort_plan_covers_every_step_once(n, pairs):
+    # The pass list of the bitonic network (Figure 1): every step j = 2^b of
+    # every phase 2^m appears exactly once and in the network's order
+    # (phases ascending, steps descending), each pass within its kernel's
+    # limits, and the step count is log_n (log_n + 1) / 2.
+    meld, _ = _lib()
+    d = meld.sort_plan(n, pairs)
+    log_n = _log2_ceil(n)
+    assert d["log_n"] == log_n and d["steps"] == log_n * (log_n + 1) // 2
+    passes = d["passes"]
+    assert d["hbm_passes"] == len(passes)
+    if passes[0]["kind"] == "tile":
+        assert len(passes) == 1 and d["log_tile"] == log_n
+        return
+    t = d["log_tile"]
+    assert 8 <= t <= (13 if pairs else 14) and t < log_n
+    assert passes[0] == {"kind": "local", "steps": t * (t + 1) // 2}
+    order = [(m, b) for m in range(t + 1, log_n + 1) for b in range(m - 1, -1, -1)]
+    seen = []
+    for p in passes[1:]:
+        m = p["m"]
+        if p["kind"] == "merge":
+            assert p["steps"] == t
+            seen += [(m, b) for b in range(t - 1, -1, -1)]
+        else:
+            assert p["kind"] in ("regs", "gather")
+            r = p["b_hi"] - p["b_lo"] + 1
+            assert p["steps"] == r and p["b_lo"] >= t
+            assert r <= (6 if p["kind"] == "regs" else (8 if pairs else 9))
+            if p["kind"] == "gather":
+                assert r >= 7
+            seen += [(m, b) for b in range(p["b_hi"], p["b_lo"] - 1, -1)]
+    assert seen == order
+    # fewest passes: per phase one merge tail plus ceil((m - t) / max steps)
+    mx = 8 if pairs else 9
+    assert len(passes) == 1 + sum(1 + -(-(m - t) // mx) for m in range(t + 1, log_n + 1))
+
+
+def test_sort_plan_edge_cases():
+    meld, lib = _lib()
+    assert meld.sort_plan(0)["passes"] == [] and meld.sort_plan(1)["hbm_passes"] == 0
+    assert meld.sort_plan(1 << 28, True)["hbm_passes"] == 38
+    buf = ctypes.create_string_buffer(8)
+    assert lib.meld_sort_plan_describe(None, 1 << 20, 0, 1, buf, 8) == meld.EINVAL
+    assert b"buffer too small" in lib.meld_last_error()
+    big = ctypes.create_string_buffer(4096)
+    assert lib.meld_sort_plan_describe(None, 1 << 31, 0, 1, big, 4096) == meld.EINVAL
+    assert lib.meld_sort_plan_describe(None, 16, 0, 9, big, 4096) == meld.EINVAL
+    assert lib.meld_sort_plan_describe(None, 16, 0, 1, None, 4096) == meld.EINVAL
+    d = meld.sort_plan(1 << 20, False, "divergent")
+    assert d["low"] == d["high"] == "divergent" and d["tuned"] is False

@@ -83,6 +83,28 @@ def test_merge_sort_large_against_oracle():
         assert np.array_equal(_host(kd), ref), v
 
 
+def test_merge_sort_with_cut_kernel_against_oracle():
+    # More than 2048 tiles of 2048 keys: the passes of runs >= 2^11 take their
+    # merge-path cuts from the separate cut kernel (8-way search); a ragged
+    # last pair in every pass, and heavy ties (keys drawn from 64 values).
+    n = (1 << 22) + (1 << 21) + 13
+    keys = workloads.keys_u32(94, n)
+    for k in (keys, keys & np.uint32(63)):
+        ref = oracle.sort_u32(k)
+        for v in ("divergent", "melded"):
+            kd = _to_dev(k)
+            meld.merge_sort(kd, variant=v)
+            torch.cuda.synchronize()
+            assert np.array_equal(_host(kd), ref), v
+    # pass by pass: after p passes each run of 2^(10+p) keys is sorted
+    kd = _to_dev(keys)
+    meld.merge_sort(kd, max_passes=3, variant="melded")
+    torch.cuda.synchronize()
+    got, run = _host(kd), 1 << 13
+    for s0 in range(0, n, run):
+        assert np.array_equal(got[s0:s0 + run], oracle.sort_u32(keys[s0:s0 + run])), s0
+
+
 def test_merge_sort_noop_and_errors():
     for n in (0, 1):
         kd = _to_dev(np.array([7] * n, np.uint32))

@@ -154,7 +154,9 @@ def test_auto_results_match_oracle_and_plans_are_recorded(tmp_path):
     ops = {e["op"] for e in desc["entries"]}
     assert {"sort", "segsort", "region"} <= ops
     for e in desc["entries"]:
-        assert e["trials"] >= 3 and e["ms"] > 0
+        # the ops with two forms only (entries left by earlier tests of the
+        # same context) time two candidates, the others at least three
+        assert e["trials"] >= (2 if e["op"] in ("oddeven", "mergesort") else 3) and e["ms"] > 0
         if e["op"] == "segsort":
             # fractions of mixed comparator-steps per stage (the probe itself is
             # pinned against brute force in test_segments_probe_matches_brute_force)
