@@ -12,8 +12,12 @@
 //           upper when bit_k(e) = 0 and e mod 2p >= k (partner e - k),
 //           idle otherwise.
 // Each lane holds E keys of the bucket (elements t, t + NT, ...) in
-// registers; a step reads partners from the LDS copy, then writes its new
-// keys back.
+// registers; a step reads partners from the LDS copy of the bucket, then
+// writes its new keys. Workgroups of 512 lanes and more keep two copies: a
+// step reads one and writes the other, so one barrier per step orders both
+// (every read of a step precedes its barrier, the next write to that copy
+// follows it); smaller ones, whose barriers are cheap, keep one copy and
+// separate the reads from the writes with a second barrier.
 //
 //   divergent: the element's region as written, an if / else-if on its
 //     role: the lower side loads the partner above and keeps the minimum, the
@@ -57,11 +61,14 @@ __global__ __launch_bounds__(NT) void oddeven_bucket_kernel(uint32_t *__restrict
         s[t + (uint32_t)r * NT] = v[r];
     }
     __syncthreads();
+    constexpr bool kTwoCopies = NT >= 512;
     int32_t steps = 0;
+    uint32_t *cur = s, *nxt = kTwoCopies ? s + T : s;
     for (uint32_t p = 1; p < T; p <<= 1) {
         for (uint32_t k = p; k >= 1; k >>= 1) {
             if (steps == max_steps) goto done;
             ++steps;
+            const uint32_t *sc = cur;
             uint32_t nv[E];
 #pragma unroll
             for (int r = 0; r < E; ++r) {
@@ -69,7 +76,7 @@ __global__ __launch_bounds__(NT) void oddeven_bucket_kernel(uint32_t *__restrict
                 const int role = oe_role(e, p, k);
                 if constexpr (MELDED) {
                     const uint32_t partner = role > 0 ? e + k : (role < 0 ? e - k : e);
-                    const uint32_t b = s[partner];
+                    const uint32_t b = sc[partner];
                     const uint32_t mn = v[r] < b ? v[r] : b;
                     const uint32_t mx = v[r] < b ? b : v[r];
                     nv[r] = role > 0 ? mn : (role < 0 ? mx : v[r]);
@@ -77,22 +84,25 @@ __global__ __launch_bounds__(NT) void oddeven_bucket_kernel(uint32_t *__restrict
                     nv[r] = v[r];
                     if (role > 0) {
                         MELD_SIDE_MARK("lower");
-                        const uint32_t b = s[e + k];
+                        const uint32_t b = sc[e + k];
                         if (b < v[r]) nv[r] = b;
                     } else if (role < 0) {
                         MELD_SIDE_MARK("upper");
-                        const uint32_t b = s[e - k];
+                        const uint32_t b = sc[e - k];
                         if (b > v[r]) nv[r] = b;
                     }
                 }
             }
-            __syncthreads();  // every partner read before any key changes
+            if constexpr (!kTwoCopies) __syncthreads();  // every partner read before any write
 #pragma unroll
             for (int r = 0; r < E; ++r) {
                 v[r] = nv[r];
-                s[t + (uint32_t)r * NT] = v[r];
+                nxt[t + (uint32_t)r * NT] = v[r];
             }
             __syncthreads();
+            uint32_t *w = cur;
+            cur = nxt;
+            nxt = w;
         }
     }
 done:
@@ -107,13 +117,15 @@ template <int E, int NT>
 hipError_t launch_oe(uint32_t *keys, uint32_t n, uint32_t log_t, int32_t max_steps, bool melded,
                      hipStream_t stream) {
     const uint32_t buckets = (uint32_t)(((uint64_t)n + (1u << log_t) - 1) >> log_t);
-    const size_t lds = ((size_t)1 << log_t) * sizeof(uint32_t);
-    if (melded)
-        hipLaunchKernelGGL((oddeven_bucket_kernel<E, NT, true>), dim3(buckets), dim3(NT), lds,
-                           stream, keys, n, log_t, max_steps);
-    else
-        hipLaunchKernelGGL((oddeven_bucket_kernel<E, NT, false>), dim3(buckets), dim3(NT), lds,
-                           stream, keys, n, log_t, max_steps);
+    const size_t lds = ((size_t)(NT >= 512 ? 2 : 1) << log_t) * sizeof(uint32_t);
+    auto kern = melded ? oddeven_bucket_kernel<E, NT, true> : oddeven_bucket_kernel<E, NT, false>;
+    if (lds > 64 * 1024) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3(buckets), dim3(NT), lds, stream, keys, n, log_t, max_steps);
     return hipGetLastError();
 }
 
