@@ -105,6 +105,18 @@ def test_merge_sort_with_cut_kernel_against_oracle():
         assert np.array_equal(got[s0:s0 + run], oracle.sort_u32(keys[s0:s0 + run])), s0
 
 
+def test_merge_sort_timed_size_against_oracle():
+    # The timed configuration: 2^24 keys of seed 1, both forms.
+    n = 1 << 24
+    keys = workloads.keys_u32(1, n)
+    ref = oracle.sort_u32(keys)
+    for v in ("divergent", "melded"):
+        kd = _to_dev(keys)
+        meld.merge_sort(kd, variant=v)
+        torch.cuda.synchronize()
+        assert np.array_equal(_host(kd), ref), v
+
+
 def test_merge_sort_noop_and_errors():
     for n in (0, 1):
         kd = _to_dev(np.array([7] * n, np.uint32))

@@ -133,6 +133,27 @@ def test_region_lanetrips_parity(rng_, p):
         assert _same_bits(y.cpu().numpy(), ref), (v, rng_, p)
 
 
+def test_region_lanetrips_full_size_sampled():
+    # The timed configuration: 2^24 lanes, 64 MiB table, trips in [8, 32] per
+    # lane on both sides, p = 0.5. The forms agree on every lane; sampled lane
+    # ranges against the oracle.
+    dev = _dev()
+    seed, n = 1, 1 << 24
+    x, tab, _, _ = workloads.region_inputs(seed, n)
+    st, sf = _ranges(8, 32, 8, 32)
+    thr = workloads.thr_from_p(0.5)
+    xd = torch.from_numpy(x).to(dev)
+    td = torch.from_numpy(tab).to(dev)
+    outs = {v: meld.region_lanetrips(xd, td, seed, thr, st, sf, variant=v).cpu().numpy()
+            for v in VARIANTS[:3]}
+    assert _same_bits(outs["divergent"], outs["melded"])
+    assert _same_bits(outs["divergent"], outs["melded_inplace"])
+    rng = np.random.default_rng(2)
+    for s0 in sorted(set(rng.integers(0, n - 2048, 8).tolist()) | {0, n - 2048}):
+        ref = oracle.region_lanetrips_f32(x[s0:s0 + 2048], tab, seed, thr, st, sf, i0=s0)
+        assert _same_bits(outs["melded"][s0:s0 + 2048], ref), s0
+
+
 def test_region_lanetrips_counts_exactly():
     # a = 1, tab = 1, x = 0: every lane's result is its own trip count.
     n = 20000
