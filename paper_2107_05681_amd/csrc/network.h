@@ -41,16 +41,23 @@ __device__ __forceinline__ void cex_divergent(E *s, uint32_t lo, uint32_t hi, bo
     }
 }
 
+// Swap condition of the melded compare-exchange: select(up, b < a, b > a),
+// the two sides' compares chosen by the direction. Written as lane-mask
+// operations (the compare's mask flipped for descending lanes, equal elements
+// never swap): as a select of two booleans hipcc keeps both compares as 0/1
+// values in VGPRs and tests the selected one again, four VALU operations more.
+template <typename E>
+__device__ __forceinline__ bool melded_swap(E a, E b, bool up) {
+    return ((b < a) == up) & (a != b);
+}
+
 // The melded region: one load pair, both compares, a select of the swap
 // condition, one conditional store pair.
 template <typename E>
 __device__ __forceinline__ void cex_melded(E *s, uint32_t lo, uint32_t hi, bool up) {
     const E a = s[lo];
     const E b = s[hi];
-    const bool lt = b < a;
-    const bool gt = b > a;
-    const bool swap = (up & lt) | (!up & gt);  // select(up, lt, gt) on lane masks
-    if (swap) {
+    if (melded_swap(a, b, up)) {
         s[lo] = b;
         s[hi] = a;
     }
@@ -137,14 +144,24 @@ __device__ __forceinline__ void lds_step_group(E *s, uint32_t base, uint32_t m, 
             a[i] = s[lo[i]];
             b[i] = s[lo[i] + j];
         }
+        if (nt >= 64) {
+            // nt is a multiple of 64 >= 2^m: every comparator of the lane has
+            // the direction of its first one
+            const bool up = (((base | lo[0]) >> m) & 1u) == 0;
 #pragma unroll
-        for (int i = 0; i < ITERS; ++i) {
-            const bool up = (((base | lo[i]) >> m) & 1u) == 0;
-            const bool lt = b[i] < a[i];
-            const bool gt = b[i] > a[i];
-            if ((up & lt) | (!up & gt)) {
-                s[lo[i]] = b[i];
-                s[lo[i] + j] = a[i];
+            for (int i = 0; i < ITERS; ++i)
+                if (melded_swap(a[i], b[i], up)) {
+                    s[lo[i]] = b[i];
+                    s[lo[i] + j] = a[i];
+                }
+        } else {
+#pragma unroll
+            for (int i = 0; i < ITERS; ++i) {
+                const bool up = (((base | lo[i]) >> m) & 1u) == 0;
+                if (melded_swap(a[i], b[i], up)) {
+                    s[lo[i]] = b[i];
+                    s[lo[i] + j] = a[i];
+                }
             }
         }
     } else if (nt >= 64) {

@@ -58,6 +58,8 @@ __device__ __forceinline__ uint32_t window_tpart(uint32_t t, uint32_t B) {
     return (t & ((1u << B) - 1)) | ((t >> B) << (B + 4));
 }
 
+// Compare-exchange of two registers for direction up, with no branch: min
+// and max, then one select per output on the direction.
 __device__ __forceinline__ void cex_regs(uint32_t &x, uint32_t &y, bool up) {
     const uint32_t mn = x < y ? x : y;
     const uint32_t mx = x < y ? y : x;

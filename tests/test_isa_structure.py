@@ -82,9 +82,11 @@ def test_bitonic_melded_has_one_load_store_pair(bitonic_asm, pairs):
     # the comparator loop: one load pair and one (conditional) store pair
     loop = body[body.index(f"ds_read_{width}", body.index("s_barrier")):]
     assert loop.count(f"ds_write_{width}") >= 2
-    cmp_lt = len(re.findall(r"v_cmp_lt_u(32|64)", body))
-    cmp_gt = len(re.findall(r"v_cmp_gt_u(32|64)", body))
-    assert cmp_lt >= 1 and cmp_gt >= 1  # both unaligned compares run
+    # select(up, b < a, b > a) as lane-mask logic: an order compare whose mask
+    # the direction flips (a scalar xor), and the tie test
+    assert re.search(r"v_cmp_(lt|gt|le|ge)_u(32|64)", body)
+    assert re.search(r"v_cmp_ne_u(32|64)", body)
+    assert re.search(r"s_xn?or_b64", body)
 
 
 def test_region_divergent_has_a_loop_per_side(region_asm):
@@ -119,7 +121,10 @@ def test_register_phases_divergent_vs_melded(bitonic_asm, pairs):
         assert blocks, side
         assert re.search(rf"v_cmp_[lg]t_{width}", blocks[0]), side
     assert "; side" not in mel
-    assert re.search(rf"v_cmp_lt_{width}", mel) and "v_cndmask_b32" in mel
+    # one order compare per comparator, its mask flipped by the direction
+    # (a scalar xor), then the selects
+    assert re.search(rf"v_cmp_(lt|gt|le|ge)_{width}", mel) and "v_cndmask_b32" in mel
+    assert re.search(r"s_xn?or_b64", mel)
 
 
 @pytest.fixture(scope="module")
