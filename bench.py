@@ -495,6 +495,10 @@ def _bench_sort(torch, np, meld, workloads, dev, args):
                         "divergent_us_dist": _dist(np, times["divergent"]),
                         "melded_us_dist": _dist(np, times["melded"]),
                         "log_tile": plan["log_tile"], "hbm_passes": plan["hbm_passes"],
+                        "hbm_frac": round(8.0 * n * plan["hbm_passes"] / (m * 1e-3) / 1e9
+                                          / HBM_PEAK_GBS, 5),
+                        "hbm_frac_note": "not meaningful: 256 KiB per pass, the sort is bound "
+                                         "by launch and per-tile latency",
                         "local_sort_kernel": {
                             "steps": local,
                             "divergent_us": round(tl["divergent"] * 1e3, 2),
@@ -603,7 +607,10 @@ def _bench_serving(meld, workloads, seconds):
     summ = serve.latency_summary(done)
     return {"rate_per_s": 2000, "seconds": seconds, "jobs": summ["jobs"],
             "failed": st["failed"], "p50_ms": round(summ["p50_ms"], 3),
-            "p99_ms": round(summ["p99_ms"], 3), "jobs_per_s": round(summ["jobs_per_s"], 1),
+            "p99_ms": round(summ["p99_ms"], 3), "wait_p50_ms": round(summ["wait_p50_ms"], 3),
+            "wait_p99_ms": round(summ["wait_p99_ms"], 3),
+            "busy_fraction": round(summ["busy_fraction"], 4),
+            "jobs_per_s": round(summ["jobs_per_s"], 1),
             "Gkeys_s": round(summ["keys_per_s"] / 1e9, 4),
             "Glanes_s": round(summ["lanes_per_s"] / 1e9, 4), "launches": st["launches"],
             "batched_jobs": st["batched_jobs"], "max_concurrent": st["max_concurrent"],

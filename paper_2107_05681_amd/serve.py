@@ -169,7 +169,19 @@ def latency_summary(done: list[dict]) -> dict:
     span = max(c["done_s"] for c in done) - min(c["submit_s"] for c in done)
     keys = sum(c["n"] for c in done if c["kind"] == JOB_SORT)
     lanes = sum(c["n"] for c in done if c["kind"] == JOB_REGION)
+    wait = np.array([c["start_s"] - c["submit_s"] for c in done])
+    # utilisation: the share of the span during which at least one job ran
+    busy, end = 0.0, -np.inf
+    for a, b in sorted((c["start_s"], c["done_s"]) for c in done):
+        if a > end:
+            busy += b - a
+            end = b
+        elif b > end:
+            busy += b - end
+            end = b
     return dict(jobs=len(done), p50_ms=float(np.percentile(lat, 50) * 1e3),
                 p99_ms=float(np.percentile(lat, 99) * 1e3), mean_ms=float(lat.mean() * 1e3),
+                wait_p50_ms=float(np.percentile(wait, 50) * 1e3),
+                wait_p99_ms=float(np.percentile(wait, 99) * 1e3),
                 jobs_per_s=len(done) / span, keys_per_s=keys / span, lanes_per_s=lanes / span,
-                span_s=span)
+                span_s=span, busy_fraction=busy / span if span > 0 else 0.0)

@@ -100,3 +100,17 @@ def test_release_of_unknown_job_fails():
     with serve.Server(budget_bytes=1 << 20, slots=1, simulated_ns_per_item=1) as srv:
         with pytest.raises(meld.MeldError):
             srv.release(12345)
+
+
+def test_latency_summary_busy_fraction_and_waits():
+    from paper_2107_05681_amd import serve
+
+    def job(sub, start, done, kind=serve.JOB_SORT, n=10):
+        return dict(submit_s=sub, start_s=start, done_s=done, kind=kind, n=n)
+    # runs [1, 3) and [2, 4) overlap into [1, 4); [6, 7) alone; span [0, 10)
+    done = [job(0.0, 1.0, 3.0), job(0.5, 2.0, 4.0), job(5.0, 6.0, 7.0), job(9.0, 9.5, 10.0)]
+    s = serve.latency_summary(done)
+    assert s["span_s"] == 10.0
+    assert abs(s["busy_fraction"] - (3.0 + 1.0 + 0.5) / 10.0) < 1e-12
+    assert abs(s["wait_p50_ms"] - 1000.0) < 1e-9  # waits 1.0, 1.5, 1.0, 0.5: median 1.0
+    assert s["jobs"] == 4 and abs(s["keys_per_s"] - 4.0) < 1e-12
