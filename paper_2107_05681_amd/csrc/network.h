@@ -132,10 +132,19 @@ template <typename E, bool MELDED, int ITERS>
 __device__ __forceinline__ void lds_step_group(E *s, uint32_t base, uint32_t m, uint32_t j,
                                                uint32_t lane0, uint32_t nt) {
     uint32_t lo[ITERS];
+    if (nt >= 64) {
+        // j <= 32 in phases k <= 64 and nt is a multiple of 64: inserting the
+        // zero bit at j leaves the comparators i * nt apart as 2 i nt, so only
+        // the first index is computed (the rest become immediate offsets)
+        const uint32_t lo0 = ((lane0 & ~(j - 1)) << 1) | (lane0 & (j - 1));
 #pragma unroll
-    for (int i = 0; i < ITERS; ++i) {
-        const uint32_t c = lane0 + (uint32_t)i * nt;
-        lo[i] = ((c & ~(j - 1)) << 1) | (c & (j - 1));
+        for (int i = 0; i < ITERS; ++i) lo[i] = lo0 + 2u * (uint32_t)i * nt;
+    } else {
+#pragma unroll
+        for (int i = 0; i < ITERS; ++i) {
+            const uint32_t c = lane0 + (uint32_t)i * nt;
+            lo[i] = ((c & ~(j - 1)) << 1) | (c & (j - 1));
+        }
     }
     if constexpr (MELDED) {
         E a[ITERS], b[ITERS];
