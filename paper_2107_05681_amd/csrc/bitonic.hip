@@ -231,6 +231,12 @@ __device__ __forceinline__ uint32_t merge_index(uint32_t t, uint32_t r) {
 
 __device__ __forceinline__ uint32_t merge_phys(uint32_t i) { return i + (i >> 4); }
 
+// For a layout index a | b with disjoint bit fields a (lane bits) and b
+// (register bits), (a | b) >> 4 = (a >> 4) + (b >> 4), so
+// merge_phys(a | b) = merge_phys(a) + merge_phys(b): the lane part is computed
+// once per transpose and the register part is a constant, an immediate offset
+// of the LDS access (a scalar for a window known only at run time).
+
 // Windows of a pass whose steps stop at element bit SLO: base bit and top
 // step bit of window w >= 1; the last layout is the last window that holds a
 // step (-1, layout V, when V's two steps are all).
@@ -254,10 +260,12 @@ constexpr int last_layout() {
 template <int L, int FROM, int TO, typename E>
 __device__ __forceinline__ void merge_transpose(E (&e)[kMergeE], E *s, uint32_t t) {
 #pragma unroll
-    for (int r = 0; r < kMergeE; ++r) s[merge_phys(merge_index<L, FROM>(t, r))] = e[r];
+    for (int r = 0; r < kMergeE; ++r)
+        s[merge_phys(merge_index<L, FROM>(t, 0u)) + merge_phys(merge_index<L, FROM>(0u, r))] = e[r];
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kMergeE; ++r) e[r] = s[merge_phys(merge_index<L, TO>(t, r))];
+    for (int r = 0; r < kMergeE; ++r)
+        e[r] = s[merge_phys(merge_index<L, TO>(t, 0u)) + merge_phys(merge_index<L, TO>(0u, r))];
     __syncthreads();
 }
 
@@ -529,12 +537,13 @@ __global__ __launch_bounds__(1 << (L - 4)) void bitonic_sort_regs_kernel(SortArr
             const uint32_t B = m > 4 * w ? m - 4 * w : 0;
             const int hi_q = (int)(m - 4 * (w - 1) - 1 - B);
             if (B != prev) {
-                const uint32_t tp = window_tpart(t, prev), tb = window_tpart(t, B);
+                const uint32_t tp = merge_phys(window_tpart(t, prev));
+                const uint32_t tb = merge_phys(window_tpart(t, B));
 #pragma unroll
-                for (int r = 0; r < kMergeE; ++r) s[merge_phys(tp | ((uint32_t)r << prev))] = e[r];
+                for (int r = 0; r < kMergeE; ++r) s[tp + merge_phys((uint32_t)r << prev)] = e[r];
                 __syncthreads();
 #pragma unroll
-                for (int r = 0; r < kMergeE; ++r) e[r] = s[merge_phys(tb | ((uint32_t)r << B))];
+                for (int r = 0; r < kMergeE; ++r) e[r] = s[tb + merge_phys((uint32_t)r << B)];
                 __syncthreads();
             }
             reg_steps<MELD_HI>(e, hi_q, up, left);

@@ -53,6 +53,11 @@ __device__ __forceinline__ void opaque(uint32_t &v) { asm volatile("" : "+v"(v))
 
 __device__ __forceinline__ uint32_t padded(uint32_t i) { return i + (i >> 4); }
 
+// For a window index tp | (r << B) the lane bits tp and the register bits are
+// disjoint fields, and then padded(tp | b) = padded(tp) + padded(b) (no shifted
+// bit of one field meets the other): the lane part is computed once per
+// transpose, the register part is a scalar (the window is the workgroup's).
+
 // Window B: element bits [B, B+4) are the register index, the others the lane.
 __device__ __forceinline__ uint32_t window_tpart(uint32_t t, uint32_t B) {
     return (t & ((1u << B) - 1)) | ((t >> B) << (B + 4));
@@ -229,12 +234,12 @@ __device__ __forceinline__ void phase_windows(uint32_t (&e)[kSegE], uint32_t *s,
     for (int top = hi_bit; top >= 0;) {
         const uint32_t B = top >= 3 ? (uint32_t)(top - 3) : 0u;
         if (B != cur) {
-            const uint32_t tp = window_tpart(t, cur), tb = window_tpart(t, B);
+            const uint32_t tp = padded(window_tpart(t, cur)), tb = padded(window_tpart(t, B));
 #pragma unroll
-            for (int r = 0; r < kSegE; ++r) s[padded(tp | ((uint32_t)r << cur))] = e[r];
+            for (int r = 0; r < kSegE; ++r) s[tp + padded((uint32_t)r << cur)] = e[r];
             __syncthreads();
 #pragma unroll
-            for (int r = 0; r < kSegE; ++r) e[r] = s[padded(tb | ((uint32_t)r << B))];
+            for (int r = 0; r < kSegE; ++r) e[r] = s[tb + padded((uint32_t)r << B)];
             __syncthreads();
         }
         seg_reg_steps<MELDED>(e, top - (int)B, up, unlimited);
@@ -247,12 +252,12 @@ __device__ __forceinline__ void phase_windows(uint32_t (&e)[kSegE], uint32_t *s,
 __device__ __forceinline__ void to_window(uint32_t (&e)[kSegE], uint32_t *s, uint32_t t,
                                           uint32_t &cur, uint32_t B) {
     if (B == cur) return;
-    const uint32_t tp = window_tpart(t, cur), tb = window_tpart(t, B);
+    const uint32_t tp = padded(window_tpart(t, cur)), tb = padded(window_tpart(t, B));
 #pragma unroll
-    for (int r = 0; r < kSegE; ++r) s[padded(tp | ((uint32_t)r << cur))] = e[r];
+    for (int r = 0; r < kSegE; ++r) s[tp + padded((uint32_t)r << cur)] = e[r];
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kSegE; ++r) e[r] = s[padded(tb | ((uint32_t)r << B))];
+    for (int r = 0; r < kSegE; ++r) e[r] = s[tb + padded((uint32_t)r << B)];
     __syncthreads();
     cur = B;
 }
