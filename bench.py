@@ -91,6 +91,16 @@ def _dist(np, samples_ms, scale=1e3):
             "p90": round(float(np.percentile(a, 90)), 2)}
 
 
+def _tuned_region_form(meld, tt, tf):
+    """The form MELD_AUTO chose for the 2^24-lane region at p = 0.5 with trips (tt, tf)."""
+    names = {0: "divergent", 1: "melded", 2: "melded_inplace"}
+    key = f"n=24 tab=24 tT={tt} tF={tf} p10=5"
+    for e in json.loads(meld.plan_describe())["entries"]:
+        if e["op"] == "region" and e["key"] == key:
+            return names.get(e["form"], str(e["form"]))
+    return None
+
+
 def _mixed_fraction(p, wave=64):
     return 1.0 - p ** wave - (1.0 - p) ** wave
 
@@ -217,13 +227,15 @@ def main():
                                   out=ys[0.5])
 
         tm = {}
-        for v in ("divergent", "melded"):
-            region_trips(v)
+        for v in ("divergent", "melded", "auto"):
+            region_trips(v)  # "auto": the tuner times the forms for this shape once
             tm[v] = float(np.median([_events_time(torch, lambda: region_trips(v), args.reps)
                                      for _ in range(3)]))
         trips_sweep[f"{tt},{tf}"] = {"divergent_us": round(tm["divergent"] * 1e3, 2),
                                      "melded_us": round(tm["melded"] * 1e3, 2),
-                                     "speedup": round(tm["divergent"] / tm["melded"], 4)}
+                                     "speedup": round(tm["divergent"] / tm["melded"], 4),
+                                     "auto_us": round(tm["auto"] * 1e3, 2),
+                                     "auto_form": _tuned_region_form(meld, tt, tf)}
 
     variants = _bench_region_variants(torch, np, meld, workloads, xd, td, ys[0.5], args)
     seeds = _bench_seeds(torch, np, meld, workloads, dev, args)
@@ -358,13 +370,14 @@ def _bench_region_variants(torch, np, meld, workloads, xd, td, y, args):
 
     def measure(run):
         t = {}
-        for v in ("divergent", "melded", "melded_inplace"):
-            run(v)
+        for v in ("divergent", "melded", "melded_inplace", "auto"):
+            run(v)  # "auto": the tuner times the three forms for this shape once
             t[v] = float(np.median([_events_time(torch, lambda: run(v), args.reps)
                                     for _ in range(3)]))
         return {"divergent_us": round(t["divergent"] * 1e3, 2),
                 "melded_us": round(t["melded"] * 1e3, 2),
                 "melded_inplace_us": round(t["melded_inplace"] * 1e3, 2),
+                "auto_us": round(t["auto"] * 1e3, 2),
                 "speedup": round(t["divergent"] / t["melded"], 4)}
 
     out = {}

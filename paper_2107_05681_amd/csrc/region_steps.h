@@ -107,14 +107,26 @@ __device__ __forceinline__ float melded_common_steps(float acc, bool taken, uint
                                                      uint32_t mask) {
     uint32_t k = 0;
     for (; k + kChunkMax <= steps; k += kBatch) {
-        float g[kBatch];
+        // The end marks keep every gather inside its side's block: without
+        // them the compiler sinks the two blocks' last gathers into one gather
+        // after the join, whose address is selected per lane, the costly
+        // mixed-stream form. Each side loads into registers of its own (the
+        // fma operand is selected per lane): loads into the same registers
+        // make the compiler wait for one side's gathers before issuing the
+        // other's.
+        float gt[kBatch], gf[kBatch];
         if (taken) {
             MELD_SIDE_MARK("gathers true");
-            gather_group(g, idx_t, step_t, tab, mask);
+            gather_group(gt, idx_t, step_t, tab, mask);
+            MELD_SIDE_MARK("gathers true end");
         } else {
             MELD_SIDE_MARK("gathers false");
-            gather_group(g, idx_f, step_f, tab, mask);
+            gather_group(gf, idx_f, step_f, tab, mask);
+            MELD_SIDE_MARK("gathers false end");
         }
+        float g[kBatch];
+#pragma unroll
+        for (int u = 0; u < (int)kBatch; ++u) g[u] = taken ? gt[u] : gf[u];
         acc = fma_group(acc, a, g);
         idx_t += kBatch * step_t;
         idx_f += kBatch * step_f;
@@ -125,9 +137,11 @@ __device__ __forceinline__ float melded_common_steps(float acc, bool taken, uint
         if (taken) {
             MELD_SIDE_MARK("gathers true");
             gather_chunk(ch, c, idx_t, step_t, tab, mask);
+            MELD_SIDE_MARK("gathers true end");
         } else {
             MELD_SIDE_MARK("gathers false");
             gather_chunk(ch, c, idx_f, step_f, tab, mask);
+            MELD_SIDE_MARK("gathers false end");
         }
         acc = fma_chunk(acc, a, ch, c);
     }
