@@ -70,26 +70,63 @@ __global__ __launch_bounds__(NT) void oddeven_bucket_kernel(uint32_t *__restrict
             ++steps;
             const uint32_t *sc = cur;
             uint32_t nv[E];
-#pragma unroll
-            for (int r = 0; r < E; ++r) {
-                const uint32_t e = t + (uint32_t)r * NT;
-                const int role = oe_role(e, p, k);
+            if (2 * p <= (uint32_t)NT) {
+                // r * NT is a multiple of 2p: every element of the lane has the
+                // role of element t, so the role, and the partner offset, are
+                // computed once per step (the divergent form branches once per
+                // step, each side with its own loads).
+                const int role = oe_role(t, p, k);
                 if constexpr (MELDED) {
-                    const uint32_t partner = role > 0 ? e + k : (role < 0 ? e - k : e);
-                    const uint32_t b = sc[partner];
-                    const uint32_t mn = v[r] < b ? v[r] : b;
-                    const uint32_t mx = v[r] < b ? b : v[r];
-                    nv[r] = role > 0 ? mn : (role < 0 ? mx : v[r]);
+                    const int32_t d = role > 0 ? (int32_t)k : (role < 0 ? -(int32_t)k : 0);
+                    const uint32_t *pp = sc + ((int32_t)t + d);
+#pragma unroll
+                    for (int r = 0; r < E; ++r) {
+                        const uint32_t b = pp[(uint32_t)r * NT];
+                        const uint32_t mn = v[r] < b ? v[r] : b;
+                        const uint32_t mx = v[r] < b ? b : v[r];
+                        nv[r] = role > 0 ? mn : (role < 0 ? mx : v[r]);
+                    }
                 } else {
-                    nv[r] = v[r];
+#pragma unroll
+                    for (int r = 0; r < E; ++r) nv[r] = v[r];
                     if (role > 0) {
                         MELD_SIDE_MARK("lower");
-                        const uint32_t b = sc[e + k];
-                        if (b < v[r]) nv[r] = b;
+#pragma unroll
+                        for (int r = 0; r < E; ++r) {
+                            const uint32_t b = sc[t + (uint32_t)r * NT + k];
+                            if (b < v[r]) nv[r] = b;
+                        }
                     } else if (role < 0) {
                         MELD_SIDE_MARK("upper");
-                        const uint32_t b = sc[e - k];
-                        if (b > v[r]) nv[r] = b;
+#pragma unroll
+                        for (int r = 0; r < E; ++r) {
+                            const uint32_t b = sc[t + (uint32_t)r * NT - k];
+                            if (b > v[r]) nv[r] = b;
+                        }
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < E; ++r) {
+                    const uint32_t e = t + (uint32_t)r * NT;
+                    const int role = oe_role(e, p, k);
+                    if constexpr (MELDED) {
+                        const uint32_t partner = role > 0 ? e + k : (role < 0 ? e - k : e);
+                        const uint32_t b = sc[partner];
+                        const uint32_t mn = v[r] < b ? v[r] : b;
+                        const uint32_t mx = v[r] < b ? b : v[r];
+                        nv[r] = role > 0 ? mn : (role < 0 ? mx : v[r]);
+                    } else {
+                        nv[r] = v[r];
+                        if (role > 0) {
+                            MELD_SIDE_MARK("lower");
+                            const uint32_t b = sc[e + k];
+                            if (b < v[r]) nv[r] = b;
+                        } else if (role < 0) {
+                            MELD_SIDE_MARK("upper");
+                            const uint32_t b = sc[e - k];
+                            if (b > v[r]) nv[r] = b;
+                        }
                     }
                 }
             }
