@@ -106,10 +106,23 @@ __global__ __launch_bounds__(NT) void oddeven_bucket_kernel(uint32_t *__restrict
                     }
                 }
             } else {
+                // 2p > NT: element r is t + r NT with rr = r NT mod 2p a
+                // multiple of NT. For k >= NT bit k of the element is a bit of
+                // r and the role depends on r alone (scalar); for k < NT bit k
+                // is t's and the block-edge tests compare t with scalars.
+                const bool tbit = (t & k) != 0;
 #pragma unroll
                 for (int r = 0; r < E; ++r) {
                     const uint32_t e = t + (uint32_t)r * NT;
-                    const int role = oe_role(e, p, k);
+                    const uint32_t rr = ((uint32_t)r * NT) & (2 * p - 1);
+                    int role;
+                    if (k >= (uint32_t)NT) {
+                        const bool rbit = (((uint32_t)r * NT) & k) != 0;
+                        role = k == p ? (rbit ? -1 : 1)
+                                      : (rbit ? (rr + k < 2 * p ? 1 : 0) : (rr >= k ? -1 : 0));
+                    } else {
+                        role = tbit ? (t + rr + k < 2 * p ? 1 : 0) : (t + rr >= k ? -1 : 0);
+                    }
                     if constexpr (MELDED) {
                         const uint32_t partner = role > 0 ? e + k : (role < 0 ? e - k : e);
                         const uint32_t b = sc[partner];
