@@ -42,7 +42,7 @@ def _parse():
     ap.add_argument("--no-sort", action="store_true", help="skip the sort measurements")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-seg", action="store_true", help="skip the segmented sort")
-    ap.add_argument("--serve-seconds", type=float, default=2.0,
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the Poisson serving trace (0 skips serving)")
     ap.add_argument("--profile", nargs="?", const="region", default=None,
                     choices=["region", "sort", "pairs", "next"],
