@@ -73,15 +73,21 @@ __device__ __forceinline__ void gather_group_way(float (&g)[G], uint32_t way, ui
                                                  uint32_t i1, uint32_t i2, const RegionSide &W0,
                                                  const RegionSide &W1, const RegionSide &W2,
                                                  const float *__restrict__ tab, uint32_t mask) {
+    // The end marks keep all of a way's gathers in its block: without them the
+    // compiler sinks most of them past the join as gathers whose address is
+    // selected per lane among the three ways (the costly mixed-stream form).
     if (way == 0) {
         MELD_SIDE_MARK("gathers way 0");
         gather_group(g, i0, W0.step, tab, mask);
+        MELD_SIDE_MARK("gathers way 0 end");
     } else if (way == 1) {
         MELD_SIDE_MARK("gathers way 1");
         gather_group(g, i1, W1.step, tab, mask);
+        MELD_SIDE_MARK("gathers way 1 end");
     } else {
         MELD_SIDE_MARK("gathers way 2");
         gather_group(g, i2, W2.step, tab, mask);
+        MELD_SIDE_MARK("gathers way 2 end");
     }
 }
 
@@ -106,12 +112,15 @@ __device__ __forceinline__ float melded3_steps(float acc, uint32_t way, uint32_t
         if (way == 0) {
             MELD_SIDE_MARK("gathers way 0");
             gather_chunk(ch, c, i0, W0.step, tab, mask);
+            MELD_SIDE_MARK("gathers way 0 end");
         } else if (way == 1) {
             MELD_SIDE_MARK("gathers way 1");
             gather_chunk(ch, c, i1, W1.step, tab, mask);
+            MELD_SIDE_MARK("gathers way 1 end");
         } else {
             MELD_SIDE_MARK("gathers way 2");
             gather_chunk(ch, c, i2, W2.step, tab, mask);
+            MELD_SIDE_MARK("gathers way 2 end");
         }
         acc = fma_chunk(acc, a, ch, c);
     }
