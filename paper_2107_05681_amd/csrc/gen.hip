@@ -11,7 +11,7 @@ namespace {
 
 // keys[i] = stream(seed, 1)[i] >> 32
 __global__ __launch_bounds__(256) void gen_keys_kernel(uint32_t *keys, uint32_t n, uint64_t key) {
-    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    const uint32_t i = linear_block() * 256 + threadIdx.x;
     if (i < n) keys[i] = (uint32_t)(mix64(key + i) >> 32);
 }
 
@@ -24,19 +24,19 @@ __global__ __launch_bounds__(256) void gen_keys_segments_kernel(uint32_t *keys,
     if (s >= nseg) return;
     const uint32_t lo = offsets[s], len = offsets[s + 1] - lo;
     const uint64_t key = stream_key(seeds[s], 1);
-    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < len; i += gridDim.x * 256)
-        keys[lo + i] = (uint32_t)(mix64(key + i) >> 32);
+    for (uint64_t i = blockIdx.x * 256 + threadIdx.x; i < len; i += (uint64_t)gridDim.x * 256)
+        keys[lo + (uint32_t)i] = (uint32_t)(mix64(key + i) >> 32);
 }
 
 // x[i] = (stream(seed, 2)[i] >> 40) * 2^-24
 __global__ __launch_bounds__(256) void gen_x_kernel(float *x, uint32_t n, uint64_t key) {
-    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    const uint32_t i = linear_block() * 256 + threadIdx.x;
     if (i < n) x[i] = (float)(mix64(key + i) >> 40) * 0x1p-24f;
 }
 
 // tab[m] = 0.5 + (stream(seed, 3)[m] >> 41) * 2^-24
 __global__ __launch_bounds__(256) void gen_tab_kernel(float *tab, uint32_t m, uint64_t key) {
-    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    const uint32_t i = linear_block() * 256 + threadIdx.x;
     if (i < m) tab[i] = 0.5f + (float)(mix64(key + i) >> 41) * 0x1p-24f;
 }
 
@@ -44,7 +44,7 @@ __global__ __launch_bounds__(256) void gen_tab_kernel(float *tab, uint32_t m, ui
 
 hipError_t launch_gen_keys(uint32_t *keys, uint32_t n, uint64_t seed, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(gen_keys_kernel, dim3((n + 255) / 256), dim3(256), 0, s, keys, n,
+    hipLaunchKernelGGL(gen_keys_kernel, lane_grid(n, 256), dim3(256), 0, s, keys, n,
                        stream_key(seed, 1));
     return hipGetLastError();
 }
@@ -53,7 +53,7 @@ hipError_t launch_gen_keys_segments(uint32_t *keys, const uint32_t *offsets,
                                     const uint64_t *seeds, uint32_t nseg, uint32_t max_len,
                                     hipStream_t s) {
     if (nseg == 0 || max_len == 0) return hipSuccess;
-    const uint32_t bx = (max_len + 255) / 256;
+    const uint32_t bx = blocks_for(max_len, 256);
     hipLaunchKernelGGL(gen_keys_segments_kernel, dim3(bx < 64 ? bx : 64, nseg), dim3(256), 0, s,
                        keys, offsets, seeds, nseg);
     return hipGetLastError();
@@ -61,14 +61,14 @@ hipError_t launch_gen_keys_segments(uint32_t *keys, const uint32_t *offsets,
 
 hipError_t launch_gen_x(float *x, uint32_t n, uint64_t seed, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(gen_x_kernel, dim3((n + 255) / 256), dim3(256), 0, s, x, n,
+    hipLaunchKernelGGL(gen_x_kernel, lane_grid(n, 256), dim3(256), 0, s, x, n,
                        stream_key(seed, 2));
     return hipGetLastError();
 }
 
 hipError_t launch_gen_tab(float *tab, uint32_t m, uint64_t seed, hipStream_t s) {
     if (m == 0) return hipSuccess;
-    hipLaunchKernelGGL(gen_tab_kernel, dim3((m + 255) / 256), dim3(256), 0, s, tab, m,
+    hipLaunchKernelGGL(gen_tab_kernel, lane_grid(m, 256), dim3(256), 0, s, tab, m,
                        stream_key(seed, 3));
     return hipGetLastError();
 }

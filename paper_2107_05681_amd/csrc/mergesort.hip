@@ -185,13 +185,13 @@ __global__ __launch_bounds__(kMsThreads) void merge_pass_kernel(const uint32_t *
 
 }  // namespace
 
-uint32_t merge_pass_cut_words(uint32_t n) { return (n + kMsTile - 1) / kMsTile; }
+uint32_t merge_pass_cut_words(uint32_t n) { return blocks_for(n, kMsTile); }
 
 hipError_t launch_merge_pass(const uint32_t *src, uint32_t *dst, uint32_t n, uint32_t log_run,
                              bool melded, uint32_t *cuts, hipStream_t stream) {
     if (n == 0) return hipSuccess;
     if ((2u << log_run) < kMsTile) return hipErrorInvalidValue;
-    const uint32_t blocks = (n + kMsTile - 1) / kMsTile;
+    const uint32_t blocks = blocks_for(n, kMsTile);
     // A separate cut kernel pays off once the grid is several times what the
     // chip holds at once (each workgroup's own search then delays every
     // later wave of workgroups) and the runs are long (deep searches).

@@ -20,9 +20,10 @@ __global__ __launch_bounds__(256) void probe_region_kernel(uint32_t n, uint64_t 
                                                            uint64_t thr,
                                                            unsigned long long *out) {
     unsigned long long mixed = 0, ones = 0, waves = 0;
-    const uint32_t stride = gridDim.x * 256;
-    for (uint32_t base = blockIdx.x * 256 + (threadIdx.x & ~63u); base < n; base += stride) {
-        const uint32_t i = base + __lane_id();
+    // 64-bit walk: with n close to 2^32 a 32-bit base would wrap below n
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint64_t base = blockIdx.x * 256 + (threadIdx.x & ~63u); base < n; base += stride) {
+        const uint32_t i = (uint32_t)base + __lane_id();
         const bool valid = i < n;
         const bool taken = valid && (mix64(bkey + i) >> 32) < thr;
         const uint64_t mt = __ballot(taken);
@@ -166,7 +167,7 @@ __global__ __launch_bounds__(64) void probe_segments_kernel(const uint32_t *__re
 hipError_t launch_probe_region(uint32_t n, uint64_t seed, uint64_t thr, unsigned long long *out,
                                hipStream_t stream) {
     if (n == 0) return hipSuccess;
-    const uint32_t blocks = (n + 255) / 256;
+    const uint32_t blocks = blocks_for(n, 256);
     hipLaunchKernelGGL(probe_region_kernel, dim3(blocks < 2048 ? blocks : 2048), dim3(256), 0,
                        stream, n, stream_key(seed, 4), thr, out);
     return hipGetLastError();

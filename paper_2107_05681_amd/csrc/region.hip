@@ -45,7 +45,7 @@ __global__ __launch_bounds__(kRegionThreads) void region_divergent_kernel(
     const float *__restrict__ x, float *__restrict__ y, uint32_t n, const float *__restrict__ tab,
     uint32_t mask, uint64_t bkey, uint64_t thr, RegionSide T, RegionSide F) {
     const uint32_t i =
-        xcd_contiguous_block(blockIdx.x, gridDim.x) * kRegionThreads + threadIdx.x;
+        xcd_contiguous_block(linear_block(), linear_blocks()) * kRegionThreads + threadIdx.x;
     if (i >= n) return;
     const bool taken = branch_taken(bkey, i, thr);
     float acc = x[i];
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kRegionThreads) void region_melded_kernel(
     const float *__restrict__ x, float *__restrict__ y, uint32_t n, const float *__restrict__ tab,
     uint32_t mask, uint64_t bkey, uint64_t thr, RegionSide T, RegionSide F) {
     const uint32_t i =
-        xcd_contiguous_block(blockIdx.x, gridDim.x) * kRegionThreads + threadIdx.x;
+        xcd_contiguous_block(linear_block(), linear_blocks()) * kRegionThreads + threadIdx.x;
     if (i >= n) return;
     const bool taken = branch_taken(bkey, i, thr);
     const float a = taken ? T.a : F.a;  // differing operand of the aligned fma: a select
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(kRegionThreads) void region_melded_inplace_kernel(
     const float *__restrict__ x, float *__restrict__ y, uint32_t n, const float *__restrict__ tab,
     uint32_t mask, uint64_t bkey, uint64_t thr, RegionSide T, RegionSide F) {
     const uint32_t i =
-        xcd_contiguous_block(blockIdx.x, gridDim.x) * kRegionThreads + threadIdx.x;
+        xcd_contiguous_block(linear_block(), linear_blocks()) * kRegionThreads + threadIdx.x;
     if (i >= n) return;
     const bool taken = branch_taken(bkey, i, thr);
     const float a = taken ? T.a : F.a;
@@ -118,7 +118,7 @@ hipError_t launch_region(const float *x, float *y, uint32_t n, const float *tab,
                          hipStream_t stream) {
     if (n == 0) return hipSuccess;
     const uint64_t bkey = stream_key(seed, 4);
-    const dim3 grid((n + kRegionThreads - 1) / kRegionThreads);
+    const dim3 grid = lane_grid(n, kRegionThreads);
     if (form == RegionForm::kMelded)
         hipLaunchKernelGGL(region_melded_kernel, grid, dim3(kRegionThreads), 0, stream, x, y, n,
                            tab, mask, bkey, thr, T, F);

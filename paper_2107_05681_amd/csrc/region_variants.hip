@@ -32,7 +32,7 @@ namespace meld {
 namespace {
 
 __device__ __forceinline__ uint32_t lane_index() {
-    return xcd_contiguous_block(blockIdx.x, gridDim.x) * kRegionThreads + threadIdx.x;
+    return xcd_contiguous_block(linear_block(), linear_blocks()) * kRegionThreads + threadIdx.x;
 }
 
 __device__ __forceinline__ uint32_t way_of(uint64_t bkey, uint32_t i, uint64_t thr0,
@@ -233,7 +233,7 @@ hipError_t launch_region3(const float *x, float *y, uint32_t n, const float *tab
                           RegionSide W1, RegionSide W2, RegionForm form, hipStream_t stream) {
     if (n == 0) return hipSuccess;
     const uint64_t bkey = stream_key(seed, 4);
-    const dim3 grid((n + kRegionThreads - 1) / kRegionThreads);
+    const dim3 grid = lane_grid(n, kRegionThreads);
     auto kern = form == RegionForm::kMelded          ? region3_melded_kernel
                 : form == RegionForm::kMeldedInPlace ? region3_melded_inplace_kernel
                                                      : region3_divergent_kernel;
@@ -248,7 +248,7 @@ hipError_t launch_region_lanetrips(const float *x, float *y, uint32_t n, const f
     if (n == 0) return hipSuccess;
     const uint64_t bkey = stream_key(seed, 4);
     const uint64_t tkey = stream_key(seed, 11);
-    const dim3 grid((n + kRegionThreads - 1) / kRegionThreads);
+    const dim3 grid = lane_grid(n, kRegionThreads);
     auto kern = form == RegionForm::kMelded          ? region_lt_melded_kernel
                 : form == RegionForm::kMeldedInPlace ? region_lt_melded_inplace_kernel
                                                      : region_lt_divergent_kernel;
