@@ -147,7 +147,8 @@ meld_status meld_sort_plan_describe(meld_ctx *ctx, size_t n, int with_payload,
  * paper's bitonic benchmark (Evaluation section, "Bitonic Sort (BIT)": each
  * thread block sorts one bucket), batched over many uneven buckets.
  *
- * keys:    device u32[offsets[nseg]].
+ * keys:    device u32[n_keys]; the segments cover keys[0 .. offsets[nseg]).
+ * n_keys:  length of the keys array; every offset must be <= n_keys.
  * offsets: device u32[nseg + 1], offsets[0] = 0, non-decreasing. Segments
  *          may be empty. Segment length <= 65536.
  * nseg:    number of segments, < 2^31; 0 is a no-op.
@@ -158,12 +159,15 @@ meld_status meld_sort_plan_describe(meld_ctx *ctx, size_t n, int with_payload,
  * by the context.
  * Errors:  MELD_EINVAL for NULL/host pointers. Offsets live on the device
  *          and are not inspected on the host: a segment longer than 65536,
- *          decreasing offsets or offsets[0] != 0 leave the keys untouched
- *          and set the context's device error flag, read by
- *          meld_segmented_sort_check().
+ *          decreasing offsets, offsets[0] != 0 or an offset above n_keys
+ *          leave the keys untouched and set the context's device error flag,
+ *          read by meld_segmented_sort_check(). MELD_AUTO reads offsets[nseg]
+ *          to size its trials and returns MELD_EINVAL at once if it exceeds
+ *          n_keys.
  */
-meld_status meld_segmented_sort_u32(meld_ctx *ctx, uint32_t *keys, const uint32_t *offsets,
-                                    size_t nseg, meld_variant variant, void *stream);
+meld_status meld_segmented_sort_u32(meld_ctx *ctx, uint32_t *keys, size_t n_keys,
+                                    const uint32_t *offsets, size_t nseg, meld_variant variant,
+                                    void *stream);
 
 /* Sorts each bucket keys[b 2^log_bucket .. min(n, (b+1) 2^log_bucket))
  * ascending in place with Batcher's odd-even merge network (the network of
@@ -208,9 +212,10 @@ meld_status meld_merge_sort_u32(meld_ctx *ctx, uint32_t *keys, size_t n, int64_t
  * registers, whose direction is a lane bit for k <= 512 and uniform per wave
  * above. Used by the tuner and for per-stage measurements. MELD_AUTO counts
  * as MELD_MELDED here. */
-meld_status meld_segmented_sort_u32_staged(meld_ctx *ctx, uint32_t *keys, const uint32_t *offsets,
-                                           size_t nseg, meld_variant low_phases,
-                                           meld_variant high_phases, void *stream);
+meld_status meld_segmented_sort_u32_staged(meld_ctx *ctx, uint32_t *keys, size_t n_keys,
+                                           const uint32_t *offsets, size_t nseg,
+                                           meld_variant low_phases, meld_variant high_phases,
+                                           void *stream);
 
 /* Synchronises `stream` and reports whether any segmented sort on the context
  * since the last check found invalid offsets (MELD_EINVAL, with the reason)

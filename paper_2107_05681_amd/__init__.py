@@ -85,9 +85,9 @@ def load_library():
     lib.meld_sort_u32_steps.restype = st
     lib.meld_sort_u32_steps.argtypes = [vp, vp, vp, sz, i64, st, vp]
     lib.meld_segmented_sort_u32.restype = st
-    lib.meld_segmented_sort_u32.argtypes = [vp, vp, vp, sz, st, vp]
+    lib.meld_segmented_sort_u32.argtypes = [vp, vp, sz, vp, sz, st, vp]
     lib.meld_segmented_sort_u32_staged.restype = st
-    lib.meld_segmented_sort_u32_staged.argtypes = [vp, vp, vp, sz, st, st, vp]
+    lib.meld_segmented_sort_u32_staged.argtypes = [vp, vp, sz, vp, sz, st, st, vp]
     lib.meld_segmented_sort_check.restype = st
     lib.meld_segmented_sort_check.argtypes = [vp, vp]
     lib.meld_probe_region.restype = st
@@ -205,7 +205,7 @@ def segmented_sort(keys, offsets, variant=AUTO, stream=None, low=None, high=None
     if keys.numel() == 0 or nseg == 0:
         return keys
     lib = load_library()
-    args = (context(keys.device.index), ctypes.c_void_p(keys.data_ptr()),
+    args = (context(keys.device.index), ctypes.c_void_p(keys.data_ptr()), keys.numel(),
             ctypes.c_void_p(offsets.data_ptr()), nseg)
     if low is None and high is None:
         _check(lib.meld_segmented_sort_u32(*args, _variant(variant), _stream_of(keys, stream)))

@@ -128,7 +128,7 @@ constexpr uint32_t kSegWorkWords = 1u << 16;  // staging of a segment of up to 2
 constexpr uint32_t kSegMaxLen = 1u << 16;
 constexpr uint32_t kSegClasses = 17;  // size class ceil(log2(len)) in 0..16
 constexpr uint32_t kSegSmallClassMax = 7;  // up to 128 keys: one wave per segment
-constexpr uint32_t kSegBadFirst = 1, kSegDecreasing = 2, kSegTooLong = 4;
+constexpr uint32_t kSegBadFirst = 1, kSegDecreasing = 2, kSegTooLong = 4, kSegBeyondEnd = 8;
 
 // Device-side work-queue state of one segmented sort.
 struct SegState {
@@ -147,11 +147,13 @@ struct SegState {
 // Persistent grid size: CUs x resident 1024-lane workgroups (68 KiB of LDS).
 hipError_t seg_sort_grid(int device, uint32_t *grid);
 
-// Enqueues reset, classify, plan, scatter and the persistent sort. cls holds
-// nseg bytes, queue nseg words, work grid * kSegWorkWords words.
-hipError_t launch_segmented_sort(uint32_t *keys, const uint32_t *off, uint32_t nseg,
-                                 SegState *st, uint8_t *cls, uint32_t *queue, uint32_t *work,
-                                 uint32_t grid, bool meld_lo, bool meld_hi, hipStream_t stream);
+// Enqueues reset, classify, plan, scatter and the persistent sort. keys holds
+// n_keys words (an offset above n_keys flags the call invalid), cls nseg
+// bytes, queue nseg words, work grid * kSegWorkWords words.
+hipError_t launch_segmented_sort(uint32_t *keys, uint32_t n_keys, const uint32_t *off,
+                                 uint32_t nseg, SegState *st, uint8_t *cls, uint32_t *queue,
+                                 uint32_t *work, uint32_t grid, bool meld_lo, bool meld_hi,
+                                 hipStream_t stream);
 
 // Batcher's odd-even merge network on each bucket of 2^log_t keys
 // (oddeven.hip; log_t in 6..14, the last bucket ragged), at most max_steps

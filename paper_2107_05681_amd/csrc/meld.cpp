@@ -37,6 +37,7 @@ struct meld_ctx {
         const void *keys;
         const void *offsets;
         size_t nseg;
+        uint32_t n_keys;
         bool lo, hi;
         hipGraphExec_t exec;
     };
@@ -270,12 +271,12 @@ void drop_seg_graphs(meld_ctx *ctx) {
     ctx->seg_graphs.clear();
 }
 
-// The graph of (keys, offsets, nseg, forms), captured on first use.
-meld_status seg_graph(meld_ctx *ctx, uint32_t *keys, const uint32_t *offsets, size_t nseg,
-                      bool lo, bool hi, hipGraphExec_t *out) {
+// The graph of (keys, n_keys, offsets, nseg, forms), captured on first use.
+meld_status seg_graph(meld_ctx *ctx, uint32_t *keys, uint32_t n_keys, const uint32_t *offsets,
+                      size_t nseg, bool lo, bool hi, hipGraphExec_t *out) {
     for (auto it = ctx->seg_graphs.begin(); it != ctx->seg_graphs.end(); ++it) {
-        if (it->keys == keys && it->offsets == offsets && it->nseg == nseg && it->lo == lo &&
-            it->hi == hi) {
+        if (it->keys == keys && it->n_keys == n_keys && it->offsets == offsets &&
+            it->nseg == nseg && it->lo == lo && it->hi == hi) {
             ctx->seg_graphs.splice(ctx->seg_graphs.begin(), ctx->seg_graphs, it);
             *out = it->exec;
             return MELD_OK;
@@ -287,9 +288,10 @@ meld_status seg_graph(meld_ctx *ctx, uint32_t *keys, const uint32_t *offsets, si
     }
     hipError_t e = hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    hipError_t le = meld::launch_segmented_sort(keys, offsets, (uint32_t)nseg, ctx->seg_state,
-                                                ctx->seg_cls, ctx->seg_queue, ctx->seg_work,
-                                                ctx->seg_grid, lo, hi, ctx->capture_stream);
+    hipError_t le = meld::launch_segmented_sort(keys, n_keys, offsets, (uint32_t)nseg,
+                                                ctx->seg_state, ctx->seg_cls, ctx->seg_queue,
+                                                ctx->seg_work, ctx->seg_grid, lo, hi,
+                                                ctx->capture_stream);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(ctx->capture_stream, &graph);
     if (le != hipSuccess || e != hipSuccess) {
@@ -304,13 +306,19 @@ meld_status seg_graph(meld_ctx *ctx, uint32_t *keys, const uint32_t *offsets, si
         (void)hipGraphExecDestroy(ctx->seg_graphs.back().exec);
         ctx->seg_graphs.pop_back();
     }
-    ctx->seg_graphs.push_front({keys, offsets, nseg, lo, hi, exec});
+    ctx->seg_graphs.push_front({keys, offsets, nseg, n_keys, lo, hi, exec});
     *out = exec;
     return MELD_OK;
 }
 
-meld_status segmented_impl(meld_ctx *ctx, uint32_t *keys, const uint32_t *offsets, size_t nseg,
-                           bool meld_lo, bool meld_hi, hipStream_t stream, const char *fn) {
+// Offsets are u32, so any key count of 2^32 - 1 or more bounds every offset.
+uint32_t key_bound(size_t n_keys) {
+    return n_keys >= 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)n_keys;
+}
+
+meld_status segmented_impl(meld_ctx *ctx, uint32_t *keys, size_t n_keys, const uint32_t *offsets,
+                           size_t nseg, bool meld_lo, bool meld_hi, hipStream_t stream,
+                           const char *fn) {
     if (nseg == 0) return MELD_OK;
     if (nseg >= (1ull << 31)) return fail(MELD_EINVAL, "%s: nseg = %zu >= 2^31", fn, nseg);
     DeviceGuard g(ctx->device);
@@ -326,14 +334,14 @@ meld_status segmented_impl(meld_ctx *ctx, uint32_t *keys, const uint32_t *offset
     hipError_t e = hipStreamIsCapturing(stream, &cs);
     if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
     if (!ctx->use_graphs || cs != hipStreamCaptureStatusNone) {
-        e = meld::launch_segmented_sort(keys, offsets, (uint32_t)nseg, ctx->seg_state,
-                                        ctx->seg_cls, ctx->seg_queue, ctx->seg_work, ctx->seg_grid,
-                                        meld_lo, meld_hi, stream);
+        e = meld::launch_segmented_sort(keys, key_bound(n_keys), offsets, (uint32_t)nseg,
+                                        ctx->seg_state, ctx->seg_cls, ctx->seg_queue,
+                                        ctx->seg_work, ctx->seg_grid, meld_lo, meld_hi, stream);
         if (e != hipSuccess) return hip_fail(e, "segmented sort launch");
         return MELD_OK;
     }
     hipGraphExec_t exec = nullptr;
-    st = seg_graph(ctx, keys, offsets, nseg, meld_lo, meld_hi, &exec);
+    st = seg_graph(ctx, keys, key_bound(n_keys), offsets, nseg, meld_lo, meld_hi, &exec);
     if (st != MELD_OK) return st;
     e = hipGraphLaunch(exec, stream);
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
@@ -655,8 +663,8 @@ meld_status auto_sort_plan(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, siz
 
 // MELD_AUTO for a segmented sort: the tuned forms of this shape class, timing
 // the four per-stage combinations on a scratch copy the first time.
-meld_status auto_seg_forms(meld_ctx *ctx, uint32_t *keys, const uint32_t *offsets, size_t nseg,
-                           hipStream_t s, bool *lo, bool *hi) {
+meld_status auto_seg_forms(meld_ctx *ctx, uint32_t *keys, size_t n_keys, const uint32_t *offsets,
+                           size_t nseg, hipStream_t s, bool *lo, bool *hi) {
     *lo = *hi = true;
     if (capturing(s)) {
         return MELD_OK;
@@ -665,6 +673,10 @@ meld_status auto_seg_forms(meld_ctx *ctx, uint32_t *keys, const uint32_t *offset
     hipError_t e = hipMemcpyAsync(&total, offsets + nseg, sizeof total, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "reading offsets[nseg]");
+    // the trials copy keys[0 .. offsets[nseg]): never past the caller's array
+    if (total > n_keys)
+        return fail(MELD_EINVAL, "meld_segmented_sort_u32: offsets[nseg] = %u > n_keys = %zu",
+                    total, n_keys);
     const std::string key = fmt("nseg=%u total=%u", log2_ceil(nseg), log2_ceil(total));
     if (const meld::TuneEntry *t = ctx->tuner.find("segsort", key)) {
         *lo = t->lo != 0;
@@ -690,7 +702,7 @@ meld_status auto_seg_forms(meld_ctx *ctx, uint32_t *keys, const uint32_t *offset
             },
             [&]() -> meld_status {
                 hipError_t r = meld::launch_segmented_sort(
-                    ctx->tune_buf, offsets, (uint32_t)nseg, ctx->seg_state, ctx->seg_cls,
+                    ctx->tune_buf, total, offsets, (uint32_t)nseg, ctx->seg_state, ctx->seg_cls,
                     ctx->seg_queue, ctx->seg_work, ctx->seg_grid, l, h, s);
                 return r == hipSuccess ? MELD_OK : hip_fail(r, "segmented sort launch");
             },
@@ -1222,8 +1234,9 @@ meld_status meld_region_lanetrips_f32(meld_ctx *ctx, const float *x, float *y, s
     return MELD_OK;
 }
 
-meld_status meld_segmented_sort_u32(meld_ctx *ctx, uint32_t *keys, const uint32_t *offsets,
-                                    size_t nseg, meld_variant variant, void *stream) {
+meld_status meld_segmented_sort_u32(meld_ctx *ctx, uint32_t *keys, size_t n_keys,
+                                    const uint32_t *offsets, size_t nseg, meld_variant variant,
+                                    void *stream) {
     if (ctx == nullptr) return fail(MELD_EINVAL, "meld_segmented_sort_u32: ctx is NULL");
     if ((unsigned)variant > MELD_MELDED_INPLACE)
         return fail(MELD_EINVAL, "meld_segmented_sort_u32: bad variant");
@@ -1236,19 +1249,20 @@ meld_status meld_segmented_sort_u32(meld_ctx *ctx, uint32_t *keys, const uint32_
                         "meld_segmented_sort_u32: keys and offsets must be device pointers on "
                         "device %d",
                         ctx->device);
-        meld_status st = auto_seg_forms(ctx, keys, offsets, nseg, s, &lo, &hi);
+        meld_status st = auto_seg_forms(ctx, keys, n_keys, offsets, nseg, s, &lo, &hi);
         if (st != MELD_OK) return st;
     }
-    return segmented_impl(ctx, keys, offsets, nseg, lo, hi, s, "meld_segmented_sort_u32");
+    return segmented_impl(ctx, keys, n_keys, offsets, nseg, lo, hi, s, "meld_segmented_sort_u32");
 }
 
-meld_status meld_segmented_sort_u32_staged(meld_ctx *ctx, uint32_t *keys, const uint32_t *offsets,
-                                           size_t nseg, meld_variant low_phases,
-                                           meld_variant high_phases, void *stream) {
+meld_status meld_segmented_sort_u32_staged(meld_ctx *ctx, uint32_t *keys, size_t n_keys,
+                                           const uint32_t *offsets, size_t nseg,
+                                           meld_variant low_phases, meld_variant high_phases,
+                                           void *stream) {
     if (ctx == nullptr) return fail(MELD_EINVAL, "meld_segmented_sort_u32_staged: ctx is NULL");
     if ((unsigned)low_phases > MELD_MELDED_INPLACE || (unsigned)high_phases > MELD_MELDED_INPLACE)
         return fail(MELD_EINVAL, "meld_segmented_sort_u32_staged: bad variant");
-    return segmented_impl(ctx, keys, offsets, nseg, use_melded(low_phases),
+    return segmented_impl(ctx, keys, n_keys, offsets, nseg, use_melded(low_phases),
                           use_melded(high_phases), static_cast<hipStream_t>(stream),
                           "meld_segmented_sort_u32_staged");
 }
@@ -1357,10 +1371,11 @@ meld_status meld_segmented_sort_check(meld_ctx *ctx, void *stream) {
     e = hipMemcpy(&ctx->seg_state->sticky, &zero, sizeof zero, hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "clearing the segmented sort flag");
     if (sticky == 0) return MELD_OK;
-    return fail(MELD_EINVAL, "segmented sort: invalid offsets (%s%s%s); keys left untouched",
+    return fail(MELD_EINVAL, "segmented sort: invalid offsets (%s%s%s%s); keys left untouched",
                 (sticky & meld::kSegBadFirst) ? "offsets[0] != 0 " : "",
                 (sticky & meld::kSegDecreasing) ? "decreasing offsets " : "",
-                (sticky & meld::kSegTooLong) ? "segment longer than 65536" : "");
+                (sticky & meld::kSegTooLong) ? "segment longer than 65536 " : "",
+                (sticky & meld::kSegBeyondEnd) ? "offset beyond n_keys" : "");
 }
 
 }  // extern "C"

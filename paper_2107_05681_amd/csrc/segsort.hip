@@ -150,7 +150,8 @@ __global__ void seg_reset_kernel(SegState *st) {
 }
 
 __global__ __launch_bounds__(256) void seg_classify_kernel(const uint32_t *__restrict__ off,
-                                                           uint32_t nseg, SegState *st,
+                                                           uint32_t nseg, uint32_t n_keys,
+                                                           SegState *st,
                                                            uint8_t *__restrict__ cls) {
     __shared__ uint32_t lcnt[kSegClasses];
     if (threadIdx.x < kSegClasses) lcnt[threadIdx.x] = 0;
@@ -161,6 +162,7 @@ __global__ __launch_bounds__(256) void seg_classify_kernel(const uint32_t *__res
         const uint32_t hi = off[s + 1];
         uint32_t f = 0;
         if (s == 0 && lo != 0) f |= kSegBadFirst;
+        if (hi > n_keys) f |= kSegBeyondEnd;
         if (hi < lo)
             f |= kSegDecreasing;
         else if (hi - lo > kSegMaxLen)
@@ -512,14 +514,15 @@ hipError_t seg_sort_grid(int device, uint32_t *grid) {
     return hipSuccess;
 }
 
-hipError_t launch_segmented_sort(uint32_t *keys, const uint32_t *off, uint32_t nseg,
-                                 SegState *st, uint8_t *cls, uint32_t *queue, uint32_t *work,
-                                 uint32_t grid, bool meld_lo, bool meld_hi, hipStream_t stream) {
+hipError_t launch_segmented_sort(uint32_t *keys, uint32_t n_keys, const uint32_t *off,
+                                 uint32_t nseg, SegState *st, uint8_t *cls, uint32_t *queue,
+                                 uint32_t *work, uint32_t grid, bool meld_lo, bool meld_hi,
+                                 hipStream_t stream) {
     if (nseg == 0) return hipSuccess;
     const uint32_t blocks = (nseg + 255) / 256;
     hipLaunchKernelGGL(seg_reset_kernel, dim3(1), dim3(64), 0, stream, st);
-    hipLaunchKernelGGL(seg_classify_kernel, dim3(blocks), dim3(256), 0, stream, off, nseg, st,
-                       cls);
+    hipLaunchKernelGGL(seg_classify_kernel, dim3(blocks), dim3(256), 0, stream, off, nseg, n_keys,
+                       st, cls);
     hipLaunchKernelGGL(seg_plan_kernel, dim3(1), dim3(64), 0, stream, st);
     hipLaunchKernelGGL(seg_scatter_kernel, dim3(blocks), dim3(256), 0, stream, nseg, cls, st,
                        queue);

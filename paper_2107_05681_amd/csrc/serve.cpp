@@ -241,7 +241,7 @@ class HipExecutor : public Executor {
                 e = meld::launch_gen_keys_segments(keys, s.off_dev, s.seed_dev, nseg, max_len,
                                                    s.stream);
             if (e != hipSuccess) return serve_fail(MELD_EHIP, "batch inputs: %s", hipGetErrorString(e));
-            st = meld_segmented_sort_u32(s.lib, keys, s.off_dev, nseg, variant_, s.stream);
+            st = meld_segmented_sort_u32(s.lib, keys, acc, s.off_dev, nseg, variant_, s.stream);
         } else {
             JobRec *j = jobs[0];
             if (j->job.kind == MELD_JOB_SORT) {

@@ -48,7 +48,7 @@ def test_null_context_is_rejected_without_gpu_work():
     s = meld.side(1, 0, 1, 1)
     assert lib.meld_divergent_region_f32(None, None, None, 10, None, 16, 0, 0, s, s, 1,
                                          None) == meld.EINVAL
-    assert lib.meld_segmented_sort_u32(None, None, None, 3, 1, None) == meld.EINVAL
+    assert lib.meld_segmented_sort_u32(None, None, 0, None, 3, 1, None) == meld.EINVAL
     assert lib.meld_sort_u32_steps(None, None, None, 8, 3, 1, None) == meld.EINVAL
     assert lib.meld_create(0, None) == meld.EINVAL
     lib.meld_destroy(None)

@@ -130,6 +130,28 @@ def test_segmented_invalid_offsets_leave_keys_untouched(bad):
     assert np.array_equal(_run(k2, good, "melded", "melded"), oracle.segmented_sort_u32(k2, good))
 
 
+def test_segmented_offsets_beyond_keys_rejected():
+    # offsets[nseg] = 300 for a keys array of 200: the explicit forms flag it on
+    # the device and touch no key; MELD_AUTO, which reads offsets[nseg] to size
+    # its trials, rejects the call at once.
+    keys = workloads.keys_u32(2, 200)
+    off = _to_dev(np.array([0, 100, 300], np.uint32))
+    for v in ("divergent", "melded"):
+        kd = _to_dev(keys)
+        meld.segmented_sort(kd, off, variant=v)
+        with pytest.raises(meld.MeldError) as e:
+            meld.segmented_sort_check(0)
+        assert e.value.status == meld.EINVAL and "beyond n_keys" in str(e.value), v
+        assert np.array_equal(_to_host(kd), keys), v
+    kd = _to_dev(keys)
+    with pytest.raises(meld.MeldError) as e:
+        meld.segmented_sort(kd, off, variant="auto")
+    assert e.value.status == meld.EINVAL
+    torch.cuda.synchronize()
+    assert np.array_equal(_to_host(kd), keys)
+    meld.segmented_sort_check(0)  # nothing flagged by the rejected call
+
+
 def test_segmented_no_segments_is_noop():
     kd = _to_dev(np.array([3, 2, 1], np.uint32))
     meld.segmented_sort(kd, _to_dev(np.array([0], np.uint32)))
