@@ -40,13 +40,20 @@ namespace {
 
 constexpr uint32_t kOePad = 0xFFFFFFFFu;
 
-// Role of element e at step (p, k): +1 lower, -1 upper, 0 idle.
-__device__ __forceinline__ int oe_role(uint32_t e, uint32_t p, uint32_t k) {
+// Partner offset of element e at step (p, k): +k at the lower end of a
+// comparator, -k at the upper end, 0 when idle; and whether a lower end keeps
+// the minimum (the side, meaningful when the offset is not 0). Branch-free.
+struct OeRole {
+    int32_t d;
+    bool lower;
+};
+__device__ __forceinline__ OeRole oe_role(uint32_t e, uint32_t p, uint32_t k) {
     const bool bit = (e & k) != 0;
-    if (k == p) return bit ? -1 : 1;
     const uint32_t pos = e & (2 * p - 1);
-    if (bit) return pos + k < 2 * p ? 1 : 0;
-    return pos >= k ? -1 : 0;
+    const bool lower = k == p ? !bit : bit;
+    const bool active = k == p || (bit ? pos + k < 2 * p : pos >= k);
+    const int32_t kk = (int32_t)k;
+    return {active ? (lower ? kk : -kk) : 0, lower};
 }
 
 // Steps with k >= NT (so 2p > NT): element r of the lane (t + r NT) has its
@@ -153,29 +160,28 @@ __device__ __forceinline__ void oe_lds_step(uint32_t (&v)[E], OeState &st, uint3
         // of element t, so the role, and the partner offset, are computed once
         // per step (the divergent form branches once per step, each side with
         // its own loads).
-        const int role = oe_role(t, p, k);
+        const OeRole role = oe_role(t, p, k);
         if constexpr (MELDED) {
             // idle: partner = the element itself, whose min and max are the key
-            const int32_t d = role > 0 ? (int32_t)k : (role < 0 ? -(int32_t)k : 0);
-            const uint32_t *pp = sc + ((int32_t)t + d);
+            const uint32_t *pp = sc + ((int32_t)t + role.d);
 #pragma unroll
             for (int r = 0; r < E; ++r) {
                 const uint32_t b = pp[(uint32_t)r * NT];
                 const uint32_t mn = v[r] < b ? v[r] : b;
                 const uint32_t mx = v[r] < b ? b : v[r];
-                nv[r] = role > 0 ? mn : mx;
+                nv[r] = role.lower ? mn : mx;
             }
         } else {
 #pragma unroll
             for (int r = 0; r < E; ++r) nv[r] = v[r];
-            if (role > 0) {
+            if (role.d > 0) {
                 MELD_SIDE_MARK("lower");
 #pragma unroll
                 for (int r = 0; r < E; ++r) {
                     const uint32_t b = sc[t + (uint32_t)r * NT + k];
                     if (b < v[r]) nv[r] = b;
                 }
-            } else if (role < 0) {
+            } else if (role.d < 0) {
                 MELD_SIDE_MARK("upper");
 #pragma unroll
                 for (int r = 0; r < E; ++r) {
