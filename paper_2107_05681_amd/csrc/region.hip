@@ -42,10 +42,11 @@ namespace {
 
 
 __global__ __launch_bounds__(kRegionThreads) void region_divergent_kernel(
-    const float *__restrict__ x, float *__restrict__ y, uint32_t n, const float *__restrict__ tab,
+    const float *__restrict__ x, float *__restrict__ y, uint32_t n, uint32_t lane0,
+    const float *__restrict__ tab,
     uint32_t mask, uint64_t bkey, uint64_t thr, RegionSide T, RegionSide F) {
     const uint32_t i =
-        xcd_contiguous_block(linear_block(), linear_blocks()) * kRegionThreads + threadIdx.x;
+        lane0 + xcd_contiguous_block(blockIdx.x, gridDim.x) * kRegionThreads + threadIdx.x;
     if (i >= n) return;
     const bool taken = branch_taken(bkey, i, thr);
     float acc = x[i];
@@ -76,10 +77,11 @@ __device__ __forceinline__ float longer_side_steps(float acc, uint32_t i, bool t
 
 // The melded form used by the library.
 __global__ __launch_bounds__(kRegionThreads) void region_melded_kernel(
-    const float *__restrict__ x, float *__restrict__ y, uint32_t n, const float *__restrict__ tab,
+    const float *__restrict__ x, float *__restrict__ y, uint32_t n, uint32_t lane0,
+    const float *__restrict__ tab,
     uint32_t mask, uint64_t bkey, uint64_t thr, RegionSide T, RegionSide F) {
     const uint32_t i =
-        xcd_contiguous_block(linear_block(), linear_blocks()) * kRegionThreads + threadIdx.x;
+        lane0 + xcd_contiguous_block(blockIdx.x, gridDim.x) * kRegionThreads + threadIdx.x;
     if (i >= n) return;
     const bool taken = branch_taken(bkey, i, thr);
     const float a = taken ? T.a : F.a;  // differing operand of the aligned fma: a select
@@ -97,10 +99,11 @@ __global__ __launch_bounds__(kRegionThreads) void region_melded_kernel(
 // vector-memory work of one lane-linear stream, which makes this form slower
 // than the divergent one whenever the sides read different data.
 __global__ __launch_bounds__(kRegionThreads) void region_melded_inplace_kernel(
-    const float *__restrict__ x, float *__restrict__ y, uint32_t n, const float *__restrict__ tab,
+    const float *__restrict__ x, float *__restrict__ y, uint32_t n, uint32_t lane0,
+    const float *__restrict__ tab,
     uint32_t mask, uint64_t bkey, uint64_t thr, RegionSide T, RegionSide F) {
     const uint32_t i =
-        xcd_contiguous_block(linear_block(), linear_blocks()) * kRegionThreads + threadIdx.x;
+        lane0 + xcd_contiguous_block(blockIdx.x, gridDim.x) * kRegionThreads + threadIdx.x;
     if (i >= n) return;
     const bool taken = branch_taken(bkey, i, thr);
     const float a = taken ? T.a : F.a;
@@ -116,18 +119,15 @@ __global__ __launch_bounds__(kRegionThreads) void region_melded_inplace_kernel(
 hipError_t launch_region(const float *x, float *y, uint32_t n, const float *tab, uint32_t mask,
                          uint64_t seed, uint64_t thr, RegionSide T, RegionSide F, RegionForm form,
                          hipStream_t stream) {
-    if (n == 0) return hipSuccess;
     const uint64_t bkey = stream_key(seed, 4);
-    const dim3 grid = lane_grid(n, kRegionThreads);
-    if (form == RegionForm::kMelded)
-        hipLaunchKernelGGL(region_melded_kernel, grid, dim3(kRegionThreads), 0, stream, x, y, n,
-                           tab, mask, bkey, thr, T, F);
-    else if (form == RegionForm::kMeldedInPlace)
-        hipLaunchKernelGGL(region_melded_inplace_kernel, grid, dim3(kRegionThreads), 0, stream, x,
-                           y, n, tab, mask, bkey, thr, T, F);
-    else
-        hipLaunchKernelGGL(region_divergent_kernel, grid, dim3(kRegionThreads), 0, stream, x, y,
-                           n, tab, mask, bkey, thr, T, F);
+    auto kern = form == RegionForm::kMelded          ? region_melded_kernel
+                : form == RegionForm::kMeldedInPlace ? region_melded_inplace_kernel
+                                                     : region_divergent_kernel;
+    for (uint64_t i0 = 0; i0 < n; i0 += kRegionLaunchLanes) {
+        const uint32_t len = (uint32_t)(n - i0 < kRegionLaunchLanes ? n - i0 : kRegionLaunchLanes);
+        hipLaunchKernelGGL(kern, dim3(blocks_for(len, kRegionThreads)), dim3(kRegionThreads), 0,
+                           stream, x, y, n, (uint32_t)i0, tab, mask, bkey, thr, T, F);
+    }
     return hipGetLastError();
 }
 

@@ -13,6 +13,9 @@ namespace meld {
 namespace {
 
 constexpr int kRegionThreads = 256;
+// Lanes per launch: HIP caps a grid dimension at 2^32 - 1 work-items, so a
+// call on more lanes runs as several launches, each told its first lane.
+constexpr uint64_t kRegionLaunchLanes = 1ull << 31;
 
 // Branch of lane i: the upper 32 bits of stream (seed, 4) at i against thr.
 __device__ __forceinline__ bool branch_taken(uint64_t bkey, uint32_t i, uint64_t thr) {

@@ -31,8 +31,8 @@ namespace meld {
 
 namespace {
 
-__device__ __forceinline__ uint32_t lane_index() {
-    return xcd_contiguous_block(linear_block(), linear_blocks()) * kRegionThreads + threadIdx.x;
+__device__ __forceinline__ uint32_t lane_index(uint32_t lane0) {
+    return lane0 + xcd_contiguous_block(blockIdx.x, gridDim.x) * kRegionThreads + threadIdx.x;
 }
 
 __device__ __forceinline__ uint32_t way_of(uint64_t bkey, uint32_t i, uint64_t thr0,
@@ -47,10 +47,11 @@ __device__ __forceinline__ const RegionSide &pick_way(uint32_t w, const RegionSi
 }
 
 __global__ __launch_bounds__(kRegionThreads) void region3_divergent_kernel(
-    const float *__restrict__ x, float *__restrict__ y, uint32_t n, const float *__restrict__ tab,
+    const float *__restrict__ x, float *__restrict__ y, uint32_t n, uint32_t lane0,
+    const float *__restrict__ tab,
     uint32_t mask, uint64_t bkey, uint64_t thr0, uint64_t thr1, RegionSide W0, RegionSide W1,
     RegionSide W2) {
-    const uint32_t i = lane_index();
+    const uint32_t i = lane_index(lane0);
     if (i >= n) return;
     const uint64_t h = mix64(bkey + i) >> 32;
     float acc = x[i];
@@ -128,10 +129,11 @@ __device__ __forceinline__ float melded3_steps(float acc, uint32_t way, uint32_t
 }
 
 __global__ __launch_bounds__(kRegionThreads) void region3_melded_kernel(
-    const float *__restrict__ x, float *__restrict__ y, uint32_t n, const float *__restrict__ tab,
+    const float *__restrict__ x, float *__restrict__ y, uint32_t n, uint32_t lane0,
+    const float *__restrict__ tab,
     uint32_t mask, uint64_t bkey, uint64_t thr0, uint64_t thr1, RegionSide W0, RegionSide W1,
     RegionSide W2) {
-    const uint32_t i = lane_index();
+    const uint32_t i = lane_index(lane0);
     if (i >= n) return;
     const uint32_t way = way_of(bkey, i, thr0, thr1);
     const RegionSide &Me = pick_way(way, W0, W1, W2);
@@ -154,10 +156,11 @@ __global__ __launch_bounds__(kRegionThreads) void region3_melded_kernel(
 }
 
 __global__ __launch_bounds__(kRegionThreads) void region3_melded_inplace_kernel(
-    const float *__restrict__ x, float *__restrict__ y, uint32_t n, const float *__restrict__ tab,
+    const float *__restrict__ x, float *__restrict__ y, uint32_t n, uint32_t lane0,
+    const float *__restrict__ tab,
     uint32_t mask, uint64_t bkey, uint64_t thr0, uint64_t thr1, RegionSide W0, RegionSide W1,
     RegionSide W2) {
-    const uint32_t i = lane_index();
+    const uint32_t i = lane_index(lane0);
     if (i >= n) return;
     const uint32_t way = way_of(bkey, i, thr0, thr1);
     const RegionSide &Me = pick_way(way, W0, W1, W2);
@@ -183,10 +186,11 @@ __device__ __forceinline__ uint32_t lane_trips(uint64_t tkey, uint32_t i, uint32
 }
 
 __global__ __launch_bounds__(kRegionThreads) void region_lt_divergent_kernel(
-    const float *__restrict__ x, float *__restrict__ y, uint32_t n, const float *__restrict__ tab,
+    const float *__restrict__ x, float *__restrict__ y, uint32_t n, uint32_t lane0,
+    const float *__restrict__ tab,
     uint32_t mask, uint64_t bkey, uint64_t tkey, uint64_t thr, RegionSideRange T,
     RegionSideRange F) {
-    const uint32_t i = lane_index();
+    const uint32_t i = lane_index(lane0);
     if (i >= n) return;
     const bool taken = branch_taken(bkey, i, thr);
     float acc = x[i];
@@ -203,10 +207,11 @@ __global__ __launch_bounds__(kRegionThreads) void region_lt_divergent_kernel(
 }
 
 __global__ __launch_bounds__(kRegionThreads) void region_lt_melded_kernel(
-    const float *__restrict__ x, float *__restrict__ y, uint32_t n, const float *__restrict__ tab,
+    const float *__restrict__ x, float *__restrict__ y, uint32_t n, uint32_t lane0,
+    const float *__restrict__ tab,
     uint32_t mask, uint64_t bkey, uint64_t tkey, uint64_t thr, RegionSideRange T,
     RegionSideRange F) {
-    const uint32_t i = lane_index();
+    const uint32_t i = lane_index(lane0);
     if (i >= n) return;
     const bool taken = branch_taken(bkey, i, thr);
     const float a = taken ? T.a : F.a;
@@ -215,10 +220,11 @@ __global__ __launch_bounds__(kRegionThreads) void region_lt_melded_kernel(
 }
 
 __global__ __launch_bounds__(kRegionThreads) void region_lt_melded_inplace_kernel(
-    const float *__restrict__ x, float *__restrict__ y, uint32_t n, const float *__restrict__ tab,
+    const float *__restrict__ x, float *__restrict__ y, uint32_t n, uint32_t lane0,
+    const float *__restrict__ tab,
     uint32_t mask, uint64_t bkey, uint64_t tkey, uint64_t thr, RegionSideRange T,
     RegionSideRange F) {
-    const uint32_t i = lane_index();
+    const uint32_t i = lane_index(lane0);
     if (i >= n) return;
     const bool taken = branch_taken(bkey, i, thr);
     const RegionSideRange &S = taken ? T : F;
@@ -231,29 +237,31 @@ __global__ __launch_bounds__(kRegionThreads) void region_lt_melded_inplace_kerne
 hipError_t launch_region3(const float *x, float *y, uint32_t n, const float *tab, uint32_t mask,
                           uint64_t seed, uint64_t thr0, uint64_t thr1, RegionSide W0,
                           RegionSide W1, RegionSide W2, RegionForm form, hipStream_t stream) {
-    if (n == 0) return hipSuccess;
     const uint64_t bkey = stream_key(seed, 4);
-    const dim3 grid = lane_grid(n, kRegionThreads);
     auto kern = form == RegionForm::kMelded          ? region3_melded_kernel
                 : form == RegionForm::kMeldedInPlace ? region3_melded_inplace_kernel
                                                      : region3_divergent_kernel;
-    hipLaunchKernelGGL(kern, grid, dim3(kRegionThreads), 0, stream, x, y, n, tab, mask, bkey, thr0,
-                       thr1, W0, W1, W2);
+    for (uint64_t i0 = 0; i0 < n; i0 += kRegionLaunchLanes) {
+        const uint32_t len = (uint32_t)(n - i0 < kRegionLaunchLanes ? n - i0 : kRegionLaunchLanes);
+        hipLaunchKernelGGL(kern, dim3(blocks_for(len, kRegionThreads)), dim3(kRegionThreads), 0,
+                           stream, x, y, n, (uint32_t)i0, tab, mask, bkey, thr0, thr1, W0, W1, W2);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_region_lanetrips(const float *x, float *y, uint32_t n, const float *tab,
                                    uint32_t mask, uint64_t seed, uint64_t thr, RegionSideRange T,
                                    RegionSideRange F, RegionForm form, hipStream_t stream) {
-    if (n == 0) return hipSuccess;
     const uint64_t bkey = stream_key(seed, 4);
     const uint64_t tkey = stream_key(seed, 11);
-    const dim3 grid = lane_grid(n, kRegionThreads);
     auto kern = form == RegionForm::kMelded          ? region_lt_melded_kernel
                 : form == RegionForm::kMeldedInPlace ? region_lt_melded_inplace_kernel
                                                      : region_lt_divergent_kernel;
-    hipLaunchKernelGGL(kern, grid, dim3(kRegionThreads), 0, stream, x, y, n, tab, mask, bkey, tkey,
-                       thr, T, F);
+    for (uint64_t i0 = 0; i0 < n; i0 += kRegionLaunchLanes) {
+        const uint32_t len = (uint32_t)(n - i0 < kRegionLaunchLanes ? n - i0 : kRegionLaunchLanes);
+        hipLaunchKernelGGL(kern, dim3(blocks_for(len, kRegionThreads)), dim3(kRegionThreads), 0,
+                           stream, x, y, n, (uint32_t)i0, tab, mask, bkey, tkey, thr, T, F);
+    }
     return hipGetLastError();
 }
 
