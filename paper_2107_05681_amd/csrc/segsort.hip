@@ -225,6 +225,75 @@ __global__ __launch_bounds__(256) void seg_scatter_kernel(uint32_t nseg,
     if (c != 0) queue[st->base[c] + lbase[c] + rank] = s;
 }
 
+// The 16 registers of window W at their padded LDS positions p[padded(r << W)]
+// (p: the lane's part of the index, already padded). With W fixed at compile
+// time every position is an immediate offset of the LDS instruction; a window
+// base known only at run time would cost three scalar instructions and a
+// vector add per register.
+template <int W>
+__device__ __forceinline__ void window_store_w(const uint32_t (&e)[kSegE], uint32_t *p) {
+#pragma unroll
+    for (int r = 0; r < kSegE; ++r) p[((uint32_t)r << W) + (((uint32_t)r << W) >> 4)] = e[r];
+}
+template <int W>
+__device__ __forceinline__ void window_load_w(uint32_t (&e)[kSegE], const uint32_t *p) {
+#pragma unroll
+    for (int r = 0; r < kSegE; ++r) e[r] = p[((uint32_t)r << W) + (((uint32_t)r << W) >> 4)];
+}
+
+// Window bases are 0 .. 10 (element bits [W, W + 4) of a tile of at most 2^14
+// keys). Each case ends in its own mark so that the compiler keeps the cases
+// apart instead of merging them back into one block with computed offsets.
+#define SEG_WINDOW_CASE(W, CALL, TAG) \
+    case W:                           \
+        CALL;                         \
+        asm volatile("; window " TAG " " #W ::: "memory"); \
+        break;
+
+__device__ __forceinline__ void window_store(const uint32_t (&e)[kSegE], uint32_t *p, uint32_t W) {
+    switch (W) {
+        SEG_WINDOW_CASE(0, window_store_w<0>(e, p), "store")
+        SEG_WINDOW_CASE(1, window_store_w<1>(e, p), "store")
+        SEG_WINDOW_CASE(2, window_store_w<2>(e, p), "store")
+        SEG_WINDOW_CASE(3, window_store_w<3>(e, p), "store")
+        SEG_WINDOW_CASE(4, window_store_w<4>(e, p), "store")
+        SEG_WINDOW_CASE(5, window_store_w<5>(e, p), "store")
+        SEG_WINDOW_CASE(6, window_store_w<6>(e, p), "store")
+        SEG_WINDOW_CASE(7, window_store_w<7>(e, p), "store")
+        SEG_WINDOW_CASE(8, window_store_w<8>(e, p), "store")
+        SEG_WINDOW_CASE(9, window_store_w<9>(e, p), "store")
+        default: window_store_w<10>(e, p); break;
+    }
+}
+
+__device__ __forceinline__ void window_load(uint32_t (&e)[kSegE], const uint32_t *p, uint32_t W) {
+    switch (W) {
+        SEG_WINDOW_CASE(0, window_load_w<0>(e, p), "load")
+        SEG_WINDOW_CASE(1, window_load_w<1>(e, p), "load")
+        SEG_WINDOW_CASE(2, window_load_w<2>(e, p), "load")
+        SEG_WINDOW_CASE(3, window_load_w<3>(e, p), "load")
+        SEG_WINDOW_CASE(4, window_load_w<4>(e, p), "load")
+        SEG_WINDOW_CASE(5, window_load_w<5>(e, p), "load")
+        SEG_WINDOW_CASE(6, window_load_w<6>(e, p), "load")
+        SEG_WINDOW_CASE(7, window_load_w<7>(e, p), "load")
+        SEG_WINDOW_CASE(8, window_load_w<8>(e, p), "load")
+        SEG_WINDOW_CASE(9, window_load_w<9>(e, p), "load")
+        default: window_load_w<10>(e, p); break;
+    }
+}
+#undef SEG_WINDOW_CASE
+
+// Moves e from window cur to window B through the padded LDS tile.
+__device__ __forceinline__ void to_window(uint32_t (&e)[kSegE], uint32_t *s, uint32_t t,
+                                          uint32_t &cur, uint32_t B) {
+    if (B == cur) return;
+    window_store(e, s + padded(window_tpart(t, cur)), cur);
+    __syncthreads();
+    window_load(e, s + padded(window_tpart(t, B)), B);
+    __syncthreads();
+    cur = B;
+}
+
 // Steps of phase k = 2^p on element bits hi_bit .. 0 of a tile held in
 // registers, 16 per lane (lane t of the tile's nt lanes): windows with bases
 // hi_bit-3, hi_bit-7, ... (clamped at 0). cur is the window e is in.
@@ -235,33 +304,10 @@ __device__ __forceinline__ void phase_windows(uint32_t (&e)[kSegE], uint32_t *s,
 #pragma unroll 1
     for (int top = hi_bit; top >= 0;) {
         const uint32_t B = top >= 3 ? (uint32_t)(top - 3) : 0u;
-        if (B != cur) {
-            const uint32_t tp = padded(window_tpart(t, cur)), tb = padded(window_tpart(t, B));
-#pragma unroll
-            for (int r = 0; r < kSegE; ++r) s[tp + padded((uint32_t)r << cur)] = e[r];
-            __syncthreads();
-#pragma unroll
-            for (int r = 0; r < kSegE; ++r) e[r] = s[tb + padded((uint32_t)r << B)];
-            __syncthreads();
-        }
+        to_window(e, s, t, cur, B);
         seg_reg_steps<MELDED>(e, top - (int)B, up, unlimited);
-        cur = B;
         top = (int)B - 1;
     }
-}
-
-// Moves e from window cur to window B through the padded LDS tile.
-__device__ __forceinline__ void to_window(uint32_t (&e)[kSegE], uint32_t *s, uint32_t t,
-                                          uint32_t &cur, uint32_t B) {
-    if (B == cur) return;
-    const uint32_t tp = padded(window_tpart(t, cur)), tb = padded(window_tpart(t, B));
-#pragma unroll
-    for (int r = 0; r < kSegE; ++r) s[tp + padded((uint32_t)r << cur)] = e[r];
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < kSegE; ++r) e[r] = s[tb + padded((uint32_t)r << B)];
-    __syncthreads();
-    cur = B;
 }
 
 // A team of 2^(m-4) lanes (lane t) sorts the 2^m positions cbase + i of a
