@@ -58,7 +58,7 @@ def test_oddeven_every_bucket_size(log_b):
             assert np.array_equal(_host(kd), ref), (log_b, n, v)
 
 
-@pytest.mark.parametrize("log_b", [6, 8, 11])
+@pytest.mark.parametrize("log_b", [6, 8, 11, 13, 14])
 def test_oddeven_stage_parity(log_b):
     # every step prefix of the network, three buckets plus a ragged one
     T = 1 << log_b
