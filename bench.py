@@ -108,7 +108,7 @@ def _mixed_fraction(p, wave=64):
 def main():
     args = _parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: measures one GPU only (asked for --gpus {args.gpus}); "
               "the kernels shard by lane range / segment but no multi-GPU path is built",
               file=sys.stderr)
         sys.exit(2)
