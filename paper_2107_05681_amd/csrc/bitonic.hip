@@ -576,9 +576,9 @@ __global__ __launch_bounds__(1 << (L - 4)) void bitonic_sort_regs_kernel(SortArr
     E e[kMergeE];
     regs_load<PAIRS, L, L>(a, map, t, mode, e);
 #pragma unroll
-    for (int r = 0; r < kMergeE; ++r) s[merge_index<L, -1>(t, r)] = e[r];  // natural order
+    for (int r = 0; r < kMergeE; ++r) s[low_swz<E, PAIRS>(merge_index<L, -1>(t, r))] = e[r];  // natural order
     __syncthreads();
-    const int32_t lo_steps = lds_network_low<E, MELD_LO, 8>(s, base, 6, t, NT, step_limit);
+    const int32_t lo_steps = lds_network_low<E, MELD_LO, 8, PAIRS>(s, base, 6, t, NT, step_limit);
     __syncthreads();
     int32_t left = step_limit < 0 ? 0x7FFFFFFF : step_limit - lo_steps;
 
@@ -588,7 +588,7 @@ __global__ __launch_bounds__(1 << (L - 4)) void bitonic_sort_regs_kernel(SortArr
     {
         const uint32_t tb = window_tpart(t, prev);
 #pragma unroll
-        for (int r = 0; r < kMergeE; ++r) e[r] = s[tb | ((uint32_t)r << prev)];
+        for (int r = 0; r < kMergeE; ++r) e[r] = s[low_swz<E, PAIRS>(tb | ((uint32_t)r << prev))];
         __syncthreads();
     }
     for (uint32_t m = 7; m <= (uint32_t)L; ++m) {

@@ -118,6 +118,25 @@ __device__ __forceinline__ int32_t lds_network(E *s, uint32_t T, uint32_t base, 
     return steps;
 }
 
+// LDS position of tile element x in the steps of phases k <= 64. With
+// comparators dealt to consecutive lanes, the ends of a step j <= 32 that a
+// pass of 32 (or 64) lanes touches are the elements of a 64 (128) block whose
+// bit j is clear, or set: in natural order two of them share every bank. For
+// 4-byte elements, flipping bits 0..4 when bit 5 is set and bit 5 when bit 6
+// is set sends them to distinct banks for every j, on 32 and on 64 banks; for
+// 8-byte elements the same with bits 4 and 5. A permutation inside each
+// 128-element (64 for 8-byte) block; positions of the blocks are unchanged.
+// SWZ = false keeps natural order: the ends of a comparator then sit a fixed
+// distance apart and pair into one ds_read2 / ds_write2, which the swizzle
+// gives up (more instructions, fewer conflicts; it pays for 8-byte pairs and
+// for the segmented sort, not for the 2^16-key local sort).
+template <typename E, bool SWZ = true>
+__device__ __forceinline__ uint32_t low_swz(uint32_t x) {
+    if constexpr (!SWZ) return x;
+    constexpr uint32_t S = sizeof(E) == 4 ? 5u : 4u;
+    return x ^ (((x >> S) & 1u) * ((1u << S) - 1u)) ^ (((x >> (S + 1)) & 1u) << S);
+}
+
 // One group of ITERS comparators of a step (k = 2^m, j) per lane: lane0,
 // lane0 + nt, ... All loads of the group are issued before its first compare,
 // so their LDS latency overlaps.
@@ -128,7 +147,7 @@ __device__ __forceinline__ int32_t lds_network(E *s, uint32_t T, uint32_t base, 
 //     comparators, so the branch is taken once per step (the loop is
 //     unswitched) and each side holds its own batched loads, compares and
 //     swap stores; with nt < 64 it stays per comparator.
-template <typename E, bool MELDED, int ITERS>
+template <typename E, bool MELDED, int ITERS, bool SWZ>
 __device__ __forceinline__ void lds_step_group(E *s, uint32_t base, uint32_t m, uint32_t j,
                                                uint32_t lane0, uint32_t nt) {
     uint32_t lo[ITERS];
@@ -146,12 +165,29 @@ __device__ __forceinline__ void lds_step_group(E *s, uint32_t base, uint32_t m, 
             lo[i] = ((c & ~(j - 1)) << 1) | (c & (j - 1));
         }
     }
+    // LDS positions of the two ends (low_swz); the direction uses lo itself
+    uint32_t pl[ITERS], ph[ITERS];
+    if (nt >= 64) {
+        // 2 i nt is a multiple of 128: it commutes with the swizzle
+        const uint32_t pl0 = low_swz<E, SWZ>(lo[0]), ph0 = low_swz<E, SWZ>(lo[0] + j);
+#pragma unroll
+        for (int i = 0; i < ITERS; ++i) {
+            pl[i] = pl0 + 2u * (uint32_t)i * nt;
+            ph[i] = ph0 + 2u * (uint32_t)i * nt;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < ITERS; ++i) {
+            pl[i] = low_swz<E, SWZ>(lo[i]);
+            ph[i] = low_swz<E, SWZ>(lo[i] + j);
+        }
+    }
     if constexpr (MELDED) {
         E a[ITERS], b[ITERS];
 #pragma unroll
         for (int i = 0; i < ITERS; ++i) {
-            a[i] = s[lo[i]];
-            b[i] = s[lo[i] + j];
+            a[i] = s[pl[i]];
+            b[i] = s[ph[i]];
         }
         if (nt >= 64) {
             // nt is a multiple of 64 >= 2^m: every comparator of the lane has
@@ -160,16 +196,16 @@ __device__ __forceinline__ void lds_step_group(E *s, uint32_t base, uint32_t m, 
 #pragma unroll
             for (int i = 0; i < ITERS; ++i)
                 if (melded_swap(a[i], b[i], up)) {
-                    s[lo[i]] = b[i];
-                    s[lo[i] + j] = a[i];
+                    s[pl[i]] = b[i];
+                    s[ph[i]] = a[i];
                 }
         } else {
 #pragma unroll
             for (int i = 0; i < ITERS; ++i) {
                 const bool up = (((base | lo[i]) >> m) & 1u) == 0;
                 if (melded_swap(a[i], b[i], up)) {
-                    s[lo[i]] = b[i];
-                    s[lo[i] + j] = a[i];
+                    s[pl[i]] = b[i];
+                    s[ph[i]] = a[i];
                 }
             }
         }
@@ -180,49 +216,49 @@ __device__ __forceinline__ void lds_step_group(E *s, uint32_t base, uint32_t m, 
             MELD_SIDE_MARK("ascending batch");
 #pragma unroll
             for (int i = 0; i < ITERS; ++i) {
-                a[i] = s[lo[i]];
-                b[i] = s[lo[i] + j];
+                a[i] = s[pl[i]];
+                b[i] = s[ph[i]];
             }
 #pragma unroll
             for (int i = 0; i < ITERS; ++i)
                 if (b[i] < a[i]) {
-                    s[lo[i]] = b[i];
-                    s[lo[i] + j] = a[i];
+                    s[pl[i]] = b[i];
+                    s[ph[i]] = a[i];
                 }
             MELD_SIDE_MARK("ascending batch end");
         } else {
             MELD_SIDE_MARK("descending batch");
 #pragma unroll
             for (int i = 0; i < ITERS; ++i) {
-                a[i] = s[lo[i]];
-                b[i] = s[lo[i] + j];
+                a[i] = s[pl[i]];
+                b[i] = s[ph[i]];
             }
 #pragma unroll
             for (int i = 0; i < ITERS; ++i)
                 if (b[i] > a[i]) {
-                    s[lo[i]] = b[i];
-                    s[lo[i] + j] = a[i];
+                    s[pl[i]] = b[i];
+                    s[ph[i]] = a[i];
                 }
             MELD_SIDE_MARK("descending batch end");
         }
     } else {
 #pragma unroll
         for (int i = 0; i < ITERS; ++i)
-            cex_divergent(s, lo[i], lo[i] + j, (((base | lo[i]) >> m) & 1u) == 0);
+            cex_divergent(s, pl[i], ph[i], (((base | lo[i]) >> m) & 1u) == 0);
     }
 }
 
 // The comparators of a step in groups of at most 4 (bounding the registers a
 // group holds in flight; 4 loads per comparator pair in flight per lane
 // already cover the LDS latency).
-template <typename E, bool MELDED, int ITERS>
+template <typename E, bool MELDED, int ITERS, bool SWZ>
 __device__ __forceinline__ void lds_step_batched(E *s, uint32_t base, uint32_t m, uint32_t j,
                                                  uint32_t lane0, uint32_t nt) {
     constexpr int G = ITERS < 4 ? ITERS : 4;
     static_assert(ITERS % G == 0, "comparators per lane must split into groups");
 #pragma unroll
     for (int h = 0; h < ITERS / G; ++h)
-        lds_step_group<E, MELDED, G>(s, base, m, j, lane0 + (uint32_t)(h * G) * nt, nt);
+        lds_step_group<E, MELDED, G, SWZ>(s, base, m, j, lane0 + (uint32_t)(h * G) * nt, nt);
 }
 
 // Phases k = 2 .. 2^m_end (m_end <= 6) of the network on a tile of
@@ -232,7 +268,7 @@ __device__ __forceinline__ void lds_step_batched(E *s, uint32_t base, uint32_t m
 // a team shorter than a wave share one wave, and for nt >= 64 a wave's
 // comparators of one iteration stay inside one 128-element block in every
 // step j <= 32.
-template <typename E, bool MELDED, int ITERS>
+template <typename E, bool MELDED, int ITERS, bool SWZ>
 __device__ __forceinline__ int32_t lds_network_low(E *s, uint32_t base, uint32_t m_end,
                                                    uint32_t lane0, uint32_t nt,
                                                    int32_t step_limit) {
@@ -241,7 +277,7 @@ __device__ __forceinline__ int32_t lds_network_low(E *s, uint32_t base, uint32_t
         for (uint32_t j = 1u << (m - 1); j > 0; j >>= 1) {
             if (steps == step_limit) return steps;
             ++steps;
-            lds_step_batched<E, MELDED, ITERS>(s, base, m, j, lane0, nt);
+            lds_step_batched<E, MELDED, ITERS, SWZ>(s, base, m, j, lane0, nt);
             wave_lds_sync();
         }
     }

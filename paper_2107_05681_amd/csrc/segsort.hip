@@ -333,9 +333,9 @@ __device__ __forceinline__ void team_sort(uint32_t *__restrict__ keys,
         e[r] = rb + tl < len ? (keys + lo + rb)[tl] : kPad;
     }
 #pragma unroll
-    for (int r = 0; r < kSegE; ++r) s[t | ((uint32_t)r << lt)] = e[r];
+    for (int r = 0; r < kSegE; ++r) s[low_swz<uint32_t>(t | ((uint32_t)r << lt))] = e[r];
     __syncthreads();
-    lds_network_low<uint32_t, MELD_LO, 8>(s, cbase, 6, t, 1u << lt, -1);
+    lds_network_low<uint32_t, MELD_LO, 8, true>(s, cbase, 6, t, 1u << lt, -1);
     __syncthreads();
     // Phase 2^7 starts in window 3 (element bits 3..6), read from the natural
     // order the comparator network leaves in s.
@@ -343,7 +343,7 @@ __device__ __forceinline__ void team_sort(uint32_t *__restrict__ keys,
     {
         const uint32_t tb = window_tpart(t, cur);
 #pragma unroll
-        for (int r = 0; r < kSegE; ++r) e[r] = s[tb | ((uint32_t)r << cur)];
+        for (int r = 0; r < kSegE; ++r) e[r] = s[low_swz<uint32_t>(tb | ((uint32_t)r << cur))];
         __syncthreads();
     }
 #pragma unroll 1
