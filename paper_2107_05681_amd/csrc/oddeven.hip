@@ -56,6 +56,15 @@ __device__ __forceinline__ OeRole oe_role(uint32_t e, uint32_t p, uint32_t k) {
     return {active ? (lower ? kk : -kk) : 0, lower};
 }
 
+// The melded update of an element with key v and partner key b: the lower end
+// keeps the minimum, the upper end the maximum. The partner is taken when
+// (b < v) equals the side, one compare, one mask operation on the scalar unit
+// and one select (ties: b equals v, either is right; an idle element reads
+// itself).
+__device__ __forceinline__ uint32_t oe_keep_side(uint32_t v, uint32_t b, bool lower) {
+    return (b < v) == lower ? b : v;
+}
+
 // Steps with k >= NT (so 2p > NT): element r of the lane (t + r NT) has its
 // partner r +- q, q = k / NT, in the lane's own registers, and its role is
 // the same for every lane: bit k of the element is bit q of r and the
@@ -105,9 +114,7 @@ __device__ __forceinline__ void oe_edge_step(const uint32_t (&v)[E], uint32_t (&
         for (int r = 0; r < E; ++r) {
             const uint32_t *pp = r % Q == 0 ? p_first : (r % Q == Q - 1 ? p_last : p_mid);
             const uint32_t b = pp[(uint32_t)r * NT];
-            const uint32_t mn = v[r] < b ? v[r] : b;
-            const uint32_t mx = v[r] < b ? b : v[r];
-            nv[r] = lower ? mn : mx;
+            nv[r] = oe_keep_side(v[r], b, lower);
         }
     } else {
 #pragma unroll
@@ -167,9 +174,7 @@ __device__ __forceinline__ void oe_lds_step(uint32_t (&v)[E], OeState &st, uint3
 #pragma unroll
             for (int r = 0; r < E; ++r) {
                 const uint32_t b = pp[(uint32_t)r * NT];
-                const uint32_t mn = v[r] < b ? v[r] : b;
-                const uint32_t mx = v[r] < b ? b : v[r];
-                nv[r] = role.lower ? mn : mx;
+                nv[r] = oe_keep_side(v[r], b, role.lower);
             }
         } else {
 #pragma unroll
