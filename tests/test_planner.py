@@ -173,3 +173,25 @@ def test_planner_on_region_kernel():
     m = P._find(res, r"region_melded_kernel", "region.hip")
     assert 0 < d["vgpr_count"] <= 512 and 0 < m["vgpr_count"] <= 512
     assert d["private_segment_fixed_size"] == 0 and m["private_segment_fixed_size"] == 0
+
+
+@pytest.mark.skipif(not os.path.exists(P.HIPCC) and shutil.which("hipcc") is None,
+                    reason="hipcc not installed")
+def test_planner_on_oddeven_kernel():
+    # The odd-even network's divergent form has a lower / upper side pair per
+    # step shape (the uniform-role steps and one per compile-time row class of
+    # the edge steps). Both sides load a partner and keep one key, so MP_S is
+    # high but below the 0.5 of identical sides: the edge rows add idle tests
+    # on one side only. The melded form has no sides left and no spills.
+    fns = P.parse_ir(P.emit_ir("oddeven.hip"))
+    fn = P._find(fns, r"oddeven_bucket_kernelILi8ELi1024ELb0E", "oddeven.hip")
+    (r,) = P.analyse_function(fn, (("lower", "upper"),))
+    assert r.instances >= 2
+    assert P.THRESHOLD <= r.mp_s < 0.5 and r.profitable
+    assert min(r.lat) > 0
+    melded = P._find(fns, r"oddeven_bucket_kernelILi8ELi1024ELb1E", "oddeven.hip")
+    assert not any(b.marks for b in melded.blocks.values())
+    res = P.resources("oddeven.hip")
+    for pat in (r"oddeven_bucket_kernelILi8ELi1024ELb0E", r"oddeven_bucket_kernelILi8ELi1024ELb1E"):
+        k = P._find(res, pat, "oddeven.hip")
+        assert k["private_segment_fixed_size"] == 0 and 0 < k["vgpr_count"] <= 64
