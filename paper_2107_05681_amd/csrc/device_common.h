@@ -36,19 +36,6 @@ constexpr uint32_t blocks_for(uint32_t n, uint32_t per) {
     return (uint32_t)(((uint64_t)n + per - 1) / per);
 }
 
-// Grid for n < 2^32 items in workgroups of `per` (a power of two <= 2^31).
-// HIP caps one grid dimension at 2^32 - 1 work-items, so past 2^31 items the
-// workgroups go in two rows of 2^31 items; kernels number them with
-// linear_block() / linear_blocks(). Rows hold a multiple of 8 workgroups, so a
-// workgroup's XCD (linear number mod 8) is the same in either numbering.
-inline dim3 lane_grid(uint32_t n, uint32_t per) {
-    const uint32_t nb = blocks_for(n, per);
-    const uint32_t row = (1u << 31) / per;
-    return nb <= row ? dim3(nb) : dim3(row, (nb + row - 1) / row);
-}
-__device__ __forceinline__ uint32_t linear_block() { return blockIdx.y * gridDim.x + blockIdx.x; }
-__device__ __forceinline__ uint32_t linear_blocks() { return gridDim.x * gridDim.y; }
-
 // MI355X deals the workgroups of a launch to its 8 XCDs in turn (workgroup w
 // runs on XCD w mod 8), and each XCD has its own L2. This renumbering gives
 // every XCD one contiguous range of logical workgroups, so data that

@@ -10,8 +10,9 @@ namespace meld {
 namespace {
 
 // keys[i] = stream(seed, 1)[i] >> 32
-__global__ __launch_bounds__(256) void gen_keys_kernel(uint32_t *keys, uint32_t n, uint64_t key) {
-    const uint32_t i = linear_block() * 256 + threadIdx.x;
+__global__ __launch_bounds__(256) void gen_keys_kernel(uint32_t *keys, uint32_t n, uint32_t i0,
+                                                       uint64_t key) {
+    const uint32_t i = i0 + blockIdx.x * 256 + threadIdx.x;
     if (i < n) keys[i] = (uint32_t)(mix64(key + i) >> 32);
 }
 
@@ -29,23 +30,37 @@ __global__ __launch_bounds__(256) void gen_keys_segments_kernel(uint32_t *keys,
 }
 
 // x[i] = (stream(seed, 2)[i] >> 40) * 2^-24
-__global__ __launch_bounds__(256) void gen_x_kernel(float *x, uint32_t n, uint64_t key) {
-    const uint32_t i = linear_block() * 256 + threadIdx.x;
+__global__ __launch_bounds__(256) void gen_x_kernel(float *x, uint32_t n, uint32_t i0,
+                                                    uint64_t key) {
+    const uint32_t i = i0 + blockIdx.x * 256 + threadIdx.x;
     if (i < n) x[i] = (float)(mix64(key + i) >> 40) * 0x1p-24f;
 }
 
 // tab[m] = 0.5 + (stream(seed, 3)[m] >> 41) * 2^-24
-__global__ __launch_bounds__(256) void gen_tab_kernel(float *tab, uint32_t m, uint64_t key) {
-    const uint32_t i = linear_block() * 256 + threadIdx.x;
+__global__ __launch_bounds__(256) void gen_tab_kernel(float *tab, uint32_t m, uint32_t i0,
+                                                      uint64_t key) {
+    const uint32_t i = i0 + blockIdx.x * 256 + threadIdx.x;
     if (i < m) tab[i] = 0.5f + (float)(mix64(key + i) >> 41) * 0x1p-24f;
+}
+
+// Launches cover at most 2^31 items each (HIP caps a grid dimension at
+// 2^32 - 1 work-items); i0 is the launch's first item.
+constexpr uint64_t kGenLaunchItems = 1ull << 31;
+
+template <typename Kern, typename T>
+void launch_items(Kern kern, T *out, uint32_t n, uint64_t key, hipStream_t s) {
+    for (uint64_t i0 = 0; i0 < n; i0 += kGenLaunchItems) {
+        const uint32_t len = (uint32_t)(n - i0 < kGenLaunchItems ? n - i0 : kGenLaunchItems);
+        hipLaunchKernelGGL(kern, dim3(blocks_for(len, 256)), dim3(256), 0, s, out, n,
+                           (uint32_t)i0, key);
+    }
 }
 
 }  // namespace
 
 hipError_t launch_gen_keys(uint32_t *keys, uint32_t n, uint64_t seed, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(gen_keys_kernel, lane_grid(n, 256), dim3(256), 0, s, keys, n,
-                       stream_key(seed, 1));
+    launch_items(gen_keys_kernel, keys, n, stream_key(seed, 1), s);
     return hipGetLastError();
 }
 
@@ -61,15 +76,13 @@ hipError_t launch_gen_keys_segments(uint32_t *keys, const uint32_t *offsets,
 
 hipError_t launch_gen_x(float *x, uint32_t n, uint64_t seed, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(gen_x_kernel, lane_grid(n, 256), dim3(256), 0, s, x, n,
-                       stream_key(seed, 2));
+    launch_items(gen_x_kernel, x, n, stream_key(seed, 2), s);
     return hipGetLastError();
 }
 
 hipError_t launch_gen_tab(float *tab, uint32_t m, uint64_t seed, hipStream_t s) {
     if (m == 0) return hipSuccess;
-    hipLaunchKernelGGL(gen_tab_kernel, lane_grid(m, 256), dim3(256), 0, s, tab, m,
-                       stream_key(seed, 3));
+    launch_items(gen_tab_kernel, tab, m, stream_key(seed, 3), s);
     return hipGetLastError();
 }
 
