@@ -136,9 +136,12 @@ def test_segmented_offsets_beyond_keys_rejected():
     # its trials, rejects the call at once.
     keys = workloads.keys_u32(2, 200)
     off = _to_dev(np.array([0, 100, 300], np.uint32))
-    for v in ("divergent", "melded"):
+    for v in ("divergent", "melded", "staged"):
         kd = _to_dev(keys)
-        meld.segmented_sort(kd, off, variant=v)
+        if v == "staged":  # per-stage forms: meld_segmented_sort_u32_staged
+            meld.segmented_sort(kd, off, low="melded", high="divergent")
+        else:
+            meld.segmented_sort(kd, off, variant=v)
         with pytest.raises(meld.MeldError) as e:
             meld.segmented_sort_check(0)
         assert e.value.status == meld.EINVAL and "beyond n_keys" in str(e.value), v
