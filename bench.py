@@ -1,18 +1,19 @@
 """Benchmark of the melded-kernel library on one MI355X.
 
-Workload (one step): the two-sided loop region over 2^24 fp32 lanes, once
-at each branch probability p in {0.1, 0.5, 0.9}, gathering from a 2^24-entry
-(64 MiB) fp32 table; each side is a loop of 8..32 fma + gather steps and the
-sides differ only in constants and trip count. Inputs are synthetic and
-seeded (workloads/), resident in HBM before the timed region. The step runs
-the library's default form (MELD_AUTO, the melded kernel).
+Workload (one step): the bitonic sort of 2^28 (u32 key, u32 payload = original
+index) pairs in place in HBM, keys uniform from seed 1, through the library's
+default form (MELD_AUTO: tile and per-stage forms tuned once). The input is
+restored from a pristine copy before each step, outside the timed events;
+inputs are synthetic and seeded (workloads/) and resident in HBM before the
+timed region.
 
-Printed: one JSON line with the whole-step throughput (lanes/s, reported as
-"Gkeys/s" with one key = one region lane), the melded/divergent speedup per
-p from interleaved per-kernel timings, the roofline of the dominant kernel
-(melded, p = 0.5) from HIP events on the launch stream, the bitonic sort of
-2^28 (key, payload) pairs and of 2^16 keys in both forms, and the CPU oracle
-timed on this host.
+Printed: one JSON line with the sort's throughput (Gkeys/s), the duration of
+every launch from HIP events on the launch stream and the roofline of the
+dominant kernel, the melded/divergent speedup on seeds 1..3 (median, p10,
+p90), the paper's published speedups (context), the two-sided loop region,
+the 2^16-key sort, the odd-even and merge sorts, the segmented sort, the
+serving loop, and the CPU oracle timed on this host (one thread and all the
+threads it may use).
 """
 from __future__ import annotations
 
@@ -28,28 +29,38 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+N_PAIRS = 1 << 28
 N_LANES = 1 << 24
 PS = (0.1, 0.5, 0.9)
 SEED = 1
+# x read, y written, the table read once: 3 arrays of 2^24 fp32
+REGION_COMPULSORY = 3 * 4 * N_LANES
 
 
 def _parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--reps", type=int, default=30, help="launches per per-kernel timing")
-    ap.add_argument("--no-sort", action="store_true", help="skip the sort measurements")
+    ap.add_argument("--seg-reps", type=int, default=40,
+                    help="timed segmented sorts per seed and form")
+    ap.add_argument("--pair-reps", type=int, default=28,
+                    help="timed 2^28-pair sorts per seed and form (28: about 1 s each)")
+    ap.add_argument("--no-region", action="store_true", help="skip the region measurements")
+    ap.add_argument("--no-sort", action="store_true",
+                    help="skip the 2^16-key, odd-even and merge sorts")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-seg", action="store_true", help="skip the segmented sort")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the Poisson serving trace (0 skips serving)")
     ap.add_argument("--profile", nargs="?", const="region", default=None,
                     choices=["region", "sort", "pairs", "next"],
-                    help="short run for rocprofv3: 'region' (a 256 MiB copy, then a few "
-                         "steps), 'sort' (2^16 keys and the 4096-segment sort, each form), "
-                         "'pairs' (one 2^28-pair sort per form) or 'next' (2^24 keys: "
-                         "odd-even buckets of 2^13 and the merge sort, each form)")
+                    help="short run for rocprofv3: 'region' (a 256 MiB copy, then the "
+                         "region in each form), 'sort' (2^16 keys and the 4096-segment sort, "
+                         "each form), 'pairs' (a 256 MiB copy, then one 2^28-pair sort per "
+                         "form and three MELD_AUTO sorts) or 'next' (2^24 keys: odd-even "
+                         "buckets of 2^13 and the merge sort, each form)")
     return ap.parse_args()
 
 
@@ -64,12 +75,12 @@ def _events_time(torch, fn, reps):
     return s.elapsed_time(e) / reps
 
 
-def _measured_traffic():
-    """HBM bytes per launch of the melded region kernel (p = 0.5) from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled by the copy calibration; None
-    when the kernel source has changed since those counters were taken."""
+def _measured_traffic(name):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs (profiles/<name>), scaled by the copy calibration; None when
+    the kernel's sources have changed since those counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "region_melded_traffic.json")
+    path = os.path.join(ROOT, "profiles", name)
     try:
         with open(path) as f:
             rec = json.load(f)
@@ -105,6 +116,51 @@ def _mixed_fraction(p, wave=64):
     return 1.0 - p ** wave - (1.0 - p) ** wave
 
 
+def _cpu_info():
+    """Host CPU model, logical CPUs and the CPUs this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = os.cpu_count() or 1
+    return {"cpu_model": model, "host_logical_cpus": os.cpu_count(), "affinity_cpus": allowed}
+
+
+def _oracle_threads():
+    """Host threads for the all-core oracle timings: the CPUs this process may use,
+    at most 16 (the host share of one GPU on the GPU machines)."""
+    return max(1, min(16, _cpu_info()["affinity_cpus"]))
+
+
+def _pairs_inputs(torch, np, workloads, dev, seed, n):
+    kin = torch.from_numpy(workloads.keys_u32(seed, n).view(np.int32)).to(dev)
+    pin = torch.arange(n, dtype=torch.int32, device=dev)
+    return kin, pin
+
+
+def _check_pairs_sorted(torch, kin, k, p):
+    """The timed output is the unique (key, payload) order of the input: keys
+    non-decreasing, payloads increasing within equal keys, payload a permutation
+    of 0..n-1 and k == kin[p] (these fix the sorted array exactly)."""
+    ku = k.to(torch.int64) & 0xFFFFFFFF
+    pu = p.to(torch.int64) & 0xFFFFFFFF
+    comp = ku * (1 << 32) + pu
+    if not bool((comp[1:] > comp[:-1]).all()):
+        raise SystemExit("2^28-pair sort: output not in strictly increasing (key, payload) order")
+    if not bool((torch.bincount(pu, minlength=k.numel()) == 1).all()):
+        raise SystemExit("2^28-pair sort: payload is not a permutation")
+    if not torch.equal(kin[pu], k):
+        raise SystemExit("2^28-pair sort: keys do not follow their payloads")
+
+
 def main():
     args = _parse()
     if args.gpus != 1:
@@ -125,6 +181,245 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
+    if args.profile == "sort":
+        _profile_sorts(torch, np, meld, workloads, dev)
+        return
+    if args.profile == "pairs":
+        _profile_pairs(torch, np, meld, workloads, dev)
+        return
+    if args.profile == "next":
+        _profile_next(torch, np, meld, workloads, dev)
+        return
+    if args.profile == "region":
+        _profile_region(torch, np, meld, workloads, dev)
+        return
+
+    # ---- Headline: bitonic sort of 2^28 (key, payload = index) pairs ----------
+    n = N_PAIRS
+    kin, pin = _pairs_inputs(torch, np, workloads, dev, SEED, n)
+    k, p = torch.empty_like(kin), torch.empty_like(pin)
+
+    def restore():
+        k.copy_(kin)
+        p.copy_(pin)
+
+    for _ in range(max(args.warmup, 1)):  # the first MELD_AUTO call tunes this shape once
+        restore()
+        meld.sort_timed(k, p, variant="auto")
+    torch.cuda.synchronize()
+    step_ms, launches = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        restore()  # outside the events: each step sorts the pristine input
+        ms = meld.sort_timed(k, p, variant="auto")
+        launches.append(ms)
+        step_ms.append(sum(ms))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    _check_pairs_sorted(torch, kin, k, p)
+    ms_per_step = float(np.mean(step_ms))
+    value = n / (ms_per_step * 1e-3) / 1e9
+    plan = meld.sort_plan(n, pairs=True, variant="auto", device=0)
+    roof, per_kind = _sort_roofline(np, plan, launches, n)
+    hbm_moved = 16.0 * n * plan["hbm_passes"]
+    del k, p
+    torch.cuda.empty_cache()
+
+    pairs_forms = _bench_pairs_forms(torch, np, meld, workloads, dev, kin, pin, args)
+    del kin, pin
+    torch.cuda.empty_cache()
+
+    region_info = None
+    if not args.no_region:
+        region_info = _bench_region(torch, np, meld, workloads, dev, args)
+
+    sort16 = oddeven_info = merge_info = None
+    if not args.no_sort:
+        sort16 = _bench_sort16(torch, np, meld, workloads, dev, args)
+        oddeven_info = _bench_oddeven(torch, np, meld, workloads, dev)
+        merge_info = _bench_mergesort(torch, np, meld, workloads, dev)
+
+    seg_info = None
+    if not args.no_seg:
+        seg_info = _bench_segmented(torch, np, meld, workloads, dev, args)
+
+    serve_info = None
+    if args.serve_seconds > 0:
+        serve_info = _bench_serving(meld, workloads, args.serve_seconds)
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = _cpu_baseline_pairs(np, workloads)
+        if sort16 is not None:
+            sort16["cpu_oracle"] = _cpu_sort_keys(np, workloads, 1 << 16)
+        if seg_info is not None:
+            seg_info["cpu_oracle"] = _cpu_segmented(np, workloads)
+        if region_info is not None:
+            region_info["cpu_oracle"] = _cpu_region(np, workloads)
+
+    out = {
+        "metric": "melded/divergent speedup; Gkeys/s and VALU lane utilisation (rocprof)",
+        "value": round(value, 4),
+        "unit": "Gkeys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step_dist": _dist(np, step_ms, scale=1.0),
+        "wall_s_timed": round(wall, 4),
+        "wall_note": "wall clock of the timed loop, including the untimed restore of the "
+                     "2 GiB input before each step",
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic (seeded SplitMix64 keys, payload = index; workloads/)",
+        "config": {
+            "workload": "bitonic sort of 2^28 (u32 key, u32 payload = original index) pairs, "
+                        "keys uniform from seed 1, in place in HBM, MELD_AUTO",
+            "n": n, "seed": SEED, "variant": "auto",
+            "log_tile": plan["log_tile"], "low_phases": plan["low"],
+            "high_phases": plan["high"], "hbm_passes": plan["hbm_passes"],
+            "launches": len(plan["passes"]),
+        },
+        "sort_hbm": {"bytes_per_sort": int(hbm_moved),
+                     "achieved_GBs": round(hbm_moved / (ms_per_step * 1e-3) / 1e9, 1),
+                     "frac_of_peak": round(hbm_moved / (ms_per_step * 1e-3) / 1e9
+                                           / HBM_PEAK_GBS, 4),
+                     "note": "16 B per pair per HBM pass (8 read + 8 written) x the plan's "
+                             "passes, over the whole sort"},
+        "kernels": per_kind,
+        "roofline": roof,
+        "melded_vs_divergent": pairs_forms,
+        "paper_context": PAPER_CONTEXT,
+        "region": region_info,
+        "sort_keys_2^16": sort16,
+        "oddeven_buckets": oddeven_info,
+        "mergesort": merge_info,
+        "segmented": seg_info,
+        "serving": serve_info,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+# Published numbers of the paper (Evaluation section, "Evaluation Setup and
+# Benchmarks" and "Performance"): context only, measured on other hardware.
+PAPER_CONTEXT = {
+    "hardware": "AMD Radeon Pro Vega 20 (wave64, 64 KiB LDS, 1700 MHz), ROCm 4.2, LLVM 12",
+    "synthetic_benchmarks_geomean_speedup": 1.36,
+    "real_world_geomean_speedup_all_block_sizes": 1.15,
+    "real_world_geomean_speedup_best_block_size": 1.16,
+    "note": "compiler-melded code vs the same kernels at -O3; context only, not a target",
+}
+
+KIND_KERNEL = {
+    "local": "bitonic_sort_regs_kernel (local sort of every tile)",
+    "regs": "bitonic_global_kernel (streaming pass, up to 6 steps in registers)",
+    "gather": "bitonic_pass_regs_kernel<L,R,L-R> (gathered streaming pass)",
+    "merge": "bitonic_pass_regs_kernel<L,L,L> (merge tail of a phase)",
+    "tile": "bitonic_sort_regs_kernel (single tile)",
+}
+
+
+def _sort_roofline(np, plan, launches, n):
+    """Per launch kind of the timed sorts: launches, average and total time, and the
+    HBM rate of its algorithmic bytes (16 B per pair per launch); the roofline of
+    the kind with the largest total time."""
+    kinds = [ps["kind"] for ps in plan["passes"]]
+    per = {}
+    for step in launches:
+        if len(step) != len(kinds):
+            raise SystemExit("sort: launches differ from the plan")
+        for kind, ms in zip(kinds, step):
+            per.setdefault(kind, []).append(ms)
+    per_kind = {}
+    for kind, ms in per.items():
+        avg = float(np.mean(ms))
+        per_kind[kind] = {"kernel": KIND_KERNEL[kind], "launches_per_sort": kinds.count(kind),
+                          "avg_launch_us": round(avg * 1e3, 2),
+                          "ms_per_sort": round(sum(ms) / len(launches), 4),
+                          "alg_GBs": round(16.0 * n / (avg * 1e-3) / 1e9, 1)}
+    dom = max(per_kind, key=lambda kd: per_kind[kd]["ms_per_sort"])
+    avg_us = per_kind[dom]["avg_launch_us"]
+    achieved = 16.0 * n / (avg_us * 1e-6) / 1e9
+    roof = {"bound": "hbm", "kernel": per_kind[dom]["kernel"], "kind": dom,
+            "avg_launch_us": avg_us, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": _measured_traffic("sort_merge_traffic.json"),
+            "alg_bytes_per_launch": int(16 * n),
+            "note": "one launch reads and writes every (key, payload) pair once: 16 B per pair; "
+                    "avg_launch_us from HIP events recorded between the launches of the timed "
+                    "sorts on their stream"}
+    return roof, per_kind
+
+
+def _bench_pairs_forms(torch, np, meld, workloads, dev, kin1, pin, args):
+    """2^28 pairs, divergent vs melded (same tile), interleaved, seeds 1..3, at least
+    ~1 s of sorts per seed and form; the local-sort launch alone per form."""
+    n = N_PAIRS
+    k, p = torch.empty_like(kin1), torch.empty_like(pin)
+    res = {}
+    reps = max(4, args.pair_reps)
+    for seed in (1, 2, 3):
+        kin = kin1 if seed == SEED else _pairs_inputs(torch, np, workloads, dev, seed, n)[0]
+        t = {"divergent": [], "melded": []}
+        for rep in range(reps + 1):
+            for v in ("divergent", "melded"):
+                k.copy_(kin)
+                p.copy_(pin)
+                s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                s.record()
+                meld.sort(k, p, variant=v)
+                e.record()
+                e.synchronize()
+                if rep > 0:
+                    t[v].append(s.elapsed_time(e))
+        d, m = float(np.median(t["divergent"])), float(np.median(t["melded"]))
+        res[f"seed_{seed}"] = {"divergent_ms": _dist(np, t["divergent"], scale=1.0),
+                               "melded_ms": _dist(np, t["melded"], scale=1.0),
+                               "speedup": round(d / m, 4), "reps": reps,
+                               "melded_Gkeys_s": round(n / (m * 1e-3) / 1e9, 3)}
+        if seed != SEED:
+            del kin
+    res["median_speedup"] = round(float(np.median(
+        [res[f"seed_{s}"]["speedup"] for s in (1, 2, 3)])), 4)
+    # the local sort alone: the network's first t (t + 1) / 2 steps are exactly that launch
+    plan = meld.sort_plan(n, pairs=True, variant="melded", device=0)
+    local = plan["passes"][0]["steps"]
+    tl = {}
+    for v in ("divergent", "melded"):
+        tl[v] = _time_sorts(torch, np, lambda v=v: meld.sort_steps(k, p, local, variant=v),
+                            lambda: (k.copy_(kin1), p.copy_(pin)), 11)
+    res["local_sort_kernel"] = {"steps": local, "log_tile": plan["log_tile"],
+                                "divergent_ms": round(tl["divergent"], 4),
+                                "melded_ms": round(tl["melded"], 4),
+                                "speedup": round(tl["divergent"] / tl["melded"], 4)}
+    del k, p
+    torch.cuda.empty_cache()
+    return res
+
+
+def _profile_region(torch, np, meld, workloads, dev):
+    """A 256 MiB copy (calibration of the byte counters), then the region at p in
+    {0.1, 0.5, 0.9} in each form."""
+    x, tab, st, sf = workloads.region_inputs(SEED, N_LANES)
+    xd, td = torch.from_numpy(x).to(dev), torch.from_numpy(tab).to(dev)
+    y = torch.empty_like(xd)
+    src = torch.empty(1 << 26, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)  # calibration copy: 256 MiB read + 256 MiB written
+    for v in ("melded", "melded", "melded", "divergent", "melded_inplace"):
+        for p in PS:
+            meld.divergent_region(xd, td, SEED, workloads.thr_from_p(p), st, sf, variant=v,
+                                  out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_run": "region", "copy_bytes": 2 * src.numel() * 4}))
+
+
+def _bench_region(torch, np, meld, workloads, dev, args):
+    """The two-sided loop region over 2^24 lanes at p in {0.1, 0.5, 0.9}: per-form
+    timings (interleaved), the tuned step, sensitivity cases and variants."""
     x, tab, st, sf = workloads.region_inputs(SEED, N_LANES)
     xd = torch.from_numpy(x).to(dev)
     td = torch.from_numpy(tab).to(dev)
@@ -138,41 +433,11 @@ def main():
         for p in PS:
             region(p, "auto")
 
-    if args.profile == "sort":
-        _profile_sorts(torch, np, meld, workloads, dev)
-        return
-    if args.profile == "pairs":
-        _profile_pairs(torch, np, meld, workloads, dev)
-        return
-    if args.profile == "next":
-        _profile_next(torch, np, meld, workloads, dev)
-        return
-    if args.profile:
-        src = torch.empty(1 << 26, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)  # calibration copy: 256 MiB read + 256 MiB written
-        for _ in range(3):
-            for p in PS:
-                region(p, "melded")
-        for p in PS:
-            region(p, "divergent")
-        for p in PS:
-            region(p, "melded_inplace")
-        torch.cuda.synchronize()
-        print(json.dumps({"profile_run": True, "copy_bytes": 2 * src.numel() * 4}))
-        return
-
-    for _ in range(args.warmup):
+    for _ in range(3):
         step()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ms_events = _events_time(torch, step, args.steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = ms_events
-    value = len(PS) * N_LANES / (ms_per_step * 1e-3) / 1e9
+    step_ms = _events_time(torch, step, 20)
 
-    # Per-kernel times, divergent and melded interleaved.
     per_p = {}
     for p in PS:
         for _ in range(3):
@@ -194,12 +459,15 @@ def main():
             "melded_inplace_us": round(mi * 1e3, 2),
             "speedup_inplace": round(d / mi, 4),
             "mixed_wave_fraction": round(_mixed_fraction(p), 5),
-            "melded_alg_GBs": round(alg_bytes / (m * 1e-3) / 1e9, 1),
-            "divergent_alg_GBs": round(alg_bytes / (d * 1e-3) / 1e9, 1),
+            "melded_gather_GBs": round(alg_bytes / (m * 1e-3) / 1e9, 1),
+            "melded_compulsory_frac": round(REGION_COMPULSORY / (m * 1e-3) / 1e9
+                                            / HBM_PEAK_GBS, 4),
+            "divergent_compulsory_frac": round(REGION_COMPULSORY / (d * 1e-3) / 1e9
+                                               / HBM_PEAK_GBS, 4),
         }
 
-    # Sensitivity: the same region with both sides gathering the same entries
-    # (sides differ only in multiplier and trip count), p = 0.5.
+    # Sensitivity: both sides gathering the same entries (sides differ only in
+    # multiplier and trip count), p = 0.5.
     same = {}
     st_s = dict(st, off=sf["off"], step=sf["step"])
 
@@ -216,8 +484,7 @@ def main():
                   "speedup": round(same["divergent"] / same["melded"], 4),
                   "speedup_inplace": round(same["divergent"] / same["melded_inplace"], 4)}
 
-    # Sensitivity: other trip counts of the workload's range (8..32 per side),
-    # p = 0.5, canonical sides.
+    # Sensitivity: other trip counts of the workload's range (8..32 per side).
     trips_sweep = {}
     for tt, tf in ((8, 8), (8, 32), (32, 8), (20, 20), (32, 32)):
         st_t, sf_t = dict(st, trips=tt), dict(sf, trips=tf)
@@ -240,90 +507,39 @@ def main():
     variants = _bench_region_variants(torch, np, meld, workloads, xd, td, ys[0.5], args)
     seeds = _bench_seeds(torch, np, meld, workloads, dev, args)
 
-    # Roofline of the dominant kernel over the timed region itself: the step is
-    # one melded launch per p, so its average launch takes ms_per_step / 3.
-    alg_step = sum(N_LANES * (8 + 4 * (p * st["trips"] + (1 - p) * sf["trips"])) for p in PS)
-    alg_bytes = alg_step / len(PS)
-    launch_us = ms_per_step * 1e3 / len(PS)
-    achieved = alg_bytes / (launch_us * 1e-6) / 1e9
-
-    # Check the timed outputs of the step once (melded == divergent, bit for bit).
+    # Check the step's outputs once (every form equal, bit for bit).
     for p in PS:
         region(p, "auto")
         a = ys[p].clone()
-        for other in ("divergent", "melded_inplace"):
+        for other in ("divergent", "melded", "melded_inplace"):
             region(p, other)
             if not torch.equal(a.view(torch.int32), ys[p].view(torch.int32)):
-                raise SystemExit(f"melded and {other} region differ at p={p}")
+                raise SystemExit(f"auto and {other} region differ at p={p}")
 
-    sort_info = None
-    if not args.no_sort:
-        sort_info = _bench_sort(torch, np, meld, workloads, dev, args)
-
-    oddeven_info = merge_info = None
-    if not args.no_sort:
-        oddeven_info = _bench_oddeven(torch, np, meld, workloads, dev)
-        merge_info = _bench_mergesort(torch, np, meld, workloads, dev)
-
-    seg_info = None
-    if not args.no_seg:
-        seg_info = _bench_segmented(torch, np, meld, workloads, dev)
-
-    serve_info = None
-    if args.serve_seconds > 0:
-        serve_info = _bench_serving(meld, workloads, args.serve_seconds)
-
-    cpu = None
-    if not args.no_cpu:
-        cpu = _cpu_baseline(np, workloads, x, tab, st, sf, thr)
-
-    out = {
-        "metric": "melded/divergent speedup; Gkeys/s and VALU lane utilisation (rocprof)",
-        "value": round(value, 3),
-        "unit": "Gkeys/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
-        "wall_s_timed": round(wall, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic (seeded SplitMix64 inputs, workloads/)",
-        "config": {
-            "workload": "divergent-region: 2^24 fp32 lanes x p in {0.1,0.5,0.9}, "
-                        "branch bit Bernoulli(p) from hash(seed,i), each side 8-32 fma+gather "
-                        "steps into a 2^24-entry (64 MiB) fp32 table",
-            "key": "one region lane",
-            "lanes_per_step": len(PS) * N_LANES,
-            "trips_true": st["trips"], "trips_false": sf["trips"],
-            "variant": "auto (melded)",
-        },
+    launch_us = step_ms * 1e3 / len(PS)
+    return {
+        "workload": "two-sided loop region: 2^24 fp32 lanes x p in {0.1,0.5,0.9}, branch bit "
+                    "Bernoulli(p) from hash(seed,i), each side 8-32 fma+gather steps into a "
+                    "2^24-entry (64 MiB) fp32 table",
+        "trips_true": st["trips"], "trips_false": sf["trips"],
+        "step_ms": round(step_ms, 4), "G_lanes_s": round(len(PS) * N_LANES / step_ms / 1e6, 2),
+        "roofline": {
+            "bound": "hbm", "kernel": "region_melded_kernel (MELD_AUTO step, one launch per p)",
+            "avg_launch_us": round(launch_us, 2),
+            "achieved": round(REGION_COMPULSORY / (launch_us * 1e-6) / 1e9, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(REGION_COMPULSORY / (launch_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic": _measured_traffic("region_melded_traffic.json"),
+            "alg_bytes_per_launch": int(REGION_COMPULSORY),
+            "note": "compulsory bytes: x read, y written and the 64 MiB table read once "
+                    "(3 x 64 MiB); the gathers re-read table entries from L2 / MALL, so the "
+                    "kernel is bound by the vector-memory address path, not by HBM"},
         "melded_vs_divergent": per_p,
         "same_index_sides": same_index,
         "trips_sweep_p0.5": trips_sweep,
         "region_variants": variants,
         "seeds": seeds,
-        "roofline": {
-            "bound": "hbm", "kernel": "region_melded_kernel (timed step, one launch per p)",
-            "avg_launch_us": round(launch_us, 2),
-            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": _measured_traffic(),
-            "alg_bytes_per_launch": int(alg_bytes),
-            "note": "algorithmic bytes count every table gather (8 + 4 t bytes per lane); "
-                    "the gathers hit in L2/MALL, so frac can exceed 1; traffic is the "
-                    "counter-measured HBM bytes per launch",
-        },
-        "sort": sort_info,
-        "oddeven_buckets": oddeven_info,
-        "mergesort": merge_info,
-        "segmented": seg_info,
-        "serving": serve_info,
-        "cpu_baseline": cpu,
     }
-    print(json.dumps(out))
 
 
 def _bench_seeds(torch, np, meld, workloads, dev, args):
@@ -446,46 +662,14 @@ def _bench_mergesort(torch, np, meld, workloads, dev):
     return res
 
 
-def _bench_sort(torch, np, meld, workloads, dev, args):
-    res = {}
-    # 2^28 (key, payload = index) pairs.
-    n = 1 << 28
-    keys = workloads.keys_u32(SEED, n)
-    kin = torch.from_numpy(keys.view(np.int32)).to(dev)
-    del keys
-    pin = torch.arange(n, dtype=torch.int32, device=dev)
-    k = torch.empty_like(kin)
-    p = torch.empty_like(pin)
-    times = {"divergent": [], "melded": []}
-    for rep in range(4):
-        for v in ("divergent", "melded"):
-            k.copy_(kin)
-            p.copy_(pin)
-            s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            s.record()
-            meld.sort(k, p, variant=v)
-            e.record()
-            e.synchronize()
-            if rep > 0:
-                times[v].append(s.elapsed_time(e))
-    d, m = float(np.median(times["divergent"])), float(np.median(times["melded"]))
-    plan = meld.sort_plan(n, pairs=True, variant="melded", device=0)
-    passes = plan["hbm_passes"]
-    moved = 16.0 * n * passes  # 8 B read + 8 B written per pair and pass
-    res["pairs_2^28"] = {"divergent_ms": round(d, 3), "melded_ms": round(m, 3),
-                         "speedup": round(d / m, 4),
-                         "melded_Gkeys_s": round(n / (m * 1e-3) / 1e9, 3),
-                         "log_tile": plan["log_tile"], "hbm_passes": passes,
-                         "melded_hbm_GBs": round(moved / (m * 1e-3) / 1e9, 1),
-                         "hbm_frac": round(moved / (m * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-    del kin, pin, k, p
-    torch.cuda.empty_cache()
-    # 2^16 keys.
+def _bench_sort16(torch, np, meld, workloads, dev, args):
+    """2^16 keys (seed 1): divergent vs melded end to end, interleaved, and the
+    local-sort launch alone."""
     n = 1 << 16
     kin = torch.from_numpy(workloads.keys_u32(SEED, n).view(np.int32)).to(dev)
     k = torch.empty_like(kin)
     times = {"divergent": [], "melded": []}
-    for rep in range(21):
+    for rep in range(41):
         for v in ("divergent", "melded"):
             k.copy_(kin)
             s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -502,22 +686,21 @@ def _bench_sort(torch, np, meld, workloads, dev, args):
     local = plan["passes"][0]["steps"]
     tl = {v: _time_sorts(torch, np, lambda v=v: meld.sort_steps(k, None, local, variant=v),
                          lambda: k.copy_(kin), 21) for v in ("divergent", "melded")}
-    res["keys_2^16"] = {"divergent_us": round(d * 1e3, 2), "melded_us": round(m * 1e3, 2),
-                        "speedup": round(d / m, 4),
-                        "melded_Gkeys_s": round(n / (m * 1e-3) / 1e9, 3),
-                        "divergent_us_dist": _dist(np, times["divergent"]),
-                        "melded_us_dist": _dist(np, times["melded"]),
-                        "log_tile": plan["log_tile"], "hbm_passes": plan["hbm_passes"],
-                        "hbm_frac": round(8.0 * n * plan["hbm_passes"] / (m * 1e-3) / 1e9
-                                          / HBM_PEAK_GBS, 5),
-                        "hbm_frac_note": "not meaningful: 256 KiB per pass, the sort is bound "
-                                         "by launch and per-tile latency",
-                        "local_sort_kernel": {
-                            "steps": local,
-                            "divergent_us": round(tl["divergent"] * 1e3, 2),
-                            "melded_us": round(tl["melded"] * 1e3, 2),
-                            "speedup": round(tl["divergent"] / tl["melded"], 4)}}
-    return res
+    return {"divergent_us": round(d * 1e3, 2), "melded_us": round(m * 1e3, 2),
+            "speedup": round(d / m, 4),
+            "melded_Gkeys_s": round(n / (m * 1e-3) / 1e9, 3),
+            "divergent_us_dist": _dist(np, times["divergent"]),
+            "melded_us_dist": _dist(np, times["melded"]),
+            "log_tile": plan["log_tile"], "hbm_passes": plan["hbm_passes"],
+            "hbm_frac": round(8.0 * n * plan["hbm_passes"] / (m * 1e-3) / 1e9
+                              / HBM_PEAK_GBS, 5),
+            "hbm_frac_note": "not meaningful: 256 KiB per pass, the sort is bound "
+                             "by launch and per-tile latency",
+            "local_sort_kernel": {
+                "steps": local,
+                "divergent_us": round(tl["divergent"] * 1e3, 2),
+                "melded_us": round(tl["melded"] * 1e3, 2),
+                "speedup": round(tl["divergent"] / tl["melded"], 4)}}
 
 
 def _profile_sorts(torch, np, meld, workloads, dev):
@@ -536,17 +719,20 @@ def _profile_sorts(torch, np, meld, workloads, dev):
 
 
 def _profile_pairs(torch, np, meld, workloads, dev):
-    """One 2^28-pair sort per form."""
-    n = 1 << 28
-    kin = torch.from_numpy(workloads.keys_u32(SEED, n).view(np.int32)).to(dev)
-    pin = torch.arange(n, dtype=torch.int32, device=dev)
+    """A 256 MiB copy (calibration of the byte counters), one 2^28-pair sort per
+    form, then three MELD_AUTO sorts (the bench's step)."""
+    n = N_PAIRS
+    kin, pin = _pairs_inputs(torch, np, workloads, dev, SEED, n)
     k, p = torch.empty_like(kin), torch.empty_like(pin)
-    for v in ("divergent", "melded"):
+    src = torch.empty(1 << 26, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)  # calibration copy: 256 MiB read + 256 MiB written
+    for v in ("divergent", "melded", "auto", "auto", "auto"):
         k.copy_(kin)
         p.copy_(pin)
         meld.sort(k, p, variant=v)
     torch.cuda.synchronize()
-    print(json.dumps({"profile_run": "pairs"}))
+    print(json.dumps({"profile_run": "pairs", "copy_bytes": 2 * src.numel() * 4}))
 
 
 def _profile_next(torch, np, meld, workloads, dev):
@@ -576,36 +762,60 @@ def _time_sorts(torch, np, run, restore, reps):
     return float(np.median(ts))
 
 
-def _bench_segmented(torch, np, meld, workloads, dev):
-    """4096 segments, lengths log-uniform in [2^6, 2^16]: one graph replay per sort."""
-    off = workloads.segment_offsets(SEED, 4096)
-    n = int(off[-1])
-    od = torch.from_numpy(off.view(np.int32)).to(dev)
-    pristine = torch.from_numpy(workloads.keys_u32(SEED, n).view(np.int32)).to(dev)
-    work = torch.empty_like(pristine)
+def _bench_segmented(torch, np, meld, workloads, dev, args):
+    """4096 segments, lengths log-uniform in [2^6, 2^16]: one graph replay per sort;
+    per-stage forms on seed 1, MELD_AUTO and both forms on seeds 1..3 with at least
+    ~1 s of sorts per seed and form."""
+    out = {"segments": 4096}
     forms = {"divergent": ("divergent", "divergent"), "melded": ("melded", "melded"),
-             "melded_low_only": ("melded", "divergent"), "melded_high_only": ("divergent", "melded")}
-    out = {"segments": 4096, "keys": n}
-    for name, (lo, hi) in forms.items():
-        ms = _time_sorts(torch, np, lambda: meld.segmented_sort(work, od, low=lo, high=hi),
-                         lambda: work.copy_(pristine), 7)
-        out[name + "_ms"] = round(ms, 4)
-    work.copy_(pristine)
-    meld.segmented_sort(work, od, variant="auto")  # tunes this shape class once
-    ms = _time_sorts(torch, np, lambda: meld.segmented_sort(work, od, variant="auto"),
-                     lambda: work.copy_(pristine), 7)
-    out["auto_ms"] = round(ms, 4)
-    out["auto_Gkeys_s"] = round(n / (ms * 1e-3) / 1e9, 3)
-    out["speedup_melded"] = round(out["divergent_ms"] / out["melded_ms"], 4)
-    (ml, al), (mh, ah) = meld.probe_segments(od)
-    out["mixed_fraction_low_phases"] = round(ml / al, 4) if al else 0.0
-    out["mixed_fraction_high_phases"] = round(mh / ah, 4) if ah else 0.0
-    out["low_phase_share_of_work"] = round(al / (al + ah), 4)
+             "melded_low_only": ("melded", "divergent"),
+             "melded_high_only": ("divergent", "melded")}
+    seeds = {}
+    for seed in (1, 2, 3):
+        off = workloads.segment_offsets(seed, 4096)
+        n = int(off[-1])
+        od = torch.from_numpy(off.view(np.int32)).to(dev)
+        pristine = torch.from_numpy(workloads.keys_u32(seed, n).view(np.int32)).to(dev)
+        work = torch.empty_like(pristine)
+        names = forms if seed == SEED else {k: forms[k] for k in ("divergent", "melded")}
+        t = {name: [] for name in names}
+        for rep in range(args.seg_reps + 1):
+            for name, (lo, hi) in names.items():
+                work.copy_(pristine)
+                s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                s.record()
+                meld.segmented_sort(work, od, low=lo, high=hi)
+                e.record()
+                e.synchronize()
+                if rep > 0:
+                    t[name].append(s.elapsed_time(e))
+        work.copy_(pristine)
+        meld.segmented_sort(work, od, variant="auto")  # tunes this shape class once
+        ms_auto = _time_sorts(torch, np, lambda: meld.segmented_sort(work, od, variant="auto"),
+                              lambda: work.copy_(pristine), 11)
+        rec = {"keys": n, "auto_ms": round(ms_auto, 4),
+               "auto_Gkeys_s": round(n / (ms_auto * 1e-3) / 1e9, 3)}
+        for name in names:
+            rec[name + "_ms"] = _dist(np, t[name], scale=1.0)
+        rec["speedup_melded"] = round(rec["divergent_ms"]["median"] / rec["melded_ms"]["median"],
+                                      4)
+        seeds[f"seed_{seed}"] = rec
+        if seed == SEED:
+            (ml, al), (mh, ah) = meld.probe_segments(od)
+            out["mixed_fraction_low_phases"] = round(ml / al, 4) if al else 0.0
+            out["mixed_fraction_high_phases"] = round(mh / ah, 4) if ah else 0.0
+            out["low_phase_share_of_work"] = round(al / (al + ah), 4)
+        meld.segmented_sort_check(0)
+        del od, pristine, work
+    out.update(seeds)
+    out["median_speedup_melded"] = round(float(np.median(
+        [seeds[f"seed_{s}"]["speedup_melded"] for s in (1, 2, 3)])), 4)
     for e in json.loads(meld.plan_describe())["entries"]:
         if e["op"] == "segsort":
-            out["tuned_plan"] = {"low": "melded" if e["lo"] else "divergent",
-                                 "high": "melded" if e["hi"] else "divergent"}
-    meld.segmented_sort_check(0)
+            out.setdefault("tuned_plans", {})[e["key"]] = {
+                "low": "melded" if e["lo"] else "divergent",
+                "high": "melded" if e["hi"] else "divergent"}
+    torch.cuda.empty_cache()
     return out
 
 
@@ -630,44 +840,118 @@ def _bench_serving(meld, workloads, seconds):
             "max_inflight_MB": round(st["max_inflight_bytes"] / 1e6, 1), "budget_GB": 8.6}
 
 
-def _cpu_baseline(np, workloads, x, tab, st, sf, thr):
-    """The CPU oracle on this host: whole steps (3 x 2^24 lanes), lanes split over
-    threads, repeated for at least 1 s of wall time; then one thread on a
-    2^22-lane slice of each p."""
+def _timed_repeat(fn, min_s):
+    """Runs fn() until at least min_s seconds have passed (at least once);
+    returns (runs, seconds)."""
+    runs, t0 = 0, time.perf_counter()
+    while runs == 0 or time.perf_counter() - t0 < min_s:
+        fn()
+        runs += 1
+    return runs, time.perf_counter() - t0
+
+
+def _cpu_baseline_pairs(np, workloads):
+    """The CPU oracle's (key, payload) sort on this host: all the threads it may use
+    (chunk sorts + pairwise merges) on 2^27 pairs, and one thread on 2^24 pairs;
+    keys from seed 1, payload = index, like the GPU step."""
     import oracle
 
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads = _oracle_threads()
+    n_all, n_one = 1 << 27, 1 << 24
+    k = workloads.keys_u32(SEED, n_all)
+    v = workloads.iota_u32(n_all)
+    t0 = time.perf_counter()
+    oracle.sort_pairs_u32_threads(k, v, threads)
+    dt_all = time.perf_counter() - t0
+    k1, v1 = workloads.keys_u32(SEED, n_one), workloads.iota_u32(n_one)
+    t1 = time.perf_counter()
+    oracle.sort_pairs_u32(k1, v1)
+    dt_one = time.perf_counter() - t1
+    info = _cpu_info()
+    return {"value": round(n_all / dt_all / 1e9, 4), "unit": "Gkeys/s", "cores": threads,
+            "kind": "oracle",
+            "one_thread_value": round(n_one / dt_one / 1e9, 4),
+            "sample": f"oracle sort of 2^27 (key, payload = index) pairs, keys from seed 1, on "
+                      f"{threads} host threads (chunk std::sort + pairwise std::merge): "
+                      f"{dt_all:.2f} s wall; one_thread_value: oracle_sort_pairs_u32 of 2^24 "
+                      f"pairs on one thread, {dt_one:.2f} s",
+            "threads_note": "at most 16 threads: the host share of one GPU on this machine",
+            **info}
+
+
+def _cpu_sort_keys(np, workloads, n):
+    """The oracle's keys sort of the 2^16-key input, one thread, repeated >= 1 s."""
+    import oracle
+    keys = workloads.keys_u32(SEED, n)
+    runs, dt = _timed_repeat(lambda: oracle.sort_u32(keys), 1.0)
+    return {"one_thread_Gkeys_s": round(runs * n / dt / 1e9, 4), "runs": runs,
+            "sample": f"oracle_sort_u32 of the same 2^16 keys, {runs} runs, {dt:.2f} s"}
+
+
+def _cpu_segmented(np, workloads):
+    """The oracle's segmented sort of the 4096-segment input (seed 1): one thread,
+    and the segments split over the threads it may use."""
+    import oracle
+    off = workloads.segment_offsets(SEED, 4096)
+    n = int(off[-1])
+    keys = workloads.keys_u32(SEED, n)
+    t1 = time.perf_counter()
+    oracle.segmented_sort_u32(keys, off)
+    dt_one = time.perf_counter() - t1
+    threads = _oracle_threads()
+    cuts = np.linspace(0, 4096, threads + 1).astype(np.int64)
+
+    def part(i):
+        a, b = cuts[i], cuts[i + 1]
+        lo, hi = int(off[a]), int(off[b])
+        oracle.segmented_sort_u32(keys[lo:hi], (off[a:b + 1] - off[a]).astype(np.uint32))
+
+    ts = [threading.Thread(target=part, args=(i,)) for i in range(threads)]
+    t0 = time.perf_counter()
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    dt_all = time.perf_counter() - t0
+    return {"Gkeys_s": round(n / dt_all / 1e9, 4), "cores": threads,
+            "one_thread_Gkeys_s": round(n / dt_one / 1e9, 4),
+            "sample": f"oracle_segmented_sort_u32 of the 4096 segments ({n} keys): one "
+                      f"thread {dt_one:.2f} s; segments split over {threads} threads "
+                      f"{dt_all:.2f} s"}
+
+
+def _cpu_region(np, workloads):
+    """The oracle's region over 2^24 lanes at p in {0.1, 0.5, 0.9}: lanes split over
+    the threads it may use (one step), and one thread on 2^22 lanes per p."""
+    import oracle
+
+    x, tab, st, sf = workloads.region_inputs(SEED, N_LANES)
+    thr = {p: workloads.thr_from_p(p) for p in PS}
+    threads = _oracle_threads()
     y = np.empty_like(x)
     chunk = (N_LANES + threads - 1) // threads
 
     def work(p, lo, hi):
         oracle.region_f32_into(x[lo:hi], y[lo:hi], tab, SEED, thr[p], st, sf, lo)
 
-    steps = 0
     t0 = time.perf_counter()
-    while steps < 3 or time.perf_counter() - t0 < 1.0:
-        for p in PS:
-            ts = [threading.Thread(target=work,
-                                   args=(p, i * chunk, min(N_LANES, (i + 1) * chunk)))
-                  for i in range(threads)]
-            for t in ts:
-                t.start()
-            for t in ts:
-                t.join()
-        steps += 1
+    for p in PS:
+        ts = [threading.Thread(target=work, args=(p, i * chunk, min(N_LANES, (i + 1) * chunk)))
+              for i in range(threads)]
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join()
     dt = time.perf_counter() - t0
     one = 1 << 22
     t1 = time.perf_counter()
     for p in PS:
         work(p, 0, one)
     dt1 = time.perf_counter() - t1
-    return {"value": round(steps * len(PS) * N_LANES / dt / 1e9, 4), "unit": "Gkeys/s",
-            "cores": threads, "kind": "oracle",
-            "one_thread_value": round(len(PS) * one / dt1 / 1e9, 4),
-            "sample": f"{steps} full steps (3 x 2^24 lanes each, p in {{0.1,0.5,0.9}}), lanes "
-                      f"split over {threads} host threads, {dt:.2f} s wall "
-                      f"(~{dt * threads:.0f} s of CPU work); one_thread_value: one thread over "
-                      f"2^22 lanes per p, {dt1:.2f} s"}
+    return {"G_lanes_s": round(len(PS) * N_LANES / dt / 1e9, 4), "cores": threads,
+            "one_thread_G_lanes_s": round(len(PS) * one / dt1 / 1e9, 4),
+            "sample": f"one step (3 x 2^24 lanes) split over {threads} threads, {dt:.2f} s; "
+                      f"one thread over 2^22 lanes per p, {dt1:.2f} s"}
 
 
 if __name__ == "__main__":

@@ -32,7 +32,12 @@
  *   - Argument errors are detected before anything is enqueued and return
  *     MELD_EINVAL with a message in meld_last_error(); the arrays are then
  *     untouched. A failed launch returns MELD_EHIP.
- *   - Calls on one context must not overlap from several host threads.
+ *   - A context's scratch (sort tail, segmented-sort queues, merge and tuning
+ *     buffers) is shared by every call on it. Calls on one context must not
+ *     overlap from several host threads, and must all be enqueued on one
+ *     stream (or on streams ordered by events): two calls on one context on
+ *     streams that run concurrently race on that scratch. Use one context per
+ *     stream.
  *   - The library never calls exit() or abort().
  */
 #ifndef MELD_H
@@ -113,6 +118,20 @@ const char *meld_last_error(void);
  */
 meld_status meld_sort_u32(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n,
                           meld_variant variant, void *stream);
+
+/* meld_sort_u32 with the duration of every launch: a HIP event is recorded
+ * on `stream` before the first launch and after each one, the call waits for
+ * the last, and launch_ms[i] receives the time between events i and i+1 in
+ * milliseconds (launch i of the plan meld_sort_plan_describe lists; for a
+ * non-power-of-two n the first also holds the fill of the padding). Used to
+ * measure each kernel against its roofline. Synchronous.
+ * launch_ms: host float[cap]; *n_launches receives the number of launches
+ * (0 for n <= 1).
+ * Errors: as meld_sort_u32, plus MELD_EINVAL for NULL launch_ms or
+ * n_launches and for cap below the number of launches. */
+meld_status meld_sort_u32_timed(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n,
+                                meld_variant variant, void *stream, float *launch_ms,
+                                size_t cap, size_t *n_launches);
 
 /* Runs only the first max_steps (k, j) steps of the same network (all of
  * them when max_steps < 0), in the same order, for stage-by-stage checks and

@@ -38,7 +38,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(
-            ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
+            ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-pthread", "-ffp-contract=off",
              _SRC, "-o", tmp])
         os.replace(tmp, _LIB)
     return _LIB
@@ -58,6 +58,8 @@ def _load():
         lib.oracle_branch_hash.restype = u64
         lib.oracle_sort_u32.argtypes = [vp, sz]
         lib.oracle_sort_u32.restype = None
+        lib.oracle_sort_pairs_u32_threads.argtypes = [vp, vp, sz, ctypes.c_uint]
+        lib.oracle_sort_pairs_u32_threads.restype = ctypes.c_int
         lib.oracle_sort_pairs_u32.argtypes = [vp, vp, sz]
         lib.oracle_sort_pairs_u32.restype = None
         lib.oracle_segmented_sort_u32.argtypes = [vp, vp, sz]
@@ -114,6 +116,17 @@ def sort_pairs_u32(keys, vals):
     if k.shape != v.shape:
         raise ValueError("keys and vals differ in length")
     _load().oracle_sort_pairs_u32(k.ctypes.data, v.ctypes.data, k.size)
+    return k, v
+
+
+def sort_pairs_u32_threads(keys, vals, threads: int):
+    """sort_pairs_u32 on ``threads`` host threads (chunk sorts + pairwise merges)."""
+    k, v = _u32(keys), _u32(vals)
+    if k.shape != v.shape:
+        raise ValueError("keys and vals differ in length")
+    if _load().oracle_sort_pairs_u32_threads(k.ctypes.data, v.ctypes.data, k.size,
+                                             int(threads)) != 0:
+        raise ValueError("threads must be positive")
     return k, v
 
 

@@ -8,6 +8,9 @@
  *    reaches exactly. Pairs use the lexicographic (key, payload) order so
  *    that exactly one output is correct. Segments follow the BIT benchmark's
  *    per-bucket sort (Evaluation section, "Bitonic Sort (BIT)").
+ *    oracle_sort_pairs_u32_threads computes the same order on several host
+ *    threads (chunk sorts, then pairwise merges): it exists to time the
+ *    oracle on all host cores.
  *  - oracle_bitonic_emulate: the Figure 1 network itself, executed one
  *    (k, j) step at a time on a power-of-two array: for each thread index
  *    t with partner p = t xor j and p > t, keep ascending order when
@@ -38,6 +41,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <thread>
 #include <vector>
 
 namespace {
@@ -102,6 +106,50 @@ void oracle_sort_pairs_u32(uint32_t *keys, uint32_t *vals, size_t n) {
         keys[i] = (uint32_t)(tmp[i] >> 32);
         vals[i] = (uint32_t)tmp[i];
     }
+}
+
+int oracle_sort_pairs_u32_threads(uint32_t *keys, uint32_t *vals, size_t n, unsigned threads) {
+    if (threads == 0) return -1;
+    // Runs fn(0 .. parts-1), one host thread each.
+    auto parallel = [](size_t parts, const auto &fn) {
+        std::vector<std::thread> ts;
+        for (size_t p = 0; p < parts; ++p) ts.emplace_back(fn, p);
+        for (auto &t : ts) t.join();
+    };
+    const size_t chunks = std::max<size_t>(1, std::min<size_t>(threads, n));
+    std::vector<uint64_t> a(n), b(n);
+    std::vector<size_t> bounds(chunks + 1);
+    for (size_t c = 0; c <= chunks; ++c) bounds[c] = n * c / chunks;
+    // each chunk sorted on its own thread
+    parallel(chunks, [&](size_t c) {
+        for (size_t i = bounds[c]; i < bounds[c + 1]; ++i) a[i] = composite(keys[i], vals[i]);
+        std::sort(a.begin() + bounds[c], a.begin() + bounds[c + 1]);
+    });
+    // sorted runs merged two at a time, the merges of a round in parallel
+    while (bounds.size() > 2) {
+        const size_t runs = bounds.size() - 1;
+        std::vector<size_t> next;
+        for (size_t r = 0; r < runs; r += 2) next.push_back(bounds[r]);
+        next.push_back(n);
+        parallel((runs + 1) / 2, [&](size_t q) {
+            const size_t r = 2 * q;
+            if (r + 1 < runs)
+                std::merge(a.begin() + bounds[r], a.begin() + bounds[r + 1],
+                           a.begin() + bounds[r + 1], a.begin() + bounds[r + 2],
+                           b.begin() + bounds[r]);
+            else
+                std::copy(a.begin() + bounds[r], a.begin() + bounds[r + 1], b.begin() + bounds[r]);
+        });
+        std::swap(a, b);
+        bounds.swap(next);
+    }
+    parallel(chunks, [&](size_t c) {
+        for (size_t i = n * c / chunks; i < n * (c + 1) / chunks; ++i) {
+            keys[i] = (uint32_t)(a[i] >> 32);
+            vals[i] = (uint32_t)a[i];
+        }
+    });
+    return 0;
 }
 
 int oracle_segmented_sort_u32(uint32_t *keys, const uint32_t *offsets, size_t nseg) {

@@ -33,6 +33,9 @@ uint64_t oracle_branch_hash(uint64_t seed, uint64_t i);
 
 void oracle_sort_u32(uint32_t *keys, size_t n);
 void oracle_sort_pairs_u32(uint32_t *keys, uint32_t *vals, size_t n);
+/* oracle_sort_pairs_u32's result on `threads` host threads: contiguous chunks
+ * sorted one per thread, then merged two at a time. -1 for threads == 0. */
+int oracle_sort_pairs_u32_threads(uint32_t *keys, uint32_t *vals, size_t n, unsigned threads);
 int oracle_segmented_sort_u32(uint32_t *keys, const uint32_t *offsets, size_t nseg);
 
 uint64_t oracle_bitonic_num_steps(size_t n_pow2);

@@ -37,7 +37,8 @@ EXPORTS = ("meld_version", "meld_create", "meld_destroy", "meld_last_error", "me
            "meld_server_drain", "meld_server_stats_get", "meld_server_last_error",
            "meld_server_destroy",
            "meld_divergent_region_f32", "meld_region3_f32", "meld_region_lanetrips_f32",
-           "meld_oddeven_sort_buckets_u32", "meld_merge_sort_u32", "meld_sort_plan_describe")
+           "meld_oddeven_sort_buckets_u32", "meld_merge_sort_u32", "meld_sort_plan_describe",
+           "meld_sort_u32_timed")
 
 
 class MeldError(RuntimeError):
@@ -58,7 +59,11 @@ class SideRange(ctypes.Structure):
 
 _lib = None
 _lock = threading.Lock()
-_ctxs: dict[int, ctypes.c_void_p] = {}
+# One library context per (device, stream): a context's scratch (sort tail,
+# segmented-sort queues, merge and tuning buffers) is shared by every call on
+# it, so calls on streams that may run concurrently must not share one.
+_ctxs: dict[tuple[int, int], ctypes.c_void_p] = {}
+_options: dict[int, dict[int, int]] = {}  # device -> option -> value, for every context
 
 
 def load_library():
@@ -82,6 +87,9 @@ def load_library():
     lib.meld_last_error.argtypes = []
     lib.meld_sort_u32.restype = st
     lib.meld_sort_u32.argtypes = [vp, vp, vp, sz, st, vp]
+    lib.meld_sort_u32_timed.restype = st
+    lib.meld_sort_u32_timed.argtypes = [vp, vp, vp, sz, st, vp, ctypes.POINTER(ctypes.c_float),
+                                        sz, ctypes.POINTER(sz)]
     lib.meld_sort_u32_steps.restype = st
     lib.meld_sort_u32_steps.argtypes = [vp, vp, vp, sz, i64, st, vp]
     lib.meld_segmented_sort_u32.restype = st
@@ -130,15 +138,39 @@ def _check(status: int) -> None:
         raise MeldError(status, msg)
 
 
-def context(device: int):
-    """The library context of HIP device ``device`` (created on first use)."""
+def _stream_handle(device: int, stream) -> int:
+    """hipStream_t of ``stream`` (a torch stream, a raw handle, or None for the
+    current torch stream of ``device``) as an integer."""
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream(device)
+    return int(stream.cuda_stream if hasattr(stream, "cuda_stream") else stream)
+
+
+def new_context(device: int):
+    """A fresh library context on ``device``, owned by the caller (free it with
+    ``destroy_context``); the functions below take it as ``ctx=``."""
+    lib = load_library()
+    ctx = ctypes.c_void_p()
+    _check(lib.meld_create(device, ctypes.byref(ctx)))
+    for opt, val in _options.get(device, {}).items():
+        _check(lib.meld_set_option(ctx, opt, val))
+    return ctx
+
+
+def destroy_context(ctx) -> None:
+    load_library().meld_destroy(ctx)
+
+
+def context(device: int, stream=None):
+    """The library context of (``device``, ``stream``), created on first use; stream
+    None is the current torch stream of the device."""
+    key = (device, _stream_handle(device, stream))
     with _lock:
-        ctx = _ctxs.get(device)
+        ctx = _ctxs.get(key)
         if ctx is None:
-            lib = load_library()
-            ctx = ctypes.c_void_p()
-            _check(lib.meld_create(device, ctypes.byref(ctx)))
-            _ctxs[device] = ctx
+            ctx = new_context(device)
+            _ctxs[key] = ctx
         return ctx
 
 
@@ -149,11 +181,12 @@ def _variant(v) -> int:
         raise ValueError(f"unknown variant {v!r}") from None
 
 
-def _stream_of(t, stream):
-    import torch
-    if stream is None:
-        stream = torch.cuda.current_stream(t.device)
-    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+def _launch_args(t, stream, ctx):
+    """(context, stream) of a call on tensor t's device: ctx if given, else the
+    context of (device, stream)."""
+    dev = t.device.index
+    h = _stream_handle(dev, stream)
+    return (ctx if ctx is not None else context(dev, h)), ctypes.c_void_p(h)
 
 
 def _u32_tensor(t, name):
@@ -165,34 +198,54 @@ def _u32_tensor(t, name):
     return t
 
 
-def sort(keys, payload=None, variant=AUTO, stream=None):
+def sort(keys, payload=None, variant=AUTO, stream=None, ctx=None):
     """In-place ascending bitonic sort of ``keys`` (u32 bits), moving ``payload`` along."""
     _u32_tensor(keys, "keys")
     if payload is not None:
         _u32_tensor(payload, "payload")
         if payload.numel() != keys.numel() or payload.device != keys.device:
             raise ValueError("payload must match keys in length and device")
-    lib = load_library()
-    _check(lib.meld_sort_u32(context(keys.device.index), ctypes.c_void_p(keys.data_ptr()),
-                             None if payload is None else ctypes.c_void_p(payload.data_ptr()),
-                             keys.numel(), _variant(variant), _stream_of(keys, stream)))
+    c, s = _launch_args(keys, stream, ctx)
+    _check(load_library().meld_sort_u32(
+        c, ctypes.c_void_p(keys.data_ptr()),
+        None if payload is None else ctypes.c_void_p(payload.data_ptr()), keys.numel(),
+        _variant(variant), s))
     return keys if payload is None else (keys, payload)
 
 
-def sort_steps(keys, payload=None, max_steps=-1, variant=AUTO, stream=None):
+def sort_timed(keys, payload=None, variant=AUTO, stream=None, ctx=None) -> list[float]:
+    """``sort`` with the duration in ms of each of its launches (HIP events on the
+    launch stream, see meld_sort_u32_timed); waits for the sort."""
+    _u32_tensor(keys, "keys")
+    if payload is not None:
+        _u32_tensor(payload, "payload")
+        if payload.numel() != keys.numel() or payload.device != keys.device:
+            raise ValueError("payload must match keys in length and device")
+    c, s = _launch_args(keys, stream, ctx)
+    cap = 1024
+    out = (ctypes.c_float * cap)()
+    n_out = ctypes.c_size_t(0)
+    _check(load_library().meld_sort_u32_timed(
+        c, ctypes.c_void_p(keys.data_ptr()),
+        None if payload is None else ctypes.c_void_p(payload.data_ptr()), keys.numel(),
+        _variant(variant), s, out, cap, ctypes.byref(n_out)))
+    return [float(out[i]) for i in range(n_out.value)]
+
+
+def sort_steps(keys, payload=None, max_steps=-1, variant=AUTO, stream=None, ctx=None):
     """The first ``max_steps`` steps of the sorting network (power-of-two length)."""
     _u32_tensor(keys, "keys")
     if payload is not None:
         _u32_tensor(payload, "payload")
-    lib = load_library()
-    _check(lib.meld_sort_u32_steps(context(keys.device.index), ctypes.c_void_p(keys.data_ptr()),
-                                   None if payload is None else ctypes.c_void_p(payload.data_ptr()),
-                                   keys.numel(), int(max_steps), _variant(variant),
-                                   _stream_of(keys, stream)))
+    c, s = _launch_args(keys, stream, ctx)
+    _check(load_library().meld_sort_u32_steps(
+        c, ctypes.c_void_p(keys.data_ptr()),
+        None if payload is None else ctypes.c_void_p(payload.data_ptr()), keys.numel(),
+        int(max_steps), _variant(variant), s))
     return keys if payload is None else (keys, payload)
 
 
-def segmented_sort(keys, offsets, variant=AUTO, stream=None, low=None, high=None):
+def segmented_sort(keys, offsets, variant=AUTO, stream=None, low=None, high=None, ctx=None):
     """Sorts every segment keys[offsets[s]:offsets[s+1]] in place.
 
     ``low`` / ``high`` pick the form per stage (phases k <= 64 / k >= 128);
@@ -205,23 +258,24 @@ def segmented_sort(keys, offsets, variant=AUTO, stream=None, low=None, high=None
     if keys.numel() == 0 or nseg == 0:
         return keys
     lib = load_library()
-    args = (context(keys.device.index), ctypes.c_void_p(keys.data_ptr()), keys.numel(),
+    c, s = _launch_args(keys, stream, ctx)
+    args = (c, ctypes.c_void_p(keys.data_ptr()), keys.numel(),
             ctypes.c_void_p(offsets.data_ptr()), nseg)
     if low is None and high is None:
-        _check(lib.meld_segmented_sort_u32(*args, _variant(variant), _stream_of(keys, stream)))
+        _check(lib.meld_segmented_sort_u32(*args, _variant(variant), s))
     else:
         lo = _variant(variant if low is None else low)
         hi = _variant(variant if high is None else high)
-        _check(lib.meld_segmented_sort_u32_staged(*args, lo, hi, _stream_of(keys, stream)))
+        _check(lib.meld_segmented_sort_u32_staged(*args, lo, hi, s))
     return keys
 
 
-def segmented_sort_check(device: int = 0, stream=None):
-    """Raises MeldError if a segmented sort on ``device`` met invalid offsets."""
-    import torch
-    lib = load_library()
-    s = stream if stream is not None else torch.cuda.current_stream(device)
-    _check(lib.meld_segmented_sort_check(context(device), ctypes.c_void_p(s.cuda_stream)))
+def segmented_sort_check(device: int = 0, stream=None, ctx=None):
+    """Raises MeldError if a segmented sort on the context of (``device``, ``stream``)
+    (or on ``ctx``) met invalid offsets."""
+    h = _stream_handle(device, stream)
+    c = ctx if ctx is not None else context(device, h)
+    _check(load_library().meld_segmented_sort_check(c, ctypes.c_void_p(h)))
 
 
 OPT_USE_GRAPHS = 0
@@ -229,8 +283,16 @@ OPT_SORT_LOG_TILE = 1
 
 
 def set_option(device: int, option: int, value: int) -> None:
-    """Sets a context option (see meld_set_option)."""
-    _check(load_library().meld_set_option(context(device), int(option), int(value)))
+    """Sets a context option (see meld_set_option) on every context of ``device``,
+    present and future."""
+    lib = load_library()
+    with _lock:
+        current = [c for (d, _), c in _ctxs.items() if d == device]
+    if not current:
+        current = [context(device)]
+    for c in current:
+        _check(lib.meld_set_option(c, int(option), int(value)))
+    _options.setdefault(device, {})[int(option)] = int(value)
 
 
 def side(a: float, off: int, step: int, trips: int) -> Side:
@@ -243,42 +305,6 @@ def _as_side(s) -> Side:
     return side(s["a"], s["off"], s["step"], s["trips"])
 
 
-def divergent_region(x, tab, seed: int, thr: int, side_true, side_false, variant=AUTO,
-                     out=None, stream=None):
-    """Two-sided loop region over the lanes of ``x`` (see meld_divergent_region_f32)."""
-    import torch
-    for t, name in ((x, "x"), (tab, "tab")):
-        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 \
-                or not t.is_contiguous():
-            raise TypeError(f"{name} must be a contiguous float32 CUDA tensor")
-    if out is None:
-        out = torch.empty_like(x)
-    lib = load_library()
-    _check(lib.meld_divergent_region_f32(
-        context(x.device.index), ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
-        x.numel(), ctypes.c_void_p(tab.data_ptr()), tab.numel(), int(seed), int(thr),
-        _as_side(side_true), _as_side(side_false), _variant(variant), _stream_of(x, stream)))
-    return out
-
-
-def oddeven_sort_buckets(keys, log_bucket: int, max_steps: int = -1, variant=AUTO,
-                         stream=None):
-    """Sorts each bucket of 2^log_bucket keys in place with Batcher's odd-even merge
-    network (see meld_oddeven_sort_buckets_u32)."""
-    _u32_tensor(keys, "keys")
-    _check(load_library().meld_oddeven_sort_buckets_u32(
-        context(keys.device.index), ctypes.c_void_p(keys.data_ptr()), keys.numel(),
-        int(log_bucket), int(max_steps), _variant(variant), _stream_of(keys, stream)))
-
-
-def merge_sort(keys, max_passes: int = -1, variant=AUTO, stream=None):
-    """Ascending bottom-up merge sort of ``keys`` in place (see meld_merge_sort_u32)."""
-    _u32_tensor(keys, "keys")
-    _check(load_library().meld_merge_sort_u32(
-        context(keys.device.index), ctypes.c_void_p(keys.data_ptr()), keys.numel(),
-        int(max_passes), _variant(variant), _stream_of(keys, stream)))
-
-
 def _region_tensors(x, tab, out):
     import torch
     for t, name in ((x, "x"), (tab, "tab")):
@@ -288,15 +314,47 @@ def _region_tensors(x, tab, out):
     return torch.empty_like(x) if out is None else out
 
 
+def divergent_region(x, tab, seed: int, thr: int, side_true, side_false, variant=AUTO,
+                     out=None, stream=None, ctx=None):
+    """Two-sided loop region over the lanes of ``x`` (see meld_divergent_region_f32)."""
+    out = _region_tensors(x, tab, out)
+    c, s = _launch_args(x, stream, ctx)
+    _check(load_library().meld_divergent_region_f32(
+        c, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), x.numel(),
+        ctypes.c_void_p(tab.data_ptr()), tab.numel(), int(seed), int(thr),
+        _as_side(side_true), _as_side(side_false), _variant(variant), s))
+    return out
+
+
+def oddeven_sort_buckets(keys, log_bucket: int, max_steps: int = -1, variant=AUTO,
+                         stream=None, ctx=None):
+    """Sorts each bucket of 2^log_bucket keys in place with Batcher's odd-even merge
+    network (see meld_oddeven_sort_buckets_u32)."""
+    _u32_tensor(keys, "keys")
+    c, s = _launch_args(keys, stream, ctx)
+    _check(load_library().meld_oddeven_sort_buckets_u32(
+        c, ctypes.c_void_p(keys.data_ptr()), keys.numel(), int(log_bucket), int(max_steps),
+        _variant(variant), s))
+
+
+def merge_sort(keys, max_passes: int = -1, variant=AUTO, stream=None, ctx=None):
+    """Ascending bottom-up merge sort of ``keys`` in place (see meld_merge_sort_u32)."""
+    _u32_tensor(keys, "keys")
+    c, s = _launch_args(keys, stream, ctx)
+    _check(load_library().meld_merge_sort_u32(
+        c, ctypes.c_void_p(keys.data_ptr()), keys.numel(), int(max_passes), _variant(variant),
+        s))
+
+
 def region3(x, tab, seed: int, thr0: int, thr1: int, way0, way1, way2, variant=AUTO, out=None,
-            stream=None):
+            stream=None, ctx=None):
     """Three-way region over the lanes of ``x`` (see meld_region3_f32)."""
     out = _region_tensors(x, tab, out)
+    c, s = _launch_args(x, stream, ctx)
     _check(load_library().meld_region3_f32(
-        context(x.device.index), ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
-        x.numel(), ctypes.c_void_p(tab.data_ptr()), tab.numel(), int(seed), int(thr0), int(thr1),
-        _as_side(way0), _as_side(way1), _as_side(way2), _variant(variant),
-        _stream_of(x, stream)))
+        c, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), x.numel(),
+        ctypes.c_void_p(tab.data_ptr()), tab.numel(), int(seed), int(thr0), int(thr1),
+        _as_side(way0), _as_side(way1), _as_side(way2), _variant(variant), s))
     return out
 
 
@@ -308,60 +366,64 @@ def _as_side_range(s) -> SideRange:
 
 
 def region_lanetrips(x, tab, seed: int, thr: int, side_true, side_false, variant=AUTO,
-                     out=None, stream=None):
+                     out=None, stream=None, ctx=None):
     """Two-sided region with per-lane trip counts (see meld_region_lanetrips_f32); the
     sides are dicts with a, off, step, trips_lo, trips_hi."""
     out = _region_tensors(x, tab, out)
+    c, s = _launch_args(x, stream, ctx)
     _check(load_library().meld_region_lanetrips_f32(
-        context(x.device.index), ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
-        x.numel(), ctypes.c_void_p(tab.data_ptr()), tab.numel(), int(seed), int(thr),
-        _as_side_range(side_true), _as_side_range(side_false), _variant(variant),
-        _stream_of(x, stream)))
+        c, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), x.numel(),
+        ctypes.c_void_p(tab.data_ptr()), tab.numel(), int(seed), int(thr),
+        _as_side_range(side_true), _as_side_range(side_false), _variant(variant), s))
     return out
 
 
-def _cur_stream(device: int):
-    import torch
-    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+def _dev_args(device: int, stream, ctx):
+    h = _stream_handle(device, stream)
+    return (ctx if ctx is not None else context(device, h)), ctypes.c_void_p(h)
 
 
-def probe_region(n: int, seed: int, thr: int, device: int = 0):
+def probe_region(n: int, seed: int, thr: int, device: int = 0, stream=None, ctx=None):
     """(mixed waves, true lanes, waves) of the region branch over lanes [0, n)."""
     out = (ctypes.c_uint64 * 3)()
-    _check(load_library().meld_probe_region(context(device), n, seed, thr, out,
-                                            _cur_stream(device)))
+    c, s = _dev_args(device, stream, ctx)
+    _check(load_library().meld_probe_region(c, n, seed, thr, out, s))
     return tuple(int(v) for v in out)
 
 
-def probe_network(log_t: int, device: int = 0):
+def probe_network(log_t: int, device: int = 0, stream=None, ctx=None):
     """[(mixed comparator-waves, comparator-waves) for phases k = 2 .. 2^log_t]."""
     out = (ctypes.c_uint64 * (2 * log_t))()
-    _check(load_library().meld_probe_network(context(device), log_t, out, _cur_stream(device)))
+    c, s = _dev_args(device, stream, ctx)
+    _check(load_library().meld_probe_network(c, log_t, out, s))
     return [(int(out[2 * i]), int(out[2 * i + 1])) for i in range(log_t)]
 
 
-def probe_segments(offsets):
+def probe_segments(offsets, stream=None, ctx=None):
     """(mixed, all) comparator-steps of the phases k <= 64 and of k >= 128."""
     _u32_tensor(offsets, "offsets")
     out = (ctypes.c_uint64 * 4)()
-    dev = offsets.device.index
-    _check(load_library().meld_probe_segments(context(dev), ctypes.c_void_p(offsets.data_ptr()),
-                                              max(offsets.numel() - 1, 0), out, _cur_stream(dev)))
+    c, s = _launch_args(offsets, stream, ctx)
+    _check(load_library().meld_probe_segments(c, ctypes.c_void_p(offsets.data_ptr()),
+                                              max(offsets.numel() - 1, 0), out, s))
     return (int(out[0]), int(out[1])), (int(out[2]), int(out[3]))
 
 
-def tune(cache_path: str, device: int = 0) -> None:
-    """Attaches a JSON tuning cache (loads it if present, saves new decisions)."""
-    _check(load_library().meld_tune(context(device), cache_path.encode()))
+def tune(cache_path: str, device: int = 0, stream=None, ctx=None) -> None:
+    """Attaches a JSON tuning cache (loads it if present, saves new decisions) to the
+    context of (``device``, ``stream``)."""
+    c, _ = _dev_args(device, stream, ctx)
+    _check(load_library().meld_tune(c, cache_path.encode()))
 
 
-def plan_describe(device: int = 0) -> str:
-    """The context's tuning decisions as JSON text."""
+def plan_describe(device: int = 0, stream=None, ctx=None) -> str:
+    """The tuning decisions of the context of (``device``, ``stream``) as JSON text."""
     lib = load_library()
+    c, _ = _dev_args(device, stream, ctx)
     size = 1 << 16
     while True:
         buf = ctypes.create_string_buffer(size)
-        st = lib.meld_plan_describe(context(device), buf, size)
+        st = lib.meld_plan_describe(c, buf, size)
         if st == OK:
             return buf.value.decode()
         if size >= 1 << 26:
@@ -369,14 +431,16 @@ def plan_describe(device: int = 0) -> str:
         size *= 4
 
 
-def sort_plan(n: int, pairs: bool = False, variant: str = "auto", device=None) -> dict:
+def sort_plan(n: int, pairs: bool = False, variant: str = "auto", device=None, stream=None,
+              ctx=None) -> dict:
     """The launches a sort of n elements runs (tile, forms, HBM passes), as a
-    dict; device None: the library's default rule without a context."""
+    dict; device None (and no ctx): the library's default rule without a context."""
     import json
     lib = load_library()
-    ctx = None if device is None else context(device)
+    c = ctx if ctx is not None else (None if device is None else _dev_args(device, stream,
+                                                                           None)[0])
     buf = ctypes.create_string_buffer(1 << 16)
-    _check(lib.meld_sort_plan_describe(ctx, n, 1 if pairs else 0, _variant(variant), buf,
+    _check(lib.meld_sort_plan_describe(c, n, 1 if pairs else 0, _variant(variant), buf,
                                        len(buf)))
     return json.loads(buf.value.decode())
 

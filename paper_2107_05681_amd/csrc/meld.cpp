@@ -62,7 +62,8 @@ struct meld_ctx {
 
 namespace {
 constexpr size_t kProbeWords = 64;
-}
+
+}  // namespace
 
 namespace {
 
@@ -229,6 +230,13 @@ std::string fmt(const char *f, ...) {
     return buf;
 }
 
+constexpr size_t kMaxSegGraphs = 8;
+
+void drop_seg_graphs(meld_ctx *ctx) {
+    for (auto &g : ctx->seg_graphs) (void)hipGraphExecDestroy(g.exec);
+    ctx->seg_graphs.clear();
+}
+
 // Scratch of the segmented sort for up to nseg segments.
 meld_status ensure_seg(meld_ctx *ctx, size_t nseg) {
     if (ctx->seg_state == nullptr) {
@@ -248,6 +256,9 @@ meld_status ensure_seg(meld_ctx *ctx, size_t nseg) {
         if (ctx->seg_cls != nullptr || ctx->seg_queue != nullptr) {
             hipError_t e = hipDeviceSynchronize();
             if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+            // Every captured graph holds the old arrays' addresses: none may
+            // be replayed after they are freed, whichever caller grows them.
+            drop_seg_graphs(ctx);
             (void)hipFree(ctx->seg_cls);
             (void)hipFree(ctx->seg_queue);
             ctx->seg_cls = nullptr;
@@ -262,13 +273,6 @@ meld_status ensure_seg(meld_ctx *ctx, size_t nseg) {
         ctx->seg_cap = nseg;
     }
     return MELD_OK;
-}
-
-constexpr size_t kMaxSegGraphs = 8;
-
-void drop_seg_graphs(meld_ctx *ctx) {
-    for (auto &g : ctx->seg_graphs) (void)hipGraphExecDestroy(g.exec);
-    ctx->seg_graphs.clear();
 }
 
 // The graph of (keys, n_keys, offsets, nseg, forms), captured on first use.
@@ -325,10 +329,8 @@ meld_status segmented_impl(meld_ctx *ctx, uint32_t *keys, size_t n_keys, const u
     if (!is_device_ptr(ctx, keys) || !is_device_ptr(ctx, offsets))
         return fail(MELD_EINVAL, "%s: keys and offsets must be device pointers on device %d", fn,
                     ctx->device);
-    const size_t cap_before = ctx->seg_cap;
-    meld_status st = ensure_seg(ctx, nseg);
+    meld_status st = ensure_seg(ctx, nseg);  // drops the graphs if the scratch moves
     if (st != MELD_OK) return st;
-    if (ctx->seg_cap != cap_before) drop_seg_graphs(ctx);  // scratch moved
     // A caller that is itself capturing gets the launches in its own graph.
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     hipError_t e = hipStreamIsCapturing(stream, &cs);
@@ -463,8 +465,15 @@ std::vector<SortPass> sort_passes(const SortPlan &plan, bool pairs, uint32_t log
 }
 
 // Enqueues the whole network (or its first step_limit steps) on keys[0..n).
+// marks: NULL, or one event per launch plus one, recorded on the stream
+// before the first launch (and the tail fill) and after every launch.
+// fixed_tail: NULL (the context's tail workspace, grown on demand), or device
+// memory of fixed_tail_words words that holds the padding instead (nothing is
+// allocated; MELD_EINVAL if it is too small).
 meld_status sort_impl(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n,
-                      const SortPlan &plan, int64_t step_limit, hipStream_t stream) {
+                      const SortPlan &plan, int64_t step_limit, hipStream_t stream,
+                      const std::vector<hipEvent_t> *marks = nullptr,
+                      uint32_t *fixed_tail = nullptr, size_t fixed_tail_words = 0) {
     const bool pairs = payload != nullptr;
     const uint32_t log_n = log2_ceil(n);
     const size_t big_n = (size_t)1 << log_n;
@@ -482,6 +491,12 @@ meld_status sort_impl(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n
         return fail(MELD_EINVAL, "sort: tile 2^%u outside 2^%u .. 2^%u", plan.log_t,
                     kMinLogRegsTile, max_log_tile(pairs));
     const std::vector<SortPass> passes = sort_passes(plan, pairs, log_n);
+    if (marks != nullptr && marks->size() != passes.size() + 1)
+        return fail(MELD_EINVAL, "sort: %zu timing events for %zu launches", marks->size(),
+                    passes.size());
+    auto mark = [&](size_t i) -> hipError_t {
+        return marks != nullptr ? hipEventRecord((*marks)[i], stream) : hipSuccess;
+    };
 
     hipError_t e;
     if (passes[0].kind == PassKind::kTile) {
@@ -491,23 +506,38 @@ meld_status sort_impl(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n
                        : (aligned16(keys) && (!pairs || aligned16(payload))) ? meld::kIoPlainVec
                                                                              : meld::kIoPlain;
         const int32_t steps = take(passes[0].steps);
+        e = mark(0);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
         if (log_t >= kMinLogRegsTile)
             e = meld::launch_bitonic_sort_regs(a, log_t, 1, steps, plan.lo, plan.hi, io, stream);
         else
             e = meld::launch_bitonic_tile(a, log_t, 1, 1, log_t, 0, steps, plan.lo, plan.hi, io,
                                           tile_threads(log_t), stream);
+        if (e == hipSuccess) e = mark(1);
         if (e != hipSuccess) return hip_fail(e, "bitonic tile launch");
         return MELD_OK;
     }
 
     if (big_n > n) {
         const size_t pad = big_n - n;
-        meld_status st = ensure_tail(ctx, pairs ? 2 * pad : pad);
-        if (st != MELD_OK) return st;
-        a.tk = ctx->tail;
-        a.tv = pairs ? ctx->tail + pad : nullptr;
-        e = meld::launch_fill_u32(ctx->tail, 0xFFFFFFFFu, pairs ? 2 * pad : pad, stream);
+        const size_t words = pairs ? 2 * pad : pad;
+        uint32_t *tail = fixed_tail;
+        if (tail == nullptr) {
+            meld_status st = ensure_tail(ctx, words);
+            if (st != MELD_OK) return st;
+            tail = ctx->tail;
+        } else if (words > fixed_tail_words) {
+            return fail(MELD_EINVAL, "sort: padding of %zu words exceeds the %zu-word scratch",
+                        words, fixed_tail_words);
+        }
+        a.tk = tail;
+        a.tv = pairs ? tail + pad : nullptr;
+        e = mark(0);
+        if (e == hipSuccess) e = meld::launch_fill_u32(tail, 0xFFFFFFFFu, words, stream);
         if (e != hipSuccess) return hip_fail(e, "fill launch");
+    } else {
+        e = mark(0);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     }
 
     const uint32_t log_t = plan.log_t;
@@ -515,7 +545,8 @@ meld_status sort_impl(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n
     const int io = a.tk != nullptr ? meld::kIoTail
                    : (aligned16(keys) && (!pairs || aligned16(payload))) ? meld::kIoPlainVec
                                                                          : meld::kIoPlain;
-    for (const SortPass &p : passes) {
+    for (size_t pi = 0; pi < passes.size(); ++pi) {
+        const SortPass &p = passes[pi];
         const int32_t steps = take(p.steps);
         switch (p.kind) {
             case PassKind::kLocal:
@@ -534,6 +565,7 @@ meld_status sort_impl(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n
             default:
                 return fail(MELD_EINVAL, "sort: unexpected pass");
         }
+        if (e == hipSuccess) e = mark(pi + 1);
         if (e != hipSuccess)
             return hip_fail(e, fmt("bitonic %s launch", pass_name(p.kind)).c_str());
     }
@@ -955,6 +987,7 @@ meld_status meld_create(int hip_device, meld_ctx **out) {
     meld_ctx *ctx = new (std::nothrow) meld_ctx();
     if (ctx == nullptr) return fail(MELD_ENOMEM, "meld_create: out of host memory");
     ctx->device = hip_device;
+
     hipDeviceProp_t prop;
     int runtime = 0;
     if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess &&
@@ -1004,6 +1037,56 @@ meld_status meld_sort_u32(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size
         if (st != MELD_OK) return st;
     }
     return sort_impl(ctx, keys, payload, n, plan, -1, s);
+}
+
+meld_status meld_sort_u32_timed(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n,
+                                meld_variant variant, void *stream, float *launch_ms,
+                                size_t cap, size_t *n_launches) {
+    const char *name = "meld_sort_u32_timed";
+    if (ctx == nullptr || launch_ms == nullptr || n_launches == nullptr)
+        return fail(MELD_EINVAL, "%s: ctx, launch_ms and n_launches must not be NULL", name);
+    *n_launches = 0;
+    if (n >= (1ull << 31)) return fail(MELD_EINVAL, "%s: n = %zu >= 2^31", name, n);
+    if ((unsigned)variant > MELD_MELDED_INPLACE) return fail(MELD_EINVAL, "%s: bad variant", name);
+    if (n <= 1) return MELD_OK;
+    DeviceGuard g(ctx->device);
+    if (!is_device_ptr(ctx, keys) || (payload != nullptr && !is_device_ptr(ctx, payload)))
+        return fail(MELD_EINVAL, "%s: keys and payload must be device pointers on device %d",
+                    name, ctx->device);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool pairs = payload != nullptr;
+    SortPlan plan = fixed_plan(ctx, pairs, n, variant);
+    if (variant == MELD_AUTO) {
+        meld_status st = auto_sort_plan(ctx, keys, payload, n, s, &plan);
+        if (st != MELD_OK) return st;
+    }
+    const size_t launches = sort_passes(plan, pairs, log2_ceil(n)).size();
+    if (cap < launches)
+        return fail(MELD_EINVAL, "%s: cap = %zu < %zu launches", name, cap, launches);
+    std::vector<hipEvent_t> marks(launches + 1, nullptr);
+    meld_status st = MELD_OK;
+    for (auto &ev : marks)
+        if (hipEventCreate(&ev) != hipSuccess) {
+            ev = nullptr;
+            st = fail(MELD_EHIP, "%s: hipEventCreate failed", name);
+            break;
+        }
+    if (st == MELD_OK) st = sort_impl(ctx, keys, payload, n, plan, -1, s, &marks);
+    if (st == MELD_OK) {
+        hipError_t e = hipEventSynchronize(marks.back());
+        if (e != hipSuccess) st = hip_fail(e, "hipEventSynchronize");
+    }
+    if (st == MELD_OK) {
+        for (size_t i = 0; i < launches; ++i) {
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, marks[i], marks[i + 1]);
+            launch_ms[i] = ms;
+        }
+        *n_launches = launches;
+    }
+    for (hipEvent_t ev : marks)
+        if (ev != nullptr) (void)hipEventDestroy(ev);
+    return st;
 }
 
 meld_status meld_sort_plan_describe(meld_ctx *ctx, size_t n, int with_payload,

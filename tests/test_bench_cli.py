@@ -37,19 +37,19 @@ def _fake_root(tmp_path, traffic=12345):
 def test_traffic_reported_while_sources_match(tmp_path, monkeypatch):
     srcs = _fake_root(tmp_path)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench._measured_traffic() == 12345
+    assert bench._measured_traffic("region_melded_traffic.json") == 12345
     # any edit of a listed source voids the record
     (tmp_path / srcs[1]).write_bytes(b"edited\n")
-    assert bench._measured_traffic() is None
+    assert bench._measured_traffic("region_melded_traffic.json") is None
 
 
 def test_traffic_missing_record_or_source_is_none(tmp_path, monkeypatch):
     srcs = _fake_root(tmp_path)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     os.remove(tmp_path / srcs[0])
-    assert bench._measured_traffic() is None
+    assert bench._measured_traffic("region_melded_traffic.json") is None
     shutil.rmtree(tmp_path / "profiles")
-    assert bench._measured_traffic() is None
+    assert bench._measured_traffic("region_melded_traffic.json") is None
 
 
 def test_committed_record_names_existing_sources():
@@ -58,3 +58,24 @@ def test_committed_record_names_existing_sources():
     assert rec["kernel"] == "region_melded_kernel"
     assert all(os.path.exists(os.path.join(ROOT, s)) for s in rec["sources"])
     assert rec["traffic_bytes"] > 0 and rec["fetch_factor"] > 0 and rec["write_factor"] > 0
+
+
+def test_sort_roofline_takes_the_kind_with_the_largest_total():
+    import numpy as np
+    plan = {"passes": [{"kind": "local"}, {"kind": "regs"}, {"kind": "merge"},
+                       {"kind": "regs"}, {"kind": "merge"}]}
+    n = 1 << 20
+    launches = [[1.0, 0.2, 0.5, 0.2, 0.5], [1.2, 0.2, 0.7, 0.2, 0.7]]
+    roof, per = bench._sort_roofline(np, plan, launches, n)
+    assert per["merge"]["launches_per_sort"] == 2
+    assert abs(per["merge"]["avg_launch_us"] - 600.0) < 1e-6
+    assert abs(per["merge"]["ms_per_sort"] - 1.2) < 1e-9
+    assert roof["kind"] == "merge"  # 1.2 ms per sort against 1.1 (local) and 0.4 (regs)
+    assert abs(roof["achieved"] - 16 * n / 600e-6 / 1e9) < 0.1
+    assert abs(roof["frac"] - roof["achieved"] / bench.HBM_PEAK_GBS) < 1e-4
+
+
+def test_cpu_info_reports_model_and_counts():
+    info = bench._cpu_info()
+    assert info["host_logical_cpus"] >= 1 and info["affinity_cpus"] >= 1
+    assert 1 <= bench._oracle_threads() <= 16

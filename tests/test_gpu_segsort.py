@@ -189,3 +189,37 @@ def test_segmented_graph_replays_match_eager():
         assert torch.equal(work, eager), rep
     meld.segmented_sort_check(0)
     assert np.array_equal(_to_host(eager), oracle.segmented_sort_u32(keys, off))
+
+
+def test_segmented_graph_not_replayed_after_scratch_growth():
+    # A fresh context: MELD_AUTO at 100 segments captures a graph over the
+    # context's queue arrays; a call at 200 segments (another shape class)
+    # grows and reallocates them; the first call again must not replay a graph
+    # that points at the freed arrays.
+    dev = _dev()
+    ctx = meld.new_context(0)
+    try:
+        runs = []
+        for nseg, seed in ((100, 21), (200, 22)):
+            off = workloads.segment_offsets(seed, nseg)
+            keys = workloads.keys_u32(seed, int(off[-1]))
+            runs.append((keys, off, _to_dev(off), _to_dev(keys)))
+        k1, off1, od1, kd1 = runs[0]
+        k2, off2, od2, kd2 = runs[1]
+        meld.segmented_sort(kd1, od1, variant="auto", ctx=ctx)
+        meld.segmented_sort(kd2, od2, variant="auto", ctx=ctx)
+        torch.cuda.synchronize()
+        assert np.array_equal(_to_host(kd2), oracle.segmented_sort_u32(k2, off2))
+        kd1.copy_(_to_dev(k1))  # same pointers as the first call
+        meld.segmented_sort(kd1, od1, variant="auto", ctx=ctx)
+        torch.cuda.synchronize()
+        meld.segmented_sort_check(0, ctx=ctx)
+        assert np.array_equal(_to_host(kd1), oracle.segmented_sort_u32(k1, off1))
+        # and the graph of the grown size still replays correctly
+        kd2.copy_(_to_dev(k2))
+        meld.segmented_sort(kd2, od2, variant="auto", ctx=ctx)
+        torch.cuda.synchronize()
+        assert np.array_equal(_to_host(kd2), oracle.segmented_sort_u32(k2, off2))
+        assert dev is not None
+    finally:
+        meld.destroy_context(ctx)

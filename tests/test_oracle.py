@@ -104,6 +104,31 @@ def test_sort_pairs_with_index_payload_is_stable_key_sort():
     assert np.array_equal(k[ov], ok)
 
 
+@pytest.mark.parametrize("threads", [1, 2, 3, 7, 16])
+def test_sort_pairs_threads_is_the_stable_key_sort(threads):
+    # The threaded oracle sort (chunks + pairwise merges) against numpy's stable
+    # argsort, on sizes that cut into uneven chunks, with heavy ties.
+    for n in (0, 1, 2, 5, 17, 1000, 40_003):
+        k = workloads.keys_u32(4 + n, n) % np.uint32(37)
+        v = workloads.iota_u32(n)
+        ok, ov = oracle.sort_pairs_u32_threads(k, v, threads)
+        order = np.argsort(k, kind="stable").astype(np.uint32)
+        assert np.array_equal(ov, order), (n, threads)
+        assert np.array_equal(ok, k[order]), (n, threads)
+
+
+def test_sort_pairs_threads_brute_force_small():
+    rng = np.random.default_rng(6)
+    for n in range(0, 7):
+        for _ in range(100):
+            k = rng.integers(0, 3, n).astype(np.uint32)
+            v = rng.integers(0, 3, n).astype(np.uint32)
+            ok, ov = oracle.sort_pairs_u32_threads(k, v, 1 + n % 4)
+            assert list(zip(ok.tolist(), ov.tolist())) == sorted(zip(k.tolist(), v.tolist()))
+    with pytest.raises(ValueError):
+        oracle.sort_pairs_u32_threads(np.zeros(3, np.uint32), np.zeros(3, np.uint32), 0)
+
+
 def test_segmented_sort_respects_boundaries():
     off = np.array([0, 0, 1, 5, 5, 12, 40], dtype=np.uint32)
     keys = workloads.keys_u32(9, 40)
