@@ -37,6 +37,11 @@ SEED = 1
 REGION_COMPULSORY = 3 * 4 * N_LANES
 
 
+def _progress(msg):
+    """One line on stderr when a part of the run has finished."""
+    print(f"bench: {msg} ({time.strftime('%H:%M:%S')})", file=sys.stderr, flush=True)
+
+
 def _parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,7 +157,9 @@ def _check_pairs_sorted(torch, kin, k, p):
     of 0..n-1 and k == kin[p] (these fix the sorted array exactly)."""
     ku = k.to(torch.int64) & 0xFFFFFFFF
     pu = p.to(torch.int64) & 0xFFFFFFFF
-    comp = ku * (1 << 32) + pu
+    # (key - 2^31) * 2^32 + payload orders like the unsigned (key, payload)
+    # pair and fits a signed 64-bit integer
+    comp = (ku - (1 << 31)) * (1 << 32) + pu
     if not bool((comp[1:] > comp[:-1]).all()):
         raise SystemExit("2^28-pair sort: output not in strictly increasing (key, payload) order")
     if not bool((torch.bincount(pu, minlength=k.numel()) == 1).all()):
@@ -225,31 +232,38 @@ def main():
     del k, p
     torch.cuda.empty_cache()
 
+    _progress("headline 2^28-pair sorts done")
     pairs_forms = _bench_pairs_forms(torch, np, meld, workloads, dev, kin, pin, args)
+    _progress("divergent / melded 2^28-pair sorts done")
     del kin, pin
     torch.cuda.empty_cache()
 
     region_info = None
     if not args.no_region:
         region_info = _bench_region(torch, np, meld, workloads, dev, args)
+        _progress("region done")
 
     sort16 = oddeven_info = merge_info = None
     if not args.no_sort:
         sort16 = _bench_sort16(torch, np, meld, workloads, dev, args)
         oddeven_info = _bench_oddeven(torch, np, meld, workloads, dev)
         merge_info = _bench_mergesort(torch, np, meld, workloads, dev)
+        _progress("2^16-key, odd-even and merge sorts done")
 
     seg_info = None
     if not args.no_seg:
         seg_info = _bench_segmented(torch, np, meld, workloads, dev, args)
+        _progress("segmented sort done")
 
     serve_info = None
     if args.serve_seconds > 0:
         serve_info = _bench_serving(meld, workloads, args.serve_seconds)
+        _progress("serving done")
 
     cpu = None
     if not args.no_cpu:
         cpu = _cpu_baseline_pairs(np, workloads)
+        _progress("CPU oracle, 2^28-pair sample done")
         if sort16 is not None:
             sort16["cpu_oracle"] = _cpu_sort_keys(np, workloads, 1 << 16)
         if seg_info is not None:

@@ -89,7 +89,22 @@ typedef enum {
      * 8..14 for keys, 8..13 for pairs, fixes it (a larger value applies to
      * key-only sorts and is clamped to 13 for pairs). MELD_EINVAL outside
      * {0} and 8..14. */
-    MELD_OPT_SORT_LOG_TILE = 1
+    MELD_OPT_SORT_LOG_TILE = 1,
+    /* How the phases k <= 64 of the sorts (tile sorts of meld_sort_u32 and
+     * meld_sort_u32_steps, and the segments of meld_segmented_sort_u32 above
+     * 128 keys) run, on top of the form meld_variant selects:
+     *   1  in registers, 16 elements per lane (element 16 t + r in register
+     *      r of lane t), the steps on element bits 4 and 5 as DPP exchanges
+     *      with lane t ^ 1 / t ^ 2. The exchange is taken before the
+     *      direction branch in both forms (warp-level intrinsics are never
+     *      melded, Detailed Design, "Computing Melding Profitability"); only
+     *      the compare and select differ between them.
+     *   0  as the LDS comparator network of Figure 1's mapping (one
+     *      comparator per lane per step).
+     *  -1  (default) the library's choice: 1 under MELD_DIVERGENT and
+     *      MELD_MELDED, timed against 0 by the tuner under MELD_AUTO.
+     * Both give the same network, step for step. MELD_EINVAL outside -1..1. */
+    MELD_OPT_LANE_EXCHANGE = 2
 } meld_option;
 
 /* Sets a context option. MELD_EINVAL for an unknown option. */

@@ -280,6 +280,7 @@ def segmented_sort_check(device: int = 0, stream=None, ctx=None):
 
 OPT_USE_GRAPHS = 0
 OPT_SORT_LOG_TILE = 1
+OPT_LANE_EXCHANGE = 2
 
 
 def set_option(device: int, option: int, value: int) -> None:

@@ -36,6 +36,7 @@
 // low bits of the index come from the lane, for the whole wave: both forms
 // coincide there and a single kernel serves them.
 #include "device_common.h"
+#include "exchange.h"
 #include "kernels.h"
 #include "network.h"
 
@@ -301,6 +302,45 @@ __device__ __forceinline__ void merge_windows(E (&e)[kMergeE], E *s, uint32_t t,
     }
 }
 
+// Steps on element bits TOP .. 0 of a merge (layout PREV on entry) that end
+// in layout W0 (window 0) instead of a last four-bit window: windows with
+// bases TOP-3, TOP-7, ... while the top step bit is at least 6, then W0,
+// where the steps on element bits 5 and 4 are DPP lane exchanges (lane bits
+// 1 and 0) and bits 3 .. 0 registers. The direction is uniform per tile, so
+// the lane steps take the melded compare-select.
+template <int L, int TOP, int PREV, typename E>
+__device__ __forceinline__ void merge_windows_xch(E (&e)[kMergeE], E *s, uint32_t t, bool up,
+                                                  int32_t nsteps) {
+    if constexpr (TOP >= 6) {
+        constexpr int B = TOP - 3;
+        merge_transpose<L, PREV, B>(e, s, t);
+        merge_window_steps<L, B, TOP>(e, up, nsteps);
+        merge_windows_xch<L, B - 1, B>(e, s, t, up, nsteps);
+    } else if constexpr (TOP >= 0) {
+        merge_transpose<L, PREV, 0>(e, s, t);
+        if constexpr (TOP >= 5)
+            if (L - 1 - 5 < nsteps) lane_step<1, true>(e, up, ((t >> 1) & 1u) == 0);
+        if constexpr (TOP >= 4)
+            if (L - 1 - 4 < nsteps) lane_step<0, true>(e, up, (t & 1u) == 0);
+        merge_window_steps<L, 0, (TOP < 3 ? TOP : 3)>(e, up, nsteps);
+    }
+}
+
+// Windows (LDS transposes) a merge tail of 2^L needs after layout V's two
+// steps: four-bit windows all the way, or ending in W0 with lane exchanges.
+constexpr int merge_windows_plain(int L) { return (L - 2 + 3) / 4; }
+constexpr int merge_windows_with_xch(int L) {
+    int n = 0, top = L - 3;
+    for (; top >= 6; top -= 4) ++n;
+    return top >= 0 ? n + 1 : n;
+}
+// The merge tail takes the lane-exchange ending where it saves a transpose
+// (tiles of 2^8, 2^11 and 2^12; for 2^13 and 2^14 both need three).
+template <int L>
+constexpr bool merge_uses_xch() {
+    return merge_windows_with_xch(L) < merge_windows_plain(L);
+}
+
 // Where element i of a tile lives in the array: its low C bits stay, the
 // bits above C move up to start at bit b_lo, and base holds the workgroup's
 // other bits. C = L is a contiguous tile at base.
@@ -488,8 +528,13 @@ __global__ __launch_bounds__(1 << (L - 4)) void bitonic_pass_regs_kernel(SortArr
     regs_load<PAIRS, L, C>(a, map, t, mode, e);
     if (0 < nsteps) merge_reg_step<3>(e, up);                // element bit L-1
     if (S >= 2 && 1 < nsteps) merge_reg_step<2>(e, up);      // element bit L-2
-    merge_windows<L, 1, -1, L - S>(e, s, t, up, nsteps);
-    regs_store<PAIRS, L, C, last_layout<L, L - S>()>(a, s, map, t, mode, e);
+    if constexpr (S == L && merge_uses_xch<L>()) {
+        merge_windows_xch<L, L - 3, -1>(e, s, t, up, nsteps);
+        regs_store<PAIRS, L, C, 0>(a, s, map, t, mode, e);
+    } else {
+        merge_windows<L, 1, -1, L - S>(e, s, t, up, nsteps);
+        regs_store<PAIRS, L, C, last_layout<L, L - S>()>(a, s, map, t, mode, e);
+    }
 }
 
 // One register step on register bit Q in the two forms of the direction
@@ -548,20 +593,53 @@ __device__ __forceinline__ void reg_steps(E (&e)[kMergeE], int hi_q, bool up, in
     }
 }
 
+// Moves a tile held in window prev to window B (run-time bases) through LDS.
+template <bool PAIRS, typename E>
+__device__ __forceinline__ void window_move(E (&e)[kMergeE], E *s, uint32_t t, uint32_t prev,
+                                            uint32_t B) {
+    if (B == prev) return;
+    if constexpr (PAIRS) {
+        // 8-byte elements: the per-case copies that the compile-time
+        // windows leave behind cost more than the scalar offsets
+        // (2^28 pairs: local sort 5.73 -> 5.97 ms melded)
+        const uint32_t tp = merge_phys(window_tpart(t, prev));
+        const uint32_t tb = merge_phys(window_tpart(t, B));
+#pragma unroll
+        for (int r = 0; r < kMergeE; ++r) s[tp + merge_phys((uint32_t)r << prev)] = e[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kMergeE; ++r) e[r] = s[tb + merge_phys((uint32_t)r << B)];
+        __syncthreads();
+    } else {
+        window_store(e, s + merge_phys(window_tpart(t, prev)), prev);
+        __syncthreads();
+        window_load(e, s + merge_phys(window_tpart(t, B)), B);
+        __syncthreads();
+    }
+}
+
 // The whole network of a tile of T = 2^L elements (phases k = 2 .. T; the
 // last one's direction is bit L of the tile's base).
 //
-// Phases k <= 64 run as the LDS comparator network, one comparator per lane
-// per iteration (Figure 1's mapping), in form MELD_LO: their direction is a
-// lane bit of the comparator index.
+// XCH = false: phases k <= 64 run as the LDS comparator network, one
+// comparator per lane per iteration (Figure 1's mapping), in form MELD_LO:
+// their direction is a lane bit of the comparator index. Phases k = 2^m >= 128
+// run in register windows: for phase m the windows have bases m-4, m-8, ...
+// (clamped at 0), each taking four of the steps on bits m-1 .. 0.
 //
-// Phases k = 2^m >= 128 run in register windows: for phase m the windows
-// have bases m-4, m-8, ... (clamped at 0), each taking four of the steps on
-// bits m-1 .. 0. In window B element bit m (>= B+4) is thread bit m-4, so
-// the direction is the same for all of a thread's elements and, for m <= 9,
-// differs between the lanes of a wave: form MELD_HI decides how that region
-// runs.
-template <bool PAIRS, int L, bool MELD_LO, bool MELD_HI>
+// XCH = true: the tile goes to layout W0 (register r of thread t holds
+// element 16 t + r) and phases k <= 64 run in registers with DPP lane
+// exchanges for the steps on element bits 4 and 5 (xch_network_low): no LDS
+// access at all. Phases 2^1 .. 2^3 then have a direction fixed per register
+// and phases 2^4 .. 2^6 one from a lane bit; form MELD_LO decides how those
+// run. Phases m >= 7 take windows with bases m-4, m-8, ... while their top
+// step bit is at least 6 and end in W0, where the steps on bits 5 and 4 are
+// lane exchanges: a window fewer for m = 9, 10, 13, 14.
+//
+// In window B element bit m (>= B+4) is thread bit m-4, so the direction is
+// the same for all of a thread's elements and, for m <= 9, differs between
+// the lanes of a wave: form MELD_HI decides how that region runs.
+template <bool PAIRS, int L, bool MELD_LO, bool MELD_HI, bool XCH>
 __global__ __launch_bounds__(1 << (L - 4)) void bitonic_sort_regs_kernel(SortArray a, int mode,
                                                                          int32_t step_limit) {
     using E = typename ElemOf<PAIRS>::type;
@@ -575,50 +653,60 @@ __global__ __launch_bounds__(1 << (L - 4)) void bitonic_sort_regs_kernel(SortArr
     const TileMap<L, L> map{base, (uint32_t)L};
     E e[kMergeE];
     regs_load<PAIRS, L, L>(a, map, t, mode, e);
-#pragma unroll
-    for (int r = 0; r < kMergeE; ++r) s[low_swz<E, PAIRS>(merge_index<L, -1>(t, r))] = e[r];  // natural order
-    __syncthreads();
-    const int32_t lo_steps = lds_network_low<E, MELD_LO, 8, PAIRS>(s, base, 6, t, NT, step_limit);
-    __syncthreads();
-    int32_t left = step_limit < 0 ? 0x7FFFFFFF : step_limit - lo_steps;
-
-    // Phase 2^7 starts in window 3 (element bits 3..6), read from the natural
-    // order the comparator network leaves in s.
-    uint32_t prev = 3;
-    {
-        const uint32_t tb = window_tpart(t, prev);
-#pragma unroll
-        for (int r = 0; r < kMergeE; ++r) e[r] = s[low_swz<E, PAIRS>(tb | ((uint32_t)r << prev))];
-        __syncthreads();
-    }
-    for (uint32_t m = 7; m <= (uint32_t)L; ++m) {
-        const bool up = (((base >> m) | (t >> (m - 4))) & 1u) == 0;
-        for (uint32_t w = 1;; ++w) {
-            const uint32_t B = m > 4 * w ? m - 4 * w : 0;
-            const int hi_q = (int)(m - 4 * (w - 1) - 1 - B);
-            if (B != prev) {
-                if constexpr (PAIRS) {
-                    // 8-byte elements: the per-case copies that the compile-time
-                    // windows leave behind cost more than the scalar offsets
-                    // (2^28 pairs: local sort 5.73 -> 5.97 ms melded)
-                    const uint32_t tp = merge_phys(window_tpart(t, prev));
-                    const uint32_t tb = merge_phys(window_tpart(t, B));
-#pragma unroll
-                    for (int r = 0; r < kMergeE; ++r) s[tp + merge_phys((uint32_t)r << prev)] = e[r];
-                    __syncthreads();
-#pragma unroll
-                    for (int r = 0; r < kMergeE; ++r) e[r] = s[tb + merge_phys((uint32_t)r << B)];
-                    __syncthreads();
-                } else {
-                    window_store(e, s + merge_phys(window_tpart(t, prev)), prev);
-                    __syncthreads();
-                    window_load(e, s + merge_phys(window_tpart(t, B)), B);
-                    __syncthreads();
-                }
+    if constexpr (XCH) {
+        merge_transpose<L, -1, 0>(e, s, t);
+        const int32_t lo_steps = xch_network_low<MELD_LO>(e, t, step_limit);
+        int32_t left = step_limit < 0 ? 0x7FFFFFFF : step_limit - lo_steps;
+        uint32_t prev = 0;
+        for (uint32_t m = 7; m <= (uint32_t)L; ++m) {
+            const bool up = (((base >> m) | (t >> (m - 4))) & 1u) == 0;
+            int top = (int)m - 1;
+            while (top >= 6) {
+                const uint32_t B = (uint32_t)top - 3;
+                window_move<PAIRS>(e, s, t, prev, B);
+                reg_steps<MELD_HI>(e, 3, up, left);
+                prev = B;
+                top = (int)B - 1;
             }
-            reg_steps<MELD_HI>(e, hi_q, up, left);
-            prev = B;
-            if (B == 0) break;
+            window_move<PAIRS>(e, s, t, prev, 0);
+            prev = 0;
+            if (top >= 5 && left > 0) {
+                lane_step<1, MELD_HI>(e, up, ((t >> 1) & 1u) == 0);
+                --left;
+            }
+            if (top >= 4 && left > 0) {
+                lane_step<0, MELD_HI>(e, up, (t & 1u) == 0);
+                --left;
+            }
+            reg_steps<MELD_HI>(e, top < 3 ? top : 3, up, left);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < kMergeE; ++r) s[low_swz<E, PAIRS>(merge_index<L, -1>(t, r))] = e[r];  // natural order
+        __syncthreads();
+        const int32_t lo_steps = lds_network_low<E, MELD_LO, 8, PAIRS>(s, base, 6, t, NT, step_limit);
+        __syncthreads();
+        int32_t left = step_limit < 0 ? 0x7FFFFFFF : step_limit - lo_steps;
+
+        // Phase 2^7 starts in window 3 (element bits 3..6), read from the natural
+        // order the comparator network leaves in s.
+        uint32_t prev = 3;
+        {
+            const uint32_t tb = window_tpart(t, prev);
+#pragma unroll
+            for (int r = 0; r < kMergeE; ++r) e[r] = s[low_swz<E, PAIRS>(tb | ((uint32_t)r << prev))];
+            __syncthreads();
+        }
+        for (uint32_t m = 7; m <= (uint32_t)L; ++m) {
+            const bool up = (((base >> m) | (t >> (m - 4))) & 1u) == 0;
+            for (uint32_t w = 1;; ++w) {
+                const uint32_t B = m > 4 * w ? m - 4 * w : 0;
+                const int hi_q = (int)(m - 4 * (w - 1) - 1 - B);
+                window_move<PAIRS>(e, s, t, prev, B);
+                reg_steps<MELD_HI>(e, hi_q, up, left);
+                prev = B;
+                if (B == 0) break;
+            }
         }
     }
     regs_store<PAIRS, L, L, 0>(a, s, map, t, mode, e);
@@ -671,11 +759,11 @@ hipError_t launch_gather_r(const SortArray &a, uint32_t log_n, uint32_t m, uint3
     return hipGetLastError();
 }
 
-template <bool PAIRS, int L, bool LO, bool HI>
+template <bool PAIRS, int L, bool LO, bool HI, bool XCH>
 hipError_t launch_sort_regs_f(const SortArray &a, uint32_t n_tiles, int32_t step_limit,
                               int io_mode, hipStream_t stream) {
     const size_t lds = regs_lds_bytes<PAIRS, L>();
-    auto kern = bitonic_sort_regs_kernel<PAIRS, L, LO, HI>;
+    auto kern = bitonic_sort_regs_kernel<PAIRS, L, LO, HI, XCH>;
     hipError_t e = allow_lds(kern, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(n_tiles), dim3(1u << (L - 4)), lds, stream, a, io_mode,
@@ -683,15 +771,26 @@ hipError_t launch_sort_regs_f(const SortArray &a, uint32_t n_tiles, int32_t step
     return hipGetLastError();
 }
 
-template <bool PAIRS, int L>
-hipError_t launch_sort_regs_l(const SortArray &a, uint32_t n_tiles, int32_t step_limit, bool lo,
+template <bool PAIRS, int L, bool XCH>
+hipError_t launch_sort_regs_x(const SortArray &a, uint32_t n_tiles, int32_t step_limit, bool lo,
                               bool hi, int io_mode, hipStream_t stream) {
     if (lo)
-        return hi ? launch_sort_regs_f<PAIRS, L, true, true>(a, n_tiles, step_limit, io_mode, stream)
-                  : launch_sort_regs_f<PAIRS, L, true, false>(a, n_tiles, step_limit, io_mode,
-                                                              stream);
-    return hi ? launch_sort_regs_f<PAIRS, L, false, true>(a, n_tiles, step_limit, io_mode, stream)
-              : launch_sort_regs_f<PAIRS, L, false, false>(a, n_tiles, step_limit, io_mode, stream);
+        return hi ? launch_sort_regs_f<PAIRS, L, true, true, XCH>(a, n_tiles, step_limit, io_mode,
+                                                                  stream)
+                  : launch_sort_regs_f<PAIRS, L, true, false, XCH>(a, n_tiles, step_limit,
+                                                                   io_mode, stream);
+    return hi ? launch_sort_regs_f<PAIRS, L, false, true, XCH>(a, n_tiles, step_limit, io_mode,
+                                                               stream)
+              : launch_sort_regs_f<PAIRS, L, false, false, XCH>(a, n_tiles, step_limit, io_mode,
+                                                                stream);
+}
+
+template <bool PAIRS, int L>
+hipError_t launch_sort_regs_l(const SortArray &a, uint32_t n_tiles, int32_t step_limit, bool lo,
+                              bool hi, bool xch, int io_mode, hipStream_t stream) {
+    return xch ? launch_sort_regs_x<PAIRS, L, true>(a, n_tiles, step_limit, lo, hi, io_mode, stream)
+               : launch_sort_regs_x<PAIRS, L, false>(a, n_tiles, step_limit, lo, hi, io_mode,
+                                                     stream);
 }
 
 #define MELD_REGS_SIZES(X) X(8) X(9) X(10) X(11) X(12) X(13) X(14)
@@ -710,10 +809,11 @@ hipError_t launch_merge_p(const SortArray &a, uint32_t log_t, uint32_t n_tiles, 
 
 template <bool PAIRS>
 hipError_t launch_sort_regs_p(const SortArray &a, uint32_t log_t, uint32_t n_tiles,
-                              int32_t step_limit, bool lo, bool hi, int io_mode,
+                              int32_t step_limit, bool lo, bool hi, bool xch, int io_mode,
                               hipStream_t stream) {
 #define MELD_CASE(L) \
-    case L: return launch_sort_regs_l<PAIRS, L>(a, n_tiles, step_limit, lo, hi, io_mode, stream);
+    case L:          \
+        return launch_sort_regs_l<PAIRS, L>(a, n_tiles, step_limit, lo, hi, xch, io_mode, stream);
     switch (log_t) {
         MELD_REGS_SIZES(MELD_CASE)
         default: return hipErrorInvalidValue;
@@ -879,15 +979,15 @@ hipError_t launch_bitonic_global(const SortArray &a, uint32_t log_n, uint32_t m,
 }
 
 hipError_t launch_bitonic_sort_regs(const SortArray &a, uint32_t log_t, uint32_t n_tiles,
-                                    int32_t step_limit, bool meld_lo, bool meld_hi, int io_mode,
-                                    hipStream_t stream) {
+                                    int32_t step_limit, bool meld_lo, bool meld_hi, bool xch,
+                                    int io_mode, hipStream_t stream) {
     if (n_tiles == 0 || step_limit == 0) return hipSuccess;
     if (io_mode == kPlain) io_mode = kTail;  // no tail workspace: every tile is below n
     if (a.vals != nullptr)
-        return launch_sort_regs_p<true>(a, log_t, n_tiles, step_limit, meld_lo, meld_hi, io_mode,
-                                        stream);
-    return launch_sort_regs_p<false>(a, log_t, n_tiles, step_limit, meld_lo, meld_hi, io_mode,
-                                     stream);
+        return launch_sort_regs_p<true>(a, log_t, n_tiles, step_limit, meld_lo, meld_hi, xch,
+                                        io_mode, stream);
+    return launch_sort_regs_p<false>(a, log_t, n_tiles, step_limit, meld_lo, meld_hi, xch,
+                                     io_mode, stream);
 }
 
 hipError_t launch_bitonic_gather(const SortArray &a, uint32_t log_n, uint32_t m, uint32_t b_hi,

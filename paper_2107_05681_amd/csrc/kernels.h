@@ -65,12 +65,14 @@ hipError_t launch_bitonic_tile(const SortArray &a, uint32_t log_t, uint32_t n_ti
                                int threads, hipStream_t stream);
 
 // The whole network of every tile of 2^log_t elements (log_t in 8..14):
-// phases k <= 64 as the LDS comparator network in form meld_lo, phases
-// k >= 128 in register windows in form meld_hi. io_mode: plain, vector, tail
-// or sentinel. At most step_limit steps run (negative: all).
+// phases k <= 64 in form meld_lo, as the LDS comparator network (xch false)
+// or in registers with DPP lane exchanges (xch true); phases k >= 128 in
+// register windows in form meld_hi (with lane exchanges for the steps on
+// element bits 4 and 5 of a phase when xch). io_mode: plain, vector, tail or
+// sentinel. At most step_limit steps run (negative: all).
 hipError_t launch_bitonic_sort_regs(const SortArray &a, uint32_t log_t, uint32_t n_tiles,
-                                    int32_t step_limit, bool meld_lo, bool meld_hi, int io_mode,
-                                    hipStream_t stream);
+                                    int32_t step_limit, bool meld_lo, bool meld_hi, bool xch,
+                                    int io_mode, hipStream_t stream);
 
 // Steps j = 2^b_hi .. 2^b_lo of phase k = 2^m over all N = 2^log_n elements
 // in one pass through LDS: each workgroup gathers 2^(b_hi-b_lo+1) rows of
@@ -147,13 +149,15 @@ struct SegState {
 // Persistent grid size: CUs x resident 1024-lane workgroups (68 KiB of LDS).
 hipError_t seg_sort_grid(int device, uint32_t *grid);
 
-// Enqueues reset, classify, plan, scatter and the persistent sort. keys holds
+// Enqueues reset, classify, plan, scatter and the persistent sort (segments
+// above 128 keys: phases k <= 64 as the LDS comparator network, or with xch in
+// registers with DPP lane exchanges). keys holds
 // n_keys words (an offset above n_keys flags the call invalid), cls nseg
 // bytes, queue nseg words, work grid * kSegWorkWords words.
 hipError_t launch_segmented_sort(uint32_t *keys, uint32_t n_keys, const uint32_t *off,
                                  uint32_t nseg, SegState *st, uint8_t *cls, uint32_t *queue,
                                  uint32_t *work, uint32_t grid, bool meld_lo, bool meld_hi,
-                                 hipStream_t stream);
+                                 bool xch, hipStream_t stream);
 
 // Batcher's odd-even merge network on each bucket of 2^log_t keys
 // (oddeven.hip; log_t in 6..14, the last bucket ragged), at most max_steps

@@ -38,13 +38,17 @@ struct meld_ctx {
         const void *offsets;
         size_t nseg;
         uint32_t n_keys;
-        bool lo, hi;
+        bool lo, hi, xch;
         hipGraphExec_t exec;
     };
     std::list<SegGraph> seg_graphs;
     hipStream_t capture_stream = nullptr;
     bool use_graphs = true;
     uint32_t sort_log_tile = 0;  // 0: chosen per call
+    // Phases k <= 64 of the sorts: -1 the library's choice (lane exchanges
+    // under a fixed form, timed under MELD_AUTO), 0 the LDS comparator
+    // network, 1 registers with DPP lane exchanges.
+    int lane_exchange = -1;
     // Tuner: decisions per shape class, scratch for timed trials on copies of
     // the caller's data, and device counters for the divergence probes.
     meld::Tuner tuner;
@@ -277,10 +281,10 @@ meld_status ensure_seg(meld_ctx *ctx, size_t nseg) {
 
 // The graph of (keys, n_keys, offsets, nseg, forms), captured on first use.
 meld_status seg_graph(meld_ctx *ctx, uint32_t *keys, uint32_t n_keys, const uint32_t *offsets,
-                      size_t nseg, bool lo, bool hi, hipGraphExec_t *out) {
+                      size_t nseg, bool lo, bool hi, bool xch, hipGraphExec_t *out) {
     for (auto it = ctx->seg_graphs.begin(); it != ctx->seg_graphs.end(); ++it) {
         if (it->keys == keys && it->n_keys == n_keys && it->offsets == offsets &&
-            it->nseg == nseg && it->lo == lo && it->hi == hi) {
+            it->nseg == nseg && it->lo == lo && it->hi == hi && it->xch == xch) {
             ctx->seg_graphs.splice(ctx->seg_graphs.begin(), ctx->seg_graphs, it);
             *out = it->exec;
             return MELD_OK;
@@ -294,7 +298,7 @@ meld_status seg_graph(meld_ctx *ctx, uint32_t *keys, uint32_t n_keys, const uint
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
     hipError_t le = meld::launch_segmented_sort(keys, n_keys, offsets, (uint32_t)nseg,
                                                 ctx->seg_state, ctx->seg_cls, ctx->seg_queue,
-                                                ctx->seg_work, ctx->seg_grid, lo, hi,
+                                                ctx->seg_work, ctx->seg_grid, lo, hi, xch,
                                                 ctx->capture_stream);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(ctx->capture_stream, &graph);
@@ -310,7 +314,7 @@ meld_status seg_graph(meld_ctx *ctx, uint32_t *keys, uint32_t n_keys, const uint
         (void)hipGraphExecDestroy(ctx->seg_graphs.back().exec);
         ctx->seg_graphs.pop_back();
     }
-    ctx->seg_graphs.push_front({keys, offsets, nseg, n_keys, lo, hi, exec});
+    ctx->seg_graphs.push_front({keys, offsets, nseg, n_keys, lo, hi, xch, exec});
     *out = exec;
     return MELD_OK;
 }
@@ -321,7 +325,7 @@ uint32_t key_bound(size_t n_keys) {
 }
 
 meld_status segmented_impl(meld_ctx *ctx, uint32_t *keys, size_t n_keys, const uint32_t *offsets,
-                           size_t nseg, bool meld_lo, bool meld_hi, hipStream_t stream,
+                           size_t nseg, bool meld_lo, bool meld_hi, bool xch, hipStream_t stream,
                            const char *fn) {
     if (nseg == 0) return MELD_OK;
     if (nseg >= (1ull << 31)) return fail(MELD_EINVAL, "%s: nseg = %zu >= 2^31", fn, nseg);
@@ -338,12 +342,13 @@ meld_status segmented_impl(meld_ctx *ctx, uint32_t *keys, size_t n_keys, const u
     if (!ctx->use_graphs || cs != hipStreamCaptureStatusNone) {
         e = meld::launch_segmented_sort(keys, key_bound(n_keys), offsets, (uint32_t)nseg,
                                         ctx->seg_state, ctx->seg_cls, ctx->seg_queue,
-                                        ctx->seg_work, ctx->seg_grid, meld_lo, meld_hi, stream);
+                                        ctx->seg_work, ctx->seg_grid, meld_lo, meld_hi, xch,
+                                        stream);
         if (e != hipSuccess) return hip_fail(e, "segmented sort launch");
         return MELD_OK;
     }
     hipGraphExec_t exec = nullptr;
-    st = seg_graph(ctx, keys, key_bound(n_keys), offsets, nseg, meld_lo, meld_hi, &exec);
+    st = seg_graph(ctx, keys, key_bound(n_keys), offsets, nseg, meld_lo, meld_hi, xch, &exec);
     if (st != MELD_OK) return st;
     e = hipGraphLaunch(exec, stream);
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
@@ -364,6 +369,7 @@ bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
 struct SortPlan {
     uint32_t log_t;
     bool lo, hi;
+    bool xch;  // phases k <= 64 in registers with lane exchanges
 };
 
 constexpr uint32_t kMinLogRegsTile = 8;  // smallest tile of the register-window kernels
@@ -509,7 +515,8 @@ meld_status sort_impl(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n
         e = mark(0);
         if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
         if (log_t >= kMinLogRegsTile)
-            e = meld::launch_bitonic_sort_regs(a, log_t, 1, steps, plan.lo, plan.hi, io, stream);
+            e = meld::launch_bitonic_sort_regs(a, log_t, 1, steps, plan.lo, plan.hi, plan.xch, io,
+                                               stream);
         else
             e = meld::launch_bitonic_tile(a, log_t, 1, 1, log_t, 0, steps, plan.lo, plan.hi, io,
                                           tile_threads(log_t), stream);
@@ -550,8 +557,8 @@ meld_status sort_impl(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n
         const int32_t steps = take(p.steps);
         switch (p.kind) {
             case PassKind::kLocal:
-                e = meld::launch_bitonic_sort_regs(a, log_t, n_tiles, steps, plan.lo, plan.hi, io,
-                                                   stream);
+                e = meld::launch_bitonic_sort_regs(a, log_t, n_tiles, steps, plan.lo, plan.hi,
+                                                   plan.xch, io, stream);
                 break;
             case PassKind::kGather:
                 e = meld::launch_bitonic_gather(a, log_n, p.m, p.b_hi, p.b_lo, steps, io, stream);
@@ -578,9 +585,12 @@ uint32_t plan_log_tile(const meld_ctx *ctx, bool pairs, uint32_t log_n) {
     return default_log_tile(pairs, log_n);
 }
 
+// Lane exchanges unless the context asks for the LDS comparator network.
+bool plan_xch(const meld_ctx *ctx) { return ctx->lane_exchange != 0; }
+
 SortPlan fixed_plan(const meld_ctx *ctx, bool pairs, size_t n, meld_variant v) {
     const bool m = use_melded(v);
-    return SortPlan{plan_log_tile(ctx, pairs, log2_ceil(n)), m, m};
+    return SortPlan{plan_log_tile(ctx, pairs, log2_ceil(n)), m, m, plan_xch(ctx)};
 }
 
 // Probe of one tile's network: mixed-wave fraction of the phases k <= 64 and
@@ -602,12 +612,15 @@ meld_status probe_network(meld_ctx *ctx, uint32_t log_t, hipStream_t s, double *
     return MELD_OK;
 }
 
-// Tuning-cache key of a sort shape class (array size class, pairs, forced tile).
+// Tuning-cache key of a sort shape class (array size class, pairs, forced
+// tile, forced low-phase path).
 std::string sort_tune_key(const meld_ctx *ctx, bool pairs, uint32_t log_n) {
     const uint32_t forced =
         ctx->sort_log_tile ? std::min(ctx->sort_log_tile, max_log_tile(pairs)) : 0;
-    return forced ? fmt("n=%u pairs=%d t=%u", log_n, pairs ? 1 : 0, forced)
-                  : fmt("n=%u pairs=%d", log_n, pairs ? 1 : 0);
+    std::string k = forced ? fmt("n=%u pairs=%d t=%u", log_n, pairs ? 1 : 0, forced)
+                           : fmt("n=%u pairs=%d", log_n, pairs ? 1 : 0);
+    if (ctx->lane_exchange >= 0) k += fmt(" x=%d", ctx->lane_exchange);
+    return k;
 }
 
 // The tuned plan of a shape class, if the tuner holds a usable one.
@@ -615,7 +628,7 @@ bool cached_sort_plan(const meld_ctx *ctx, bool pairs, uint32_t log_n, SortPlan 
     if (const meld::TuneEntry *e = ctx->tuner.find("sort", sort_tune_key(ctx, pairs, log_n))) {
         const uint32_t t = (uint32_t)e->log_t;
         if (t >= kMinLogRegsTile && t <= max_log_tile(pairs)) {
-            *out = SortPlan{t, e->lo != 0, e->hi != 0};
+            *out = SortPlan{t, e->lo != 0, e->hi != 0, e->xch != 0};
             return true;
         }
     }
@@ -632,7 +645,7 @@ meld_status auto_sort_plan(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, siz
     const uint32_t forced = ctx->sort_log_tile ? std::min(ctx->sort_log_tile, max_t) : 0;
     const std::string key = sort_tune_key(ctx, pairs, log_n);
     if (cached_sort_plan(ctx, pairs, log_n, out)) return MELD_OK;
-    *out = SortPlan{plan_log_tile(ctx, pairs, log_n), true, true};
+    *out = SortPlan{plan_log_tile(ctx, pairs, log_n), true, true, plan_xch(ctx)};
     if (capturing(s)) return MELD_OK;  // no timing inside a capture; untuned default
     // Candidate tiles: from one that leaves a few hundred tiles up to the
     // largest (a single tile when everything fits); the forced one alone.
@@ -653,8 +666,15 @@ meld_status auto_sort_plan(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, siz
     std::vector<SortPlan> cands;
     std::vector<double> ms;
     std::vector<int> flo, fhi;
+    // Low-phase paths: the forced one, else both (LDS network, lane exchanges).
+    std::vector<bool> xchs;
+    if (ctx->lane_exchange >= 0)
+        xchs.push_back(ctx->lane_exchange != 0);
+    else
+        xchs = {false, true};
     for (uint32_t t : tiles)
-        for (int f = 0; f < 4; ++f) cands.push_back(SortPlan{t, (f & 1) != 0, (f & 2) != 0});
+        for (bool x : xchs)
+            for (int f = 0; f < 4; ++f) cands.push_back(SortPlan{t, (f & 1) != 0, (f & 2) != 0, x});
     const int reps = n >= (1u << 24) ? 2 : 3;
     for (const SortPlan &p : cands) {
         double t = 0;
@@ -684,6 +704,7 @@ meld_status auto_sort_plan(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, siz
     e.lo = out->lo;
     e.hi = out->hi;
     e.log_t = (int)out->log_t;
+    e.xch = out->xch ? 1 : 0;
     e.form = out->lo ? 1 : 0;
     e.ms = ms[pick];
     e.mixed_lo = mixed_lo;
@@ -696,8 +717,9 @@ meld_status auto_sort_plan(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, siz
 // MELD_AUTO for a segmented sort: the tuned forms of this shape class, timing
 // the four per-stage combinations on a scratch copy the first time.
 meld_status auto_seg_forms(meld_ctx *ctx, uint32_t *keys, size_t n_keys, const uint32_t *offsets,
-                           size_t nseg, hipStream_t s, bool *lo, bool *hi) {
+                           size_t nseg, hipStream_t s, bool *lo, bool *hi, bool *xch) {
     *lo = *hi = true;
+    *xch = plan_xch(ctx);
     if (capturing(s)) {
         return MELD_OK;
     }
@@ -709,10 +731,12 @@ meld_status auto_seg_forms(meld_ctx *ctx, uint32_t *keys, size_t n_keys, const u
     if (total > n_keys)
         return fail(MELD_EINVAL, "meld_segmented_sort_u32: offsets[nseg] = %u > n_keys = %zu",
                     total, n_keys);
-    const std::string key = fmt("nseg=%u total=%u", log2_ceil(nseg), log2_ceil(total));
+    std::string key = fmt("nseg=%u total=%u", log2_ceil(nseg), log2_ceil(total));
+    if (ctx->lane_exchange >= 0) key += fmt(" x=%d", ctx->lane_exchange);
     if (const meld::TuneEntry *t = ctx->tuner.find("segsort", key)) {
         *lo = t->lo != 0;
         *hi = t->hi != 0;
+        *xch = t->xch != 0;
         return MELD_OK;
     }
     if (total == 0) return MELD_OK;
@@ -721,9 +745,11 @@ meld_status auto_seg_forms(meld_ctx *ctx, uint32_t *keys, size_t n_keys, const u
     st = ensure_seg(ctx, nseg);
     if (st != MELD_OK) return st;
     std::vector<double> ms;
-    std::vector<int> flo, fhi;
-    for (int f = 0; f < 4; ++f) {
+    std::vector<int> flo, fhi, fx;
+    const int paths = ctx->lane_exchange >= 0 ? 1 : 2;
+    for (int f = 0; f < 4 * paths; ++f) {
         const bool l = (f & 1) != 0, h = (f & 2) != 0;
+        const bool x = ctx->lane_exchange >= 0 ? ctx->lane_exchange != 0 : (f & 4) != 0;
         double t = 0;
         st = time_median(
             s, 3,
@@ -735,7 +761,7 @@ meld_status auto_seg_forms(meld_ctx *ctx, uint32_t *keys, size_t n_keys, const u
             [&]() -> meld_status {
                 hipError_t r = meld::launch_segmented_sort(
                     ctx->tune_buf, total, offsets, (uint32_t)nseg, ctx->seg_state, ctx->seg_cls,
-                    ctx->seg_queue, ctx->seg_work, ctx->seg_grid, l, h, s);
+                    ctx->seg_queue, ctx->seg_work, ctx->seg_grid, l, h, x, s);
                 return r == hipSuccess ? MELD_OK : hip_fail(r, "segmented sort launch");
             },
             &t);
@@ -743,6 +769,7 @@ meld_status auto_seg_forms(meld_ctx *ctx, uint32_t *keys, size_t n_keys, const u
         ms.push_back(t);
         flo.push_back(l);
         fhi.push_back(h);
+        fx.push_back(x);
     }
     unsigned long long c[4] = {0};
     st = run_probe(ctx, s, 4, c, [&](unsigned long long *out) {
@@ -751,20 +778,22 @@ meld_status auto_seg_forms(meld_ctx *ctx, uint32_t *keys, size_t n_keys, const u
     if (st != MELD_OK) return st;
     const double mixed_lo = c[1] ? (double)c[0] / (double)c[1] : 0.0;
     const double mixed_hi = c[3] ? (double)c[2] / (double)c[3] : 0.0;
-    const int pick = meld::choose(4, ms.data(), flo.data(), fhi.data(), mixed_lo, mixed_hi,
-                                  ctx->theta, ctx->tie);
+    const int pick = meld::choose((int)ms.size(), ms.data(), flo.data(), fhi.data(), mixed_lo,
+                                  mixed_hi, ctx->theta, ctx->tie);
     *lo = flo[pick] != 0;
     *hi = fhi[pick] != 0;
+    *xch = fx[pick] != 0;
     meld::TuneEntry te;
     te.op = "segsort";
     te.key = key;
     te.lo = *lo;
     te.hi = *hi;
+    te.xch = *xch;
     te.form = *lo ? 1 : 0;
     te.ms = ms[pick];
     te.mixed_lo = mixed_lo;
     te.mixed_hi = mixed_hi;
-    te.trials = 4;
+    te.trials = (int)ms.size();
     ctx->tuner.put(te);
     return MELD_OK;
 }
@@ -1098,10 +1127,11 @@ meld_status meld_sort_plan_describe(meld_ctx *ctx, size_t n, int with_payload,
     const bool pairs = with_payload != 0;
     const uint32_t log_n = n <= 1 ? 0 : log2_ceil(n);
     const bool m = variant == MELD_AUTO || use_melded(variant);
-    SortPlan plan{default_log_tile(pairs, log_n), m, m};
+    SortPlan plan{default_log_tile(pairs, log_n), m, m, true};
     bool tuned = false;
     if (ctx != nullptr) {
         plan.log_t = plan_log_tile(ctx, pairs, log_n);
+        plan.xch = plan_xch(ctx);
         if (variant == MELD_AUTO) tuned = cached_sort_plan(ctx, pairs, log_n, &plan);
     }
     std::string d = fmt("{\"n\": %zu, \"log_n\": %u, \"pairs\": %s, \"tuned\": %s", n, log_n,
@@ -1110,9 +1140,11 @@ meld_status meld_sort_plan_describe(meld_ctx *ctx, size_t n, int with_payload,
     std::string list;
     if (n > 1) {
         const std::vector<SortPass> passes = sort_passes(plan, pairs, log_n);
-        d += fmt(", \"log_tile\": %u, \"low\": \"%s\", \"high\": \"%s\"",
+        const bool regs_kernel = passes[0].kind != PassKind::kTile || log_n >= kMinLogRegsTile;
+        d += fmt(", \"log_tile\": %u, \"low\": \"%s\", \"high\": \"%s\", \"low_path\": \"%s\"",
                  passes[0].kind == PassKind::kTile ? std::max<uint32_t>(log_n, 1) : plan.log_t,
-                 plan.lo ? "melded" : "divergent", plan.hi ? "melded" : "divergent");
+                 plan.lo ? "melded" : "divergent", plan.hi ? "melded" : "divergent",
+                 !regs_kernel ? "lds" : plan.xch ? "lane_exchange" : "lds");
         for (const SortPass &p : passes) {
             if (!list.empty()) list += ", ";
             list += fmt("{\"kind\": \"%s\", \"steps\": %u", pass_name(p.kind), p.steps);
@@ -1324,7 +1356,7 @@ meld_status meld_segmented_sort_u32(meld_ctx *ctx, uint32_t *keys, size_t n_keys
     if ((unsigned)variant > MELD_MELDED_INPLACE)
         return fail(MELD_EINVAL, "meld_segmented_sort_u32: bad variant");
     const hipStream_t s = static_cast<hipStream_t>(stream);
-    bool lo = use_melded(variant), hi = lo;
+    bool lo = use_melded(variant), hi = lo, xch = plan_xch(ctx);
     if (variant == MELD_AUTO && nseg > 0 && nseg < (1ull << 31)) {
         DeviceGuard g(ctx->device);
         if (!is_device_ptr(ctx, keys) || !is_device_ptr(ctx, offsets))
@@ -1332,10 +1364,11 @@ meld_status meld_segmented_sort_u32(meld_ctx *ctx, uint32_t *keys, size_t n_keys
                         "meld_segmented_sort_u32: keys and offsets must be device pointers on "
                         "device %d",
                         ctx->device);
-        meld_status st = auto_seg_forms(ctx, keys, n_keys, offsets, nseg, s, &lo, &hi);
+        meld_status st = auto_seg_forms(ctx, keys, n_keys, offsets, nseg, s, &lo, &hi, &xch);
         if (st != MELD_OK) return st;
     }
-    return segmented_impl(ctx, keys, n_keys, offsets, nseg, lo, hi, s, "meld_segmented_sort_u32");
+    return segmented_impl(ctx, keys, n_keys, offsets, nseg, lo, hi, xch, s,
+                          "meld_segmented_sort_u32");
 }
 
 meld_status meld_segmented_sort_u32_staged(meld_ctx *ctx, uint32_t *keys, size_t n_keys,
@@ -1346,7 +1379,7 @@ meld_status meld_segmented_sort_u32_staged(meld_ctx *ctx, uint32_t *keys, size_t
     if ((unsigned)low_phases > MELD_MELDED_INPLACE || (unsigned)high_phases > MELD_MELDED_INPLACE)
         return fail(MELD_EINVAL, "meld_segmented_sort_u32_staged: bad variant");
     return segmented_impl(ctx, keys, n_keys, offsets, nseg, use_melded(low_phases),
-                          use_melded(high_phases), static_cast<hipStream_t>(stream),
+                          use_melded(high_phases), plan_xch(ctx), static_cast<hipStream_t>(stream),
                           "meld_segmented_sort_u32_staged");
 }
 
@@ -1435,6 +1468,12 @@ meld_status meld_set_option(meld_ctx *ctx, meld_option option, int64_t value) {
                 return fail(MELD_EINVAL, "meld_set_option: sort tile 2^%lld outside 2^%u .. 2^%d",
                             (long long)value, kMinLogRegsTile, meld::kMaxLogTileKeys);
             ctx->sort_log_tile = (uint32_t)value;
+            return MELD_OK;
+        case MELD_OPT_LANE_EXCHANGE:
+            if (value < -1 || value > 1)
+                return fail(MELD_EINVAL, "meld_set_option: lane exchange %lld not in {-1, 0, 1}",
+                            (long long)value);
+            ctx->lane_exchange = (int)value;
             return MELD_OK;
         default:
             return fail(MELD_EINVAL, "meld_set_option: unknown option %d", (int)option);

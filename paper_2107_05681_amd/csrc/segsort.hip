@@ -31,6 +31,7 @@
 // padding) in a per-workgroup scratch of 2^16 words. All of it stays inside
 // one workgroup, so no grid-wide synchronisation is needed.
 #include "device_common.h"
+#include "exchange.h"
 #include "kernels.h"
 #include "network.h"
 
@@ -44,6 +45,9 @@ constexpr uint32_t kSmallMax = 128;
 constexpr uint32_t kSmallClassMax = kSegSmallClassMax;
 
 constexpr int kSegE = 16;  // keys per lane in the register phases
+// Registers per branch of a divergent lane step: the partner values of 8
+// registers at a time keep the kernel within its 64 VGPRs without spills.
+constexpr int kSegLaneGroup = 8;
 
 // Hides v's value from the optimiser at this point: the LDS and global
 // addresses derived from it are then computed where they are used instead of
@@ -310,13 +314,40 @@ __device__ __forceinline__ void phase_windows(uint32_t (&e)[kSegE], uint32_t *s,
     }
 }
 
+// Phase steps on element bits hi_bit .. 0 ending in layout W0 (register r of
+// lane t holds element 16 t + r): four-bit windows with bases hi_bit-3,
+// hi_bit-7, ... while the top bit is at least 6, then W0, where the steps on
+// element bits 5 and 4 are DPP exchanges with lane t ^ 2 and t ^ 1 and bits
+// 3 .. 0 registers. One LDS transpose fewer than phase_windows when hi_bit is
+// 8, 9, 12 or 13.
+template <bool MELDED>
+__device__ __forceinline__ void phase_windows_xch(uint32_t (&e)[kSegE], uint32_t *s, uint32_t t,
+                                                  uint32_t &cur, int hi_bit, bool up) {
+    int32_t unlimited = 0x7FFFFFFF;
+    int top = hi_bit;
+#pragma unroll 1
+    while (top >= 6) {
+        const uint32_t B = (uint32_t)(top - 3);
+        to_window(e, s, t, cur, B);
+        seg_reg_steps<MELDED>(e, 3, up, unlimited);
+        top = (int)B - 1;
+    }
+    to_window(e, s, t, cur, 0);
+    if (top >= 5) lane_step<1, MELDED, kSegLaneGroup>(e, up, ((t >> 1) & 1u) == 0);
+    if (top >= 4) lane_step<0, MELDED, kSegLaneGroup>(e, up, (t & 1u) == 0);
+    seg_reg_steps<MELDED>(e, top < 3 ? top : 3, up, unlimited);
+}
+
 // A team of 2^(m-4) lanes (lane t) sorts the 2^m positions cbase + i of a
 // segment (8 <= m <= 14): positions below len come from keys[lo + q], the
 // others are padding. s is the team's own LDS region of 17 * 2^(m-4) words.
 // With work != nullptr every result goes to work[q]; otherwise results
 // below len go to keys and the padding is dropped. The direction of phase p
 // is bit p of cbase + i, so a chunk with bit m of cbase set ends descending.
-template <bool MELD_LO, bool MELD_HI>
+// XCH: phases k <= 64 in registers with lane exchanges (the tile moved to
+// layout W0 first) and the later phases ending each in W0; otherwise the LDS
+// comparator network and four-bit windows.
+template <bool MELD_LO, bool MELD_HI, bool XCH>
 __device__ __forceinline__ void team_sort(uint32_t *__restrict__ keys,
                                           uint32_t *__restrict__ work, uint32_t *s, uint32_t lo,
                                           uint32_t len, uint32_t m, uint32_t cbase, uint32_t t) {
@@ -332,24 +363,36 @@ __device__ __forceinline__ void team_sort(uint32_t *__restrict__ keys,
         const uint32_t rb = cbase + ((uint32_t)r << lt);
         e[r] = rb + tl < len ? (keys + lo + rb)[tl] : kPad;
     }
-#pragma unroll
-    for (int r = 0; r < kSegE; ++r) s[low_swz<uint32_t>(t | ((uint32_t)r << lt))] = e[r];
-    __syncthreads();
-    lds_network_low<uint32_t, MELD_LO, 8, true>(s, cbase, 6, t, 1u << lt, -1);
-    __syncthreads();
-    // Phase 2^7 starts in window 3 (element bits 3..6), read from the natural
-    // order the comparator network leaves in s.
-    uint32_t cur = 3;
-    {
-        const uint32_t tb = window_tpart(t, cur);
-#pragma unroll
-        for (int r = 0; r < kSegE; ++r) e[r] = s[low_swz<uint32_t>(tb | ((uint32_t)r << cur))];
-        __syncthreads();
-    }
+    uint32_t cur;
+    if constexpr (XCH) {
+        cur = lt;
+        to_window(e, s, t, cur, 0);
+        xch_network_low<MELD_LO, kSegLaneGroup>(e, t, -1);
 #pragma unroll 1
-    for (uint32_t p = 7; p <= m; ++p) {
-        const bool up = (((cbase >> p) | (t >> (p - 4))) & 1u) == 0;
-        phase_windows<MELD_HI>(e, s, t, cur, (int)p - 1, up);
+        for (uint32_t p = 7; p <= m; ++p) {
+            const bool up = (((cbase >> p) | (t >> (p - 4))) & 1u) == 0;
+            phase_windows_xch<MELD_HI>(e, s, t, cur, (int)p - 1, up);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < kSegE; ++r) s[low_swz<uint32_t>(t | ((uint32_t)r << lt))] = e[r];
+        __syncthreads();
+        lds_network_low<uint32_t, MELD_LO, 8, true>(s, cbase, 6, t, 1u << lt, -1);
+        __syncthreads();
+        // Phase 2^7 starts in window 3 (element bits 3..6), read from the natural
+        // order the comparator network leaves in s.
+        cur = 3;
+        {
+            const uint32_t tb = window_tpart(t, cur);
+#pragma unroll
+            for (int r = 0; r < kSegE; ++r) e[r] = s[low_swz<uint32_t>(tb | ((uint32_t)r << cur))];
+            __syncthreads();
+        }
+#pragma unroll 1
+        for (uint32_t p = 7; p <= m; ++p) {
+            const bool up = (((cbase >> p) | (t >> (p - 4))) & 1u) == 0;
+            phase_windows<MELD_HI>(e, s, t, cur, (int)p - 1, up);
+        }
     }
     to_window(e, s, t, cur, lt);
     if (work != nullptr) {
@@ -398,7 +441,9 @@ __device__ void seg_global_steps(uint32_t *__restrict__ work, uint32_t m, uint32
 // Steps j = 2^13 .. 1 of a phase on chunk cbase of a segment in the
 // workgroup's scratch; the direction is the same for the whole chunk, so
 // both forms coincide. The last phase writes the positions below len to the
-// caller's keys, earlier ones write back to the scratch.
+// caller's keys, earlier ones write back to the scratch. XCH: the steps end
+// in layout W0 with lane exchanges (three transposes instead of four).
+template <bool XCH>
 __device__ void chunk_merge(uint32_t *__restrict__ keys, uint32_t *__restrict__ work, uint32_t *s,
                             uint32_t lo, uint32_t len, uint32_t cbase, uint32_t t, bool up,
                             bool last) {
@@ -409,7 +454,10 @@ __device__ void chunk_merge(uint32_t *__restrict__ keys, uint32_t *__restrict__ 
 #pragma unroll
     for (int r = 0; r < kSegE; ++r) e[r] = (work + cbase + ((uint32_t)r << lt))[tl];
     uint32_t cur = lt;
-    phase_windows<true>(e, s, t, cur, (int)kSegLogChunk - 1, up);
+    if constexpr (XCH)
+        phase_windows_xch<true>(e, s, t, cur, (int)kSegLogChunk - 1, up);
+    else
+        phase_windows<true>(e, s, t, cur, (int)kSegLogChunk - 1, up);
     to_window(e, s, t, cur, lt);
     if (last) {
 #pragma unroll
@@ -425,20 +473,22 @@ __device__ void chunk_merge(uint32_t *__restrict__ keys, uint32_t *__restrict__ 
 
 // A segment of class 15..16 in 2^14-key chunks (the whole workgroup),
 // staged in the workgroup's scratch of 2^16 words.
-template <bool MELD_LO, bool MELD_HI>
+template <bool MELD_LO, bool MELD_HI, bool XCH>
 __device__ void sort_chunked(uint32_t *__restrict__ keys, uint32_t *s, uint32_t *__restrict__ work,
                              uint32_t lo, uint32_t len, uint32_t m, uint32_t tid) {
     const uint32_t chunks = 1u << (m - kSegLogChunk);
 #pragma unroll 1
     for (uint32_t h = 0; h < chunks; ++h)
-        team_sort<MELD_LO, MELD_HI>(keys, work, s, lo, len, kSegLogChunk, h << kSegLogChunk, tid);
+        team_sort<MELD_LO, MELD_HI, XCH>(keys, work, s, lo, len, kSegLogChunk, h << kSegLogChunk,
+                                         tid);
 #pragma unroll 1
     for (uint32_t p = kSegLogChunk + 1; p <= m; ++p) {
         seg_global_steps(work, m, p, tid);
 #pragma unroll 1
         for (uint32_t h = 0; h < chunks; ++h) {
             const uint32_t cbase = h << kSegLogChunk;
-            chunk_merge(keys, work, s, lo, len, cbase, tid, ((cbase >> p) & 1u) == 0, p == m);
+            chunk_merge<XCH>(keys, work, s, lo, len, cbase, tid, ((cbase >> p) & 1u) == 0,
+                             p == m);
         }
     }
 }
@@ -457,7 +507,7 @@ __device__ void sort_small(uint32_t *__restrict__ keys, uint32_t *ws, uint32_t l
     if (lane + 64 < len) keys[lo + lane + 64] = ws[lane + 64];
 }
 
-template <bool MELD_LO, bool MELD_HI>
+template <bool MELD_LO, bool MELD_HI, bool XCH>
 // At most 64 VGPRs (8 waves per SIMD): two 1024-lane workgroups fit on a CU
 // (2 x 68 KiB of LDS), which hides the barriers and LDS latency of the
 // network steps better than one (measured on the 4096-segment workload: 19 %
@@ -497,7 +547,7 @@ __global__ __launch_bounds__(kSegThreads, 8) void seg_sort_kernel(uint32_t *__re
             if (c > kSegLogChunk) {
                 const uint32_t seg = queue[st->base[c] + k];
                 const uint32_t lo = off[seg];
-                sort_chunked<MELD_LO, MELD_HI>(keys, s, work, lo, off[seg + 1] - lo, c, tid);
+                sort_chunked<MELD_LO, MELD_HI, XCH>(keys, s, work, lo, off[seg + 1] - lo, c, tid);
             } else {
                 const uint32_t lt = c - 4;
                 const uint32_t team = tid >> lt, t = tid & ((1u << lt) - 1);
@@ -508,8 +558,8 @@ __global__ __launch_bounds__(kSegThreads, 8) void seg_sort_kernel(uint32_t *__re
                     lo = off[seg];
                     len = off[seg + 1] - lo;
                 }
-                team_sort<MELD_LO, MELD_HI>(keys, nullptr, s + team * (17u << lt), lo, len, c, 0,
-                                            t);
+                team_sort<MELD_LO, MELD_HI, XCH>(keys, nullptr, s + team * (17u << lt), lo, len, c,
+                                                 0, t);
             }
         } else {
             const uint32_t w = tid >> 6;
@@ -525,17 +575,27 @@ __global__ __launch_bounds__(kSegThreads, 8) void seg_sort_kernel(uint32_t *__re
     }
 }
 
-template <bool LO, bool HI>
+template <bool LO, bool HI, bool XCH>
 hipError_t launch_sort_t(uint32_t *keys, const uint32_t *off, const uint32_t *queue, SegState *st,
                          uint32_t *work, uint32_t grid, hipStream_t stream) {
-    hipLaunchKernelGGL((seg_sort_kernel<LO, HI>), dim3(grid), dim3(kSegThreads),
+    hipLaunchKernelGGL((seg_sort_kernel<LO, HI, XCH>), dim3(grid), dim3(kSegThreads),
                        kSegLdsWords * sizeof(uint32_t), stream, keys, off, queue, st, work);
     return hipGetLastError();
 }
 
-template <bool LO, bool HI>
+template <bool XCH>
+hipError_t launch_sort_x(uint32_t *keys, const uint32_t *off, const uint32_t *queue, SegState *st,
+                         uint32_t *work, uint32_t grid, bool lo, bool hi, hipStream_t stream) {
+    if (lo)
+        return hi ? launch_sort_t<true, true, XCH>(keys, off, queue, st, work, grid, stream)
+                  : launch_sort_t<true, false, XCH>(keys, off, queue, st, work, grid, stream);
+    return hi ? launch_sort_t<false, true, XCH>(keys, off, queue, st, work, grid, stream)
+              : launch_sort_t<false, false, XCH>(keys, off, queue, st, work, grid, stream);
+}
+
+template <bool LO, bool HI, bool XCH>
 hipError_t allow_big_lds() {
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(seg_sort_kernel<LO, HI>),
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(seg_sort_kernel<LO, HI, XCH>),
                                hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)(kSegLdsWords * sizeof(uint32_t)));
 }
@@ -548,12 +608,24 @@ hipError_t seg_sort_grid(int device, uint32_t *grid) {
     if (e != hipSuccess) return e;
     int per_cu = 0;
     // The LDS limit is raised for every form up front, outside any capture.
-    for (hipError_t r : {allow_big_lds<true, true>(), allow_big_lds<true, false>(),
-                         allow_big_lds<false, true>(), allow_big_lds<false, false>()})
+    for (hipError_t r :
+         {allow_big_lds<true, true, false>(), allow_big_lds<true, false, false>(),
+          allow_big_lds<false, true, false>(), allow_big_lds<false, false, false>(),
+          allow_big_lds<true, true, true>(), allow_big_lds<true, false, true>(),
+          allow_big_lds<false, true, true>(), allow_big_lds<false, false, true>()})
         if (r != hipSuccess) return r;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, reinterpret_cast<const void *>(seg_sort_kernel<true, true>), kSegThreads,
-        kSegLdsWords * sizeof(uint32_t));
+    // The grid is sized for the form with the fewest resident workgroups.
+    per_cu = 1 << 30;
+    for (const void *k : {reinterpret_cast<const void *>(seg_sort_kernel<true, true, false>),
+                          reinterpret_cast<const void *>(seg_sort_kernel<false, false, false>),
+                          reinterpret_cast<const void *>(seg_sort_kernel<true, true, true>),
+                          reinterpret_cast<const void *>(seg_sort_kernel<false, false, true>)}) {
+        int b = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k, kSegThreads,
+                                                         kSegLdsWords * sizeof(uint32_t));
+        if (e != hipSuccess) return e;
+        if (b < per_cu) per_cu = b;
+    }
     if (e != hipSuccess) return e;
     if (per_cu < 1) per_cu = 1;
     *grid = (uint32_t)(cus * per_cu);
@@ -563,7 +635,7 @@ hipError_t seg_sort_grid(int device, uint32_t *grid) {
 hipError_t launch_segmented_sort(uint32_t *keys, uint32_t n_keys, const uint32_t *off,
                                  uint32_t nseg, SegState *st, uint8_t *cls, uint32_t *queue,
                                  uint32_t *work, uint32_t grid, bool meld_lo, bool meld_hi,
-                                 hipStream_t stream) {
+                                 bool xch, hipStream_t stream) {
     if (nseg == 0) return hipSuccess;
     const uint32_t blocks = (nseg + 255) / 256;
     hipLaunchKernelGGL(seg_reset_kernel, dim3(1), dim3(64), 0, stream, st);
@@ -574,11 +646,8 @@ hipError_t launch_segmented_sort(uint32_t *keys, uint32_t n_keys, const uint32_t
                        queue);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (meld_lo)
-        return meld_hi ? launch_sort_t<true, true>(keys, off, queue, st, work, grid, stream)
-                       : launch_sort_t<true, false>(keys, off, queue, st, work, grid, stream);
-    return meld_hi ? launch_sort_t<false, true>(keys, off, queue, st, work, grid, stream)
-                   : launch_sort_t<false, false>(keys, off, queue, st, work, grid, stream);
+    return xch ? launch_sort_x<true>(keys, off, queue, st, work, grid, meld_lo, meld_hi, stream)
+               : launch_sort_x<false>(keys, off, queue, st, work, grid, meld_lo, meld_hi, stream);
 }
 
 }  // namespace meld

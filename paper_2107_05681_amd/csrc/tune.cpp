@@ -10,14 +10,19 @@ namespace meld {
 
 namespace {
 
+// 2: entries carry the sorts' low-phase path (xch); files of version 1 are
+// ignored (their decisions predate that choice).
+constexpr int kTuneFileVersion = 2;
+
 std::string entry_key(const std::string &op, const std::string &key) { return op + "|" + key; }
 
 std::string to_json(const TuneEntry &e) {
     char buf[512];
     snprintf(buf, sizeof buf,
              "{\"op\": \"%s\", \"key\": \"%s\", \"lo\": %d, \"hi\": %d, \"log_t\": %d, "
-             "\"form\": %d, \"ms\": %.6f, \"mixed_lo\": %.6f, \"mixed_hi\": %.6f, \"trials\": %d}",
-             e.op.c_str(), e.key.c_str(), e.lo, e.hi, e.log_t, e.form, e.ms, e.mixed_lo,
+             "\"xch\": %d, \"form\": %d, \"ms\": %.6f, \"mixed_lo\": %.6f, \"mixed_hi\": %.6f, "
+             "\"trials\": %d}",
+             e.op.c_str(), e.key.c_str(), e.lo, e.hi, e.log_t, e.xch, e.form, e.ms, e.mixed_lo,
              e.mixed_hi, e.trials);
     return buf;
 }
@@ -38,7 +43,7 @@ bool Tuner::attach(const std::string &path) {
             if (sscanf(line.c_str(), " {\"version\": %d, \"arch\": \"%127[^\"]\", \"runtime\": %d",
                        &version, arch, &runtime) != 3)
                 return false;
-            header_ok = version == 1 && arch_ == arch && runtime_ == runtime;
+            header_ok = version == kTuneFileVersion && arch_ == arch && runtime_ == runtime;
             continue;
         }
         if (line.find("{\"op\"") == std::string::npos) continue;
@@ -46,10 +51,10 @@ bool Tuner::attach(const std::string &path) {
         TuneEntry e;
         if (sscanf(line.c_str(),
                    " {\"op\": \"%31[^\"]\", \"key\": \"%127[^\"]\", \"lo\": %d, \"hi\": %d, "
-                   "\"log_t\": %d, \"form\": %d, \"ms\": %lf, \"mixed_lo\": %lf, "
+                   "\"log_t\": %d, \"xch\": %d, \"form\": %d, \"ms\": %lf, \"mixed_lo\": %lf, "
                    "\"mixed_hi\": %lf, \"trials\": %d",
-                   op, key, &e.lo, &e.hi, &e.log_t, &e.form, &e.ms, &e.mixed_lo, &e.mixed_hi,
-                   &e.trials) != 10)
+                   op, key, &e.lo, &e.hi, &e.log_t, &e.xch, &e.form, &e.ms, &e.mixed_lo,
+                   &e.mixed_hi, &e.trials) != 11)
             return false;
         e.op = op;
         e.key = key;
@@ -72,7 +77,7 @@ void Tuner::put(const TuneEntry &e) {
 
 std::string Tuner::describe() const {
     std::ostringstream o;
-    o << "{\"version\": 1, \"arch\": \"" << arch_ << "\", \"runtime\": " << runtime_
+    o << "{\"version\": " << kTuneFileVersion << ", \"arch\": \"" << arch_ << "\", \"runtime\": " << runtime_
       << ", \"entries\": [\n";
     size_t i = 0;
     for (auto &kv : entries_) {

@@ -13,6 +13,7 @@ struct TuneEntry {
     int lo = 1;        // form of the phases k <= 64 (or of the region): 1 melded, 0 divergent
     int hi = 1;        // form of the phases k >= 128
     int log_t = 0;     // sort tile size (log2), 0 if not applicable
+    int xch = 0;       // sorts: phases k <= 64 with lane exchanges (1) or the LDS network (0)
     int form = 0;      // region: 0 divergent, 1 melded, 3 melded with aligned gathers
     double ms = 0;     // median time of the chosen candidate
     double mixed_lo = 0, mixed_hi = 0;  // probe: mixed-wave fraction per stage

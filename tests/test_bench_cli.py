@@ -79,3 +79,25 @@ def test_cpu_info_reports_model_and_counts():
     info = bench._cpu_info()
     assert info["host_logical_cpus"] >= 1 and info["affinity_cpus"] >= 1
     assert 1 <= bench._oracle_threads() <= 16
+
+
+def test_pairs_check_accepts_the_sorted_order_with_high_keys():
+    # keys on both sides of 2^31: the composite must order them as unsigned
+    import pytest
+    torch = pytest.importorskip("torch")
+    kin = torch.tensor([0xFFFFFFF0, 5, 0x80000000, 5, 0x7FFFFFFF, 0xFFFFFFF0],
+                       dtype=torch.int64).to(torch.int32)
+    order = sorted(range(6), key=lambda i: ((int(kin[i]) & 0xFFFFFFFF), i))
+    p = torch.tensor(order, dtype=torch.int32)
+    k = kin[p.long()]
+    bench._check_pairs_sorted(torch, kin, k, p)  # passes
+    bad = p.clone()
+    bad[[0, 5]] = bad[[5, 0]]
+    with pytest.raises(SystemExit):
+        bench._check_pairs_sorted(torch, kin, kin[bad.long()], bad)
+    # equal keys out of payload order
+    swapped = p.clone()
+    i, j = [n for n in range(6) if int(k[n]) == 5]
+    swapped[[i, j]] = swapped[[j, i]]
+    with pytest.raises(SystemExit):
+        bench._check_pairs_sorted(torch, kin, kin[swapped.long()], swapped)

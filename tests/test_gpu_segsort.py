@@ -14,8 +14,19 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 meld = pytest.importorskip("paper_2107_05681_amd")
 
-FORMS = [("divergent", "divergent"), ("melded", "melded"), ("melded", "divergent"),
-         ("divergent", "melded")]
+STAGE_FORMS = [("divergent", "divergent"), ("melded", "melded"), ("melded", "divergent"),
+               ("divergent", "melded")]
+# Each per-stage form on both paths of the phases k <= 64 of segments above
+# 128 keys: the LDS comparator network (0) and registers with DPP lane
+# exchanges (1).
+FORMS = [(lo, hi, x) for x in (0, 1) for lo, hi in STAGE_FORMS]
+
+
+@pytest.fixture(autouse=True)
+def _default_path():
+    yield
+    if torch.cuda.is_available():
+        meld.set_option(0, meld.OPT_LANE_EXCHANGE, -1)
 
 
 def _dev():
@@ -36,9 +47,10 @@ def _offsets(lengths):
     return np.concatenate([[0], np.cumsum(lengths)]).astype(np.uint32)
 
 
-def _run(keys, off, low, high):
+def _run(keys, off, low, high, x=-1):
     kd = _to_dev(keys)
     od = _to_dev(off)
+    meld.set_option(0, meld.OPT_LANE_EXCHANGE, x)
     meld.segmented_sort(kd, od, low=low, high=high)
     torch.cuda.synchronize()
     meld.segmented_sort_check(0)
@@ -51,9 +63,9 @@ def test_segmented_full_size_log_uniform():
     n = int(off[-1])
     keys = workloads.keys_u32(1, n)
     ref = oracle.segmented_sort_u32(keys, off)
-    for low, high in FORMS:
-        got = _run(keys, off, low, high)
-        assert np.array_equal(got, ref), (low, high)
+    for low, high, x in FORMS:
+        got = _run(keys, off, low, high, x)
+        assert np.array_equal(got, ref), (low, high, x)
 
 
 def test_segmented_edge_lengths():
@@ -66,9 +78,9 @@ def test_segmented_edge_lengths():
     keys[5::17] = 0
     keys[::29] = keys[1::29][: keys[::29].size] if n > 29 else keys[::29]
     ref = oracle.segmented_sort_u32(keys, off)
-    for low, high in FORMS:
-        got = _run(keys, off, low, high)
-        assert np.array_equal(got, ref), (low, high)
+    for low, high, x in FORMS:
+        got = _run(keys, off, low, high, x)
+        assert np.array_equal(got, ref), (low, high, x)
 
 
 def test_segmented_zero_one_principle():
@@ -78,7 +90,7 @@ def test_segmented_zero_one_principle():
     off = (np.arange((1 << 16) + 1, dtype=np.uint64) * 16).astype(np.uint32)
     ones = np.array([bin(b).count("1") for b in range(1 << 16)])
     expect = (np.arange(16)[None, :] >= (16 - ones)[:, None]).astype(np.uint32).ravel()
-    for low, high in FORMS[:2]:
+    for low, high in STAGE_FORMS[:2]:
         got = _run(keys, off, low, high)
         assert np.array_equal(got, expect), (low, high)
 
@@ -89,7 +101,7 @@ def test_segmented_many_tiny_segments():
     off = _offsets(lengths)
     keys = workloads.keys_u32(3, int(off[-1])) % np.uint32(7)
     ref = oracle.segmented_sort_u32(keys, off)
-    for low, high in FORMS[:2]:
+    for low, high in STAGE_FORMS[:2]:
         assert np.array_equal(_run(keys, off, low, high), ref)
 
 
@@ -101,8 +113,8 @@ def test_segmented_one_class_each_size():
     off = _offsets(lengths)
     keys = workloads.keys_u32(11, int(off[-1]))
     ref = oracle.segmented_sort_u32(keys, off)
-    for low, high in FORMS:
-        assert np.array_equal(_run(keys, off, low, high), ref), (low, high)
+    for low, high, x in FORMS:
+        assert np.array_equal(_run(keys, off, low, high, x), ref), (low, high, x)
 
 
 @pytest.mark.parametrize("bad", ["decreasing", "too_long", "first_nonzero"])

@@ -17,6 +17,20 @@ torch = pytest.importorskip("torch")
 meld = pytest.importorskip("paper_2107_05681_amd")
 
 VARIANTS = ("divergent", "melded")  # for the sorts MELDED_INPLACE == MELDED
+# Each form on both paths of the phases k <= 64: the LDS comparator network
+# (0) and registers with DPP lane exchanges (1).
+FORMS = [(v, x) for x in (0, 1) for v in VARIANTS]
+
+
+def _path(x):
+    meld.set_option(0, meld.OPT_LANE_EXCHANGE, x)
+
+
+@pytest.fixture(autouse=True)
+def _default_path():
+    yield
+    if torch.cuda.is_available():
+        meld.set_option(0, meld.OPT_LANE_EXCHANGE, -1)
 
 
 def _dev():
@@ -49,9 +63,10 @@ SIZES = [2, 3, 63, 64, 65, 1000, 1025, 4096, 1 << 13, (1 << 13) + 1, 1 << 14, (1
 def test_sort_keys(n):
     keys = workloads.keys_u32(n, n)
     ref = oracle.sort_u32(keys)
-    for v in VARIANTS:
+    for v, x in FORMS:
+        _path(x)
         got, _ = _gpu_sort(keys, None, v)
-        assert np.array_equal(got, ref), (n, v)
+        assert np.array_equal(got, ref), (n, v, x)
 
 
 @pytest.mark.parametrize("n", SIZES)
@@ -59,9 +74,10 @@ def test_sort_pairs(n):
     keys = workloads.keys_u32(n + 1, n)
     vals = workloads.iota_u32(n)
     rk, rv = oracle.sort_pairs_u32(keys, vals)
-    for v in VARIANTS:
+    for v, x in FORMS:
+        _path(x)
         gk, gv = _gpu_sort(keys, vals, v)
-        assert np.array_equal(gk, rk) and np.array_equal(gv, rv), (n, v)
+        assert np.array_equal(gk, rk) and np.array_equal(gv, rv), (n, v, x)
 
 
 def test_sort_pairs_heavy_ties_and_extremes():
@@ -71,9 +87,10 @@ def test_sort_pairs_heavy_ties_and_extremes():
     vals = (workloads.keys_u32(9, n) % np.uint32(3)).astype(np.uint32)
     vals[::89] = 0xFFFFFFFF
     rk, rv = oracle.sort_pairs_u32(keys, vals)
-    for v in VARIANTS:
+    for v, x in FORMS:
+        _path(x)
         gk, gv = _gpu_sort(keys, vals, v)
-        assert np.array_equal(gk, rk) and np.array_equal(gv, rv), v
+        assert np.array_equal(gk, rk) and np.array_equal(gv, rv), (v, x)
 
 
 def test_sort_n_below_two_is_noop():
@@ -98,16 +115,17 @@ def test_stage_parity_with_figure1_emulator(log_n, pairs):
                             rng.integers(1, total, 12).tolist()))
     for s in checks:
         ref = oracle.bitonic_emulate(keys, vals, max_steps=s)
-        for v in VARIANTS:
+        for v, x in FORMS:
+            _path(x)
             kd = _to_dev(keys)
             vd = None if vals is None else _to_dev(vals)
             meld.sort_steps(kd, vd, max_steps=s, variant=v)
             torch.cuda.synchronize()
             if pairs:
                 assert np.array_equal(_to_host(kd), ref[0]) and \
-                    np.array_equal(_to_host(vd), ref[1]), (s, v)
+                    np.array_equal(_to_host(vd), ref[1]), (s, v, x)
             else:
-                assert np.array_equal(_to_host(kd), ref), (s, v)
+                assert np.array_equal(_to_host(kd), ref), (s, v, x)
 
 
 def test_sort_pairs_full_size_properties():
@@ -119,7 +137,8 @@ def test_sort_pairs_full_size_properties():
     keys = workloads.keys_u32(1, n)
     kin = torch.from_numpy(keys.view(np.int32)).to(dev)
     del keys
-    for v in VARIANTS:
+    for v, x in FORMS:
+        _path(x)
         k = kin.clone()
         p = torch.arange(n, dtype=torch.int32, device=dev)
         meld.sort(k, p, variant=v)
@@ -129,13 +148,13 @@ def test_sort_pairs_full_size_properties():
         k64 = (k.to(torch.int64) & 0xFFFFFFFF) - (1 << 31)
         comp = (k64 << 32) + (p.to(torch.int64) & 0xFFFFFFFF)
         del k64
-        assert bool((comp[1:] > comp[:-1]).all()), v
+        assert bool((comp[1:] > comp[:-1]).all()), (v, x)
         del comp
         seen = torch.zeros(n, dtype=torch.bool, device=dev)
         seen[p.long()] = True
-        assert bool(seen.all()), v
+        assert bool(seen.all()), (v, x)
         del seen
-        assert torch.equal(kin[p.long()], k), v
+        assert torch.equal(kin[p.long()], k), (v, x)
         del k, p
         torch.cuda.empty_cache()
 
@@ -167,11 +186,12 @@ def test_sort_every_tile_size(log_t, tile_option):
         ref = oracle.sort_u32(keys)
         vals = workloads.iota_u32(n)
         rk, rv = oracle.sort_pairs_u32(keys, vals)
-        for v in VARIANTS:
+        for v, x in FORMS:
+            _path(x)
             got, _ = _gpu_sort(keys, None, v)
-            assert np.array_equal(got, ref), (log_t, n, v)
+            assert np.array_equal(got, ref), (log_t, n, v, x)
             gk, gv = _gpu_sort(keys, vals, v)
-            assert np.array_equal(gk, rk) and np.array_equal(gv, rv), (log_t, n, v)
+            assert np.array_equal(gk, rk) and np.array_equal(gv, rv), (log_t, n, v, x)
 
 
 @pytest.mark.parametrize("log_t,log_n,pairs", [(8, 12, False), (8, 11, True), (11, 13, True)])
@@ -186,16 +206,17 @@ def test_stage_parity_small_tiles(log_t, log_n, pairs, tile_option):
     total = oracle.bitonic_num_steps(n)
     for s in range(1, total + 1):
         ref = oracle.bitonic_emulate(keys, vals, max_steps=s)
-        for v in VARIANTS:
+        for v, x in FORMS:
+            _path(x)
             kd = _to_dev(keys)
             vd = None if vals is None else _to_dev(vals)
             meld.sort_steps(kd, vd, max_steps=s, variant=v)
             torch.cuda.synchronize()
             if pairs:
                 assert np.array_equal(_to_host(kd), ref[0]) and \
-                    np.array_equal(_to_host(vd), ref[1]), (s, v)
+                    np.array_equal(_to_host(vd), ref[1]), (s, v, x)
             else:
-                assert np.array_equal(_to_host(kd), ref), (s, v)
+                assert np.array_equal(_to_host(kd), ref), (s, v, x)
 
 
 @pytest.mark.parametrize("n", [1 << 12, (1 << 15) + 9])
@@ -205,14 +226,15 @@ def test_sort_unaligned_arrays(n):
     keys = workloads.keys_u32(300, n)
     vals = workloads.iota_u32(n)
     rk, rv = oracle.sort_pairs_u32(keys, vals)
-    for v in VARIANTS:
+    for v, x in FORMS:
+        _path(x)
         kb = _to_dev(np.concatenate([[0], keys]).astype(np.uint32))
         vb = _to_dev(np.concatenate([[0], vals]).astype(np.uint32))
         kd, vd = kb[1:], vb[1:]
         assert kd.data_ptr() % 16 != 0
         meld.sort(kd, vd, variant=v)
         torch.cuda.synchronize()
-        assert np.array_equal(_to_host(kd), rk) and np.array_equal(_to_host(vd), rv), (n, v)
+        assert np.array_equal(_to_host(kd), rk) and np.array_equal(_to_host(vd), rv), (n, v, x)
         assert _to_host(kb)[0] == 0 and _to_host(vb)[0] == 0
 
 
@@ -238,16 +260,17 @@ def test_gathered_passes_stage_parity(pairs, tile_option):
     total = oracle.bitonic_num_steps(n)
     for s in range(total - 15 - 14, total + 1):
         ref = oracle.bitonic_emulate(keys, vals, max_steps=s)
-        for v in VARIANTS:
+        for v, x in FORMS:
+            _path(x)
             kd = _to_dev(keys)
             vd = None if vals is None else _to_dev(vals)
             meld.sort_steps(kd, vd, max_steps=s, variant=v)
             torch.cuda.synchronize()
             if pairs:
                 assert np.array_equal(_to_host(kd), ref[0]) and \
-                    np.array_equal(_to_host(vd), ref[1]), (s, v)
+                    np.array_equal(_to_host(vd), ref[1]), (s, v, x)
             else:
-                assert np.array_equal(_to_host(kd), ref), (s, v)
+                assert np.array_equal(_to_host(kd), ref), (s, v, x)
 
 
 @pytest.mark.parametrize("log_t", [8, 9])
@@ -261,8 +284,9 @@ def test_gathered_passes_full_sort(log_t, n, tile_option):
     vals = workloads.iota_u32(n)
     ref = oracle.sort_u32(keys)
     rk, rv = oracle.sort_pairs_u32(keys, vals)
-    for v in VARIANTS:
+    for v, x in FORMS:
+        _path(x)
         got, _ = _gpu_sort(keys, None, v)
-        assert np.array_equal(got, ref), (log_t, n, v)
+        assert np.array_equal(got, ref), (log_t, n, v, x)
         gk, gv = _gpu_sort(keys, vals, v)
-        assert np.array_equal(gk, rk) and np.array_equal(gv, rv), (log_t, n, v)
+        assert np.array_equal(gk, rk) and np.array_equal(gv, rv), (log_t, n, v, x)

@@ -113,8 +113,8 @@ def test_register_phases_divergent_vs_melded(bitonic_asm, pairs):
     # Phases k >= 128 of the tile sort run in registers: the divergent form
     # keeps Figure 1's two sides (one per direction), the melded one has none.
     p = "b1" if pairs else "b0"
-    div = _kernel(bitonic_asm, rf"bitonic_sort_regs_kernelIL{p}ELi13ELb0ELb0E")
-    mel = _kernel(bitonic_asm, rf"bitonic_sort_regs_kernelIL{p}ELi13ELb1ELb1E")
+    div = _kernel(bitonic_asm, rf"bitonic_sort_regs_kernelIL{p}ELi13ELb0ELb0ELb0E")
+    mel = _kernel(bitonic_asm, rf"bitonic_sort_regs_kernelIL{p}ELi13ELb1ELb1ELb0E")
     width = "u64" if pairs else "u32"
     for side in ("ascending regs\n", "descending regs\n"):
         blocks = _blocks_after(div, side)
@@ -185,3 +185,73 @@ def test_merge_step_divergent_sides_each_load(mergesort_asm):
 def test_merge_step_melded_has_no_sides(mergesort_asm):
     body = _kernel(mergesort_asm, r"merge_pass_kernelILb1E")
     assert "; side" not in body and "v_cndmask_b32" in body
+
+
+def _kernel_all(asm, pattern):
+    """A kernel's whole text, with the blocks the compiler placed after its
+    first s_endpgm."""
+    names = re.findall(r"^(_Z\S*):", asm, flags=re.M)
+    match = [n for n in names if re.search(pattern, n)]
+    assert match, f"no kernel matches {pattern}"
+    start = asm.index(match[0] + ":")
+    return asm[start:asm.index(".Lfunc_end", start)]
+
+
+def _lane_sides(body):
+    """(direction, text) of every side block of the divergent lane steps: from
+    its mark to the end of its basic block."""
+    return re.findall(r"; side ((?:a|de)scending) lanes\n(.*?)(?=^\.LBB|^; %bb\.)", body,
+                      re.S | re.M)
+
+
+@pytest.mark.parametrize("pairs", [False, True])
+def test_lane_exchanges_sit_outside_the_divergent_sides(bitonic_asm, pairs):
+    # Tile sort of 2^11 with lane exchanges: three lane steps in phases
+    # k <= 64 and the two of the later phases' last layout. The divergent form
+    # moves each partner value with a DPP move of its own, before the branch;
+    # its sides hold only compares and selects.
+    p = "b1" if pairs else "b0"
+    div = _kernel_all(bitonic_asm, rf"bitonic_sort_regs_kernelIL{p}ELi11ELb0ELb0ELb1E")
+    sides = _lane_sides(div)
+    assert sum(1 for d, _ in sides if d == "ascending") >= 5
+    assert sum(1 for d, _ in sides if d == "descending") >= 5
+    for _, text in sides:
+        assert "_dpp" not in text and "ds_" not in text and "permlane" not in text
+        # each side its own compare (keys: min and max) and select
+        assert (re.search(r"v_cmp_\w+_u64", text) if pairs else
+                ("v_min_u32" in text and "v_max_u32" in text)), text[:400]
+        assert "v_cndmask_b32" in text
+    halves = 2 if pairs else 1
+    assert div.count("v_mov_b32_dpp") == 5 * 16 * halves
+    assert "quad_perm:[1,0,3,2]" in div and "quad_perm:[2,3,0,1]" in div
+
+
+@pytest.mark.parametrize("pairs", [False, True])
+def test_lane_exchanges_melded_compare_select_on_the_full_wave(bitonic_asm, pairs):
+    p = "b1" if pairs else "b0"
+    mel = _kernel_all(bitonic_asm, rf"bitonic_sort_regs_kernelIL{p}ELi11ELb1ELb1ELb1E")
+    assert "; side" not in mel
+    if pairs:
+        # both halves moved, one 64-bit compare, a select per half
+        assert mel.count("v_mov_b32_dpp") == 5 * 16 * 2
+        assert re.search(r"v_cmp_(lt|gt)_u64", mel)
+    else:
+        # the move folds into the min and max that use it
+        assert mel.count("v_min_u32_dpp") == 5 * 16 and mel.count("v_max_u32_dpp") == 5 * 16
+        assert "v_mov_b32_dpp" not in mel
+
+
+@pytest.fixture(scope="module")
+def segsort_asm(tmp_path_factory):
+    return _asm("segsort.hip", tmp_path_factory.mktemp("isa"))
+
+
+def test_segmented_lane_exchanges_outside_the_sides(segsort_asm):
+    div = _kernel_all(segsort_asm, r"seg_sort_kernelILb0ELb0ELb1E")
+    sides = _lane_sides(div)
+    assert sides
+    for _, text in sides:
+        assert "_dpp" not in text and "ds_" not in text
+    mel = _kernel_all(segsort_asm, r"seg_sort_kernelILb1ELb1ELb1E")
+    assert not _lane_sides(mel)
+    assert "v_min_u32_dpp" in mel and "v_max_u32_dpp" in mel
