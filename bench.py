@@ -117,6 +117,15 @@ def _tuned_region_form(meld, tt, tf):
     return None
 
 
+PATHS = {"lds": 0, "lane_exchange": 1}  # MELD_OPT_LANE_EXCHANGE values
+
+
+def _set_path(meld, x):
+    """Phases k <= 64 of the sorts: 0 the LDS comparator network, 1 registers with
+    DPP lane exchanges, -1 the library's choice."""
+    meld.set_option(0, meld.OPT_LANE_EXCHANGE, x)
+
+
 def _mixed_fraction(p, wave=64):
     return 1.0 - p ** wave - (1.0 - p) ** wave
 
@@ -377,38 +386,53 @@ def _bench_pairs_forms(torch, np, meld, workloads, dev, kin1, pin, args):
     reps = max(4, args.pair_reps)
     for seed in (1, 2, 3):
         kin = kin1 if seed == SEED else _pairs_inputs(torch, np, workloads, dev, seed, n)[0]
-        t = {"divergent": [], "melded": []}
-        for rep in range(reps + 1):
-            for v in ("divergent", "melded"):
-                k.copy_(kin)
-                p.copy_(pin)
-                s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                s.record()
-                meld.sort(k, p, variant=v)
-                e.record()
-                e.synchronize()
-                if rep > 0:
-                    t[v].append(s.elapsed_time(e))
-        d, m = float(np.median(t["divergent"])), float(np.median(t["melded"]))
-        res[f"seed_{seed}"] = {"divergent_ms": _dist(np, t["divergent"], scale=1.0),
-                               "melded_ms": _dist(np, t["melded"], scale=1.0),
-                               "speedup": round(d / m, 4), "reps": reps,
-                               "melded_Gkeys_s": round(n / (m * 1e-3) / 1e9, 3)}
+        rec = {"reps": reps}
+        for path, x in PATHS.items():
+            _set_path(meld, x)
+            t = {"divergent": [], "melded": []}
+            for rep in range(reps + 1):
+                for v in ("divergent", "melded"):
+                    k.copy_(kin)
+                    p.copy_(pin)
+                    s = torch.cuda.Event(enable_timing=True)
+                    e = torch.cuda.Event(enable_timing=True)
+                    s.record()
+                    meld.sort(k, p, variant=v)
+                    e.record()
+                    e.synchronize()
+                    if rep > 0:
+                        t[v].append(s.elapsed_time(e))
+            d, m = float(np.median(t["divergent"])), float(np.median(t["melded"]))
+            rec[path] = {"divergent_ms": _dist(np, t["divergent"], scale=1.0),
+                         "melded_ms": _dist(np, t["melded"], scale=1.0),
+                         "speedup": round(d / m, 4),
+                         "melded_Gkeys_s": round(n / (m * 1e-3) / 1e9, 3)}
+        _set_path(meld, -1)
+        rec["speedup"] = rec["lane_exchange"]["speedup"]
+        res[f"seed_{seed}"] = rec
         if seed != SEED:
             del kin
     res["median_speedup"] = round(float(np.median(
         [res[f"seed_{s}"]["speedup"] for s in (1, 2, 3)])), 4)
+    res["median_speedup_lds_path"] = round(float(np.median(
+        [res[f"seed_{s}"]["lds"]["speedup"] for s in (1, 2, 3)])), 4)
     # the local sort alone: the network's first t (t + 1) / 2 steps are exactly that launch
     plan = meld.sort_plan(n, pairs=True, variant="melded", device=0)
     local = plan["passes"][0]["steps"]
-    tl = {}
-    for v in ("divergent", "melded"):
-        tl[v] = _time_sorts(torch, np, lambda v=v: meld.sort_steps(k, p, local, variant=v),
-                            lambda: (k.copy_(kin1), p.copy_(pin)), 11)
-    res["local_sort_kernel"] = {"steps": local, "log_tile": plan["log_tile"],
-                                "divergent_ms": round(tl["divergent"], 4),
-                                "melded_ms": round(tl["melded"], 4),
-                                "speedup": round(tl["divergent"] / tl["melded"], 4)}
+    res["local_sort_kernel"] = {"steps": local, "log_tile": plan["log_tile"]}
+    for path, x in PATHS.items():
+        _set_path(meld, x)
+        tl = {}
+        for v in ("divergent", "melded"):
+            tl[v] = _time_sorts(torch, np, lambda v=v: meld.sort_steps(k, p, local, variant=v),
+                                lambda: (k.copy_(kin1), p.copy_(pin)), 11)
+        res["local_sort_kernel"][path] = {"divergent_ms": round(tl["divergent"], 4),
+                                          "melded_ms": round(tl["melded"], 4),
+                                          "speedup": round(tl["divergent"] / tl["melded"], 4)}
+    _set_path(meld, -1)
+    lx = res["local_sort_kernel"]
+    lx["melded_lane_exchange_vs_melded_lds"] = round(lx["lds"]["melded_ms"]
+                                                     / lx["lane_exchange"]["melded_ms"], 4)
     del k, p
     torch.cuda.empty_cache()
     return res
@@ -682,39 +706,46 @@ def _bench_sort16(torch, np, meld, workloads, dev, args):
     n = 1 << 16
     kin = torch.from_numpy(workloads.keys_u32(SEED, n).view(np.int32)).to(dev)
     k = torch.empty_like(kin)
-    times = {"divergent": [], "melded": []}
-    for rep in range(41):
-        for v in ("divergent", "melded"):
-            k.copy_(kin)
-            s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            s.record()
-            meld.sort(k, None, variant=v)
-            e.record()
-            e.synchronize()
-            if rep > 0:
-                times[v].append(s.elapsed_time(e))
-    d, m = float(np.median(times["divergent"])), float(np.median(times["melded"]))
-    # the local-sort kernel alone: the network's first t (t + 1) / 2 steps are
-    # exactly that launch
     plan = meld.sort_plan(n, pairs=False, variant="melded", device=0)
     local = plan["passes"][0]["steps"]
-    tl = {v: _time_sorts(torch, np, lambda v=v: meld.sort_steps(k, None, local, variant=v),
-                         lambda: k.copy_(kin), 21) for v in ("divergent", "melded")}
-    return {"divergent_us": round(d * 1e3, 2), "melded_us": round(m * 1e3, 2),
-            "speedup": round(d / m, 4),
-            "melded_Gkeys_s": round(n / (m * 1e-3) / 1e9, 3),
-            "divergent_us_dist": _dist(np, times["divergent"]),
-            "melded_us_dist": _dist(np, times["melded"]),
-            "log_tile": plan["log_tile"], "hbm_passes": plan["hbm_passes"],
-            "hbm_frac": round(8.0 * n * plan["hbm_passes"] / (m * 1e-3) / 1e9
-                              / HBM_PEAK_GBS, 5),
-            "hbm_frac_note": "not meaningful: 256 KiB per pass, the sort is bound "
-                             "by launch and per-tile latency",
-            "local_sort_kernel": {
-                "steps": local,
-                "divergent_us": round(tl["divergent"] * 1e3, 2),
-                "melded_us": round(tl["melded"] * 1e3, 2),
-                "speedup": round(tl["divergent"] / tl["melded"], 4)}}
+    out = {"log_tile": plan["log_tile"], "hbm_passes": plan["hbm_passes"],
+           "hbm_frac_note": "not meaningful: 256 KiB per pass, the sort is bound "
+                            "by launch and per-tile latency"}
+    for path, x in PATHS.items():
+        _set_path(meld, x)
+        times = {"divergent": [], "melded": []}
+        for rep in range(41):
+            for v in ("divergent", "melded"):
+                k.copy_(kin)
+                s = torch.cuda.Event(enable_timing=True)
+                e = torch.cuda.Event(enable_timing=True)
+                s.record()
+                meld.sort(k, None, variant=v)
+                e.record()
+                e.synchronize()
+                if rep > 0:
+                    times[v].append(s.elapsed_time(e))
+        d, m = float(np.median(times["divergent"])), float(np.median(times["melded"]))
+        # the local-sort kernel alone: the network's first t (t + 1) / 2 steps
+        # are exactly that launch
+        tl = {v: _time_sorts(torch, np, lambda v=v: meld.sort_steps(k, None, local, variant=v),
+                             lambda: k.copy_(kin), 21) for v in ("divergent", "melded")}
+        out[path] = {"divergent_us": round(d * 1e3, 2), "melded_us": round(m * 1e3, 2),
+                     "speedup": round(d / m, 4),
+                     "melded_Gkeys_s": round(n / (m * 1e-3) / 1e9, 3),
+                     "divergent_us_dist": _dist(np, times["divergent"]),
+                     "melded_us_dist": _dist(np, times["melded"]),
+                     "hbm_frac": round(8.0 * n * plan["hbm_passes"] / (m * 1e-3) / 1e9
+                                       / HBM_PEAK_GBS, 5),
+                     "local_sort_kernel": {
+                         "steps": local,
+                         "divergent_us": round(tl["divergent"] * 1e3, 2),
+                         "melded_us": round(tl["melded"] * 1e3, 2),
+                         "speedup": round(tl["divergent"] / tl["melded"], 4)}}
+    _set_path(meld, -1)
+    out["melded_lane_exchange_vs_melded_lds"] = round(
+        out["lds"]["melded_us"] / out["lane_exchange"]["melded_us"], 4)
+    return out
 
 
 def _profile_sorts(torch, np, meld, workloads, dev):
@@ -781,9 +812,12 @@ def _bench_segmented(torch, np, meld, workloads, dev, args):
     per-stage forms on seed 1, MELD_AUTO and both forms on seeds 1..3 with at least
     ~1 s of sorts per seed and form."""
     out = {"segments": 4096}
-    forms = {"divergent": ("divergent", "divergent"), "melded": ("melded", "melded"),
-             "melded_low_only": ("melded", "divergent"),
-             "melded_high_only": ("divergent", "melded")}
+    # (low form, high form, path of the phases k <= 64): lane exchanges unless
+    # named "_lds"
+    forms = {"divergent": ("divergent", "divergent", 1), "melded": ("melded", "melded", 1),
+             "melded_low_only": ("melded", "divergent", 1),
+             "melded_high_only": ("divergent", "melded", 1),
+             "divergent_lds": ("divergent", "divergent", 0), "melded_lds": ("melded", "melded", 0)}
     seeds = {}
     for seed in (1, 2, 3):
         off = workloads.segment_offsets(seed, 4096)
@@ -794,7 +828,8 @@ def _bench_segmented(torch, np, meld, workloads, dev, args):
         names = forms if seed == SEED else {k: forms[k] for k in ("divergent", "melded")}
         t = {name: [] for name in names}
         for rep in range(args.seg_reps + 1):
-            for name, (lo, hi) in names.items():
+            for name, (lo, hi, x) in names.items():
+                _set_path(meld, x)
                 work.copy_(pristine)
                 s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 s.record()
@@ -803,6 +838,7 @@ def _bench_segmented(torch, np, meld, workloads, dev, args):
                 e.synchronize()
                 if rep > 0:
                     t[name].append(s.elapsed_time(e))
+        _set_path(meld, -1)
         work.copy_(pristine)
         meld.segmented_sort(work, od, variant="auto")  # tunes this shape class once
         ms_auto = _time_sorts(torch, np, lambda: meld.segmented_sort(work, od, variant="auto"),
@@ -813,6 +849,11 @@ def _bench_segmented(torch, np, meld, workloads, dev, args):
             rec[name + "_ms"] = _dist(np, t[name], scale=1.0)
         rec["speedup_melded"] = round(rec["divergent_ms"]["median"] / rec["melded_ms"]["median"],
                                       4)
+        if "melded_lds_ms" in rec:
+            rec["speedup_melded_lds_path"] = round(
+                rec["divergent_lds_ms"]["median"] / rec["melded_lds_ms"]["median"], 4)
+            rec["melded_lane_exchange_vs_melded_lds"] = round(
+                rec["melded_lds_ms"]["median"] / rec["melded_ms"]["median"], 4)
         seeds[f"seed_{seed}"] = rec
         if seed == SEED:
             (ml, al), (mh, ah) = meld.probe_segments(od)
@@ -828,7 +869,8 @@ def _bench_segmented(torch, np, meld, workloads, dev, args):
         if e["op"] == "segsort":
             out.setdefault("tuned_plans", {})[e["key"]] = {
                 "low": "melded" if e["lo"] else "divergent",
-                "high": "melded" if e["hi"] else "divergent"}
+                "high": "melded" if e["hi"] else "divergent",
+                "low_path": "lane_exchange" if e.get("xch") else "lds"}
     torch.cuda.empty_cache()
     return out
 

@@ -9,6 +9,7 @@ melded-in-place forms and MELD_AUTO.
 import numpy as np
 import pytest
 
+import _oracle_par
 import oracle
 import workloads
 
@@ -60,23 +61,20 @@ def test_region3_parity(trips, ps):
         assert _same_bits(y.cpu().numpy(), ref), (v, trips, ps)
 
 
-def test_region3_full_size_sampled():
-    # 2^24 lanes over the 64 MiB table; sampled lane ranges against the oracle,
-    # the forms against each other on every lane.
+def test_region3_full_size_every_lane():
+    # The timed configuration: 2^24 lanes over the 64 MiB table, ways a third
+    # each; every lane of every form against the oracle.
     dev = _dev()
     seed, n = 1, 1 << 24
     x, tab, w0, w1, w2 = workloads.region3_inputs(seed, n)
     xd = torch.from_numpy(x).to(dev)
     td = torch.from_numpy(tab).to(dev)
     thr0, thr1 = workloads.thr_from_p(1 / 3), workloads.thr_from_p(2 / 3)
-    outs = {v: meld.region3(xd, td, seed, thr0, thr1, w0, w1, w2, variant=v).cpu().numpy()
-            for v in VARIANTS[:3]}
-    assert _same_bits(outs["divergent"], outs["melded"])
-    assert _same_bits(outs["divergent"], outs["melded_inplace"])
-    rng = np.random.default_rng(1)
-    for s0 in sorted(set(rng.integers(0, n - 2048, 8).tolist()) | {0, n - 2048}):
-        ref = oracle.region3_f32(x[s0:s0 + 2048], tab, seed, thr0, thr1, w0, w1, w2, i0=s0)
-        assert _same_bits(outs["melded"][s0:s0 + 2048], ref), s0
+    ref = _oracle_par.by_chunks(
+        lambda s0, s1: oracle.region3_f32(x[s0:s1], tab, seed, thr0, thr1, w0, w1, w2, i0=s0), n)
+    for v in VARIANTS[:3]:
+        got = meld.region3(xd, td, seed, thr0, thr1, w0, w1, w2, variant=v).cpu().numpy()
+        assert _same_bits(got, ref), v
 
 
 @pytest.mark.parametrize("n", [1, 63, 65, 257])
@@ -133,10 +131,9 @@ def test_region_lanetrips_parity(rng_, p):
         assert _same_bits(y.cpu().numpy(), ref), (v, rng_, p)
 
 
-def test_region_lanetrips_full_size_sampled():
+def test_region_lanetrips_full_size_every_lane():
     # The timed configuration: 2^24 lanes, 64 MiB table, trips in [8, 32] per
-    # lane on both sides, p = 0.5. The forms agree on every lane; sampled lane
-    # ranges against the oracle.
+    # lane on both sides, p = 0.5; every lane of every form against the oracle.
     dev = _dev()
     seed, n = 1, 1 << 24
     x, tab, _, _ = workloads.region_inputs(seed, n)
@@ -144,14 +141,11 @@ def test_region_lanetrips_full_size_sampled():
     thr = workloads.thr_from_p(0.5)
     xd = torch.from_numpy(x).to(dev)
     td = torch.from_numpy(tab).to(dev)
-    outs = {v: meld.region_lanetrips(xd, td, seed, thr, st, sf, variant=v).cpu().numpy()
-            for v in VARIANTS[:3]}
-    assert _same_bits(outs["divergent"], outs["melded"])
-    assert _same_bits(outs["divergent"], outs["melded_inplace"])
-    rng = np.random.default_rng(2)
-    for s0 in sorted(set(rng.integers(0, n - 2048, 8).tolist()) | {0, n - 2048}):
-        ref = oracle.region_lanetrips_f32(x[s0:s0 + 2048], tab, seed, thr, st, sf, i0=s0)
-        assert _same_bits(outs["melded"][s0:s0 + 2048], ref), s0
+    ref = _oracle_par.by_chunks(
+        lambda s0, s1: oracle.region_lanetrips_f32(x[s0:s1], tab, seed, thr, st, sf, i0=s0), n)
+    for v in VARIANTS[:3]:
+        got = meld.region_lanetrips(xd, td, seed, thr, st, sf, variant=v).cpu().numpy()
+        assert _same_bits(got, ref), v
 
 
 def test_region_lanetrips_counts_exactly():
