@@ -134,6 +134,28 @@ const char *meld_last_error(void);
 meld_status meld_sort_u32(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n,
                           meld_variant variant, void *stream);
 
+/* Words of the device scratch behind meld_sort_u32_noalloc: 2^22 (16 MiB). */
+#define MELD_NOALLOC_SCRATCH_WORDS (1u << 22)
+
+/* meld_sort_u32 for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * It allocates nothing (no hipMalloc, hipFree or allocating library call):
+ * the padding of a non-power-of-two n lives in a device array of the library
+ * (MELD_NOALLOC_SCRATCH_WORDS u32, one copy per device, held until the
+ * process ends, its address looked up by meld_create), filled with the
+ * sentinel by a kernel on every call. The same network, forms and result as
+ * meld_sort_u32; MELD_AUTO takes the tuner's decision for the shape if it
+ * holds one and the melded default otherwise (it never times trials).
+ * The array is shared by every call on the device, whatever the context:
+ * calls that overlap on one GPU (other host threads, or streams that run
+ * concurrently) race on it and must be ordered by the caller.
+ * Arguments and errors: as meld_sort_u32, plus MELD_EINVAL when the padding
+ * (N - n words for keys, 2 (N - n) for pairs, N the next power of two >= n)
+ * exceeds MELD_NOALLOC_SCRATCH_WORDS and n is above one tile (every n up to
+ * 2^22 keys or 2^21 pairs fits, as does every power of two). */
+meld_status meld_sort_u32_noalloc(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n,
+                                  meld_variant variant, void *stream);
+
 /* meld_sort_u32 with the duration of every launch: a HIP event is recorded
  * on `stream` before the first launch and after each one, the call waits for
  * the last, and launch_ms[i] receives the time between events i and i+1 in

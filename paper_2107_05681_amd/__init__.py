@@ -38,7 +38,7 @@ EXPORTS = ("meld_version", "meld_create", "meld_destroy", "meld_last_error", "me
            "meld_server_destroy",
            "meld_divergent_region_f32", "meld_region3_f32", "meld_region_lanetrips_f32",
            "meld_oddeven_sort_buckets_u32", "meld_merge_sort_u32", "meld_sort_plan_describe",
-           "meld_sort_u32_timed")
+           "meld_sort_u32_timed", "meld_sort_u32_noalloc")
 
 
 class MeldError(RuntimeError):
@@ -87,6 +87,8 @@ def load_library():
     lib.meld_last_error.argtypes = []
     lib.meld_sort_u32.restype = st
     lib.meld_sort_u32.argtypes = [vp, vp, vp, sz, st, vp]
+    lib.meld_sort_u32_noalloc.restype = st
+    lib.meld_sort_u32_noalloc.argtypes = [vp, vp, vp, sz, st, vp]
     lib.meld_sort_u32_timed.restype = st
     lib.meld_sort_u32_timed.argtypes = [vp, vp, vp, sz, st, vp, ctypes.POINTER(ctypes.c_float),
                                         sz, ctypes.POINTER(sz)]
@@ -198,15 +200,19 @@ def _u32_tensor(t, name):
     return t
 
 
-def sort(keys, payload=None, variant=AUTO, stream=None, ctx=None):
-    """In-place ascending bitonic sort of ``keys`` (u32 bits), moving ``payload`` along."""
+def sort(keys, payload=None, variant=AUTO, stream=None, ctx=None, noalloc=False):
+    """In-place ascending bitonic sort of ``keys`` (u32 bits), moving ``payload`` along.
+    noalloc: through meld_sort_u32_noalloc (no device allocation; padding in the
+    library's fixed device scratch)."""
     _u32_tensor(keys, "keys")
     if payload is not None:
         _u32_tensor(payload, "payload")
         if payload.numel() != keys.numel() or payload.device != keys.device:
             raise ValueError("payload must match keys in length and device")
     c, s = _launch_args(keys, stream, ctx)
-    _check(load_library().meld_sort_u32(
+    lib = load_library()
+    fn = lib.meld_sort_u32_noalloc if noalloc else lib.meld_sort_u32
+    _check(fn(
         c, ctypes.c_void_p(keys.data_ptr()),
         None if payload is None else ctypes.c_void_p(payload.data_ptr()), keys.numel(),
         _variant(variant), s))

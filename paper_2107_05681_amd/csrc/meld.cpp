@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <list>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -66,6 +67,37 @@ struct meld_ctx {
 
 namespace {
 constexpr size_t kProbeWords = 64;
+
+// Scratch of meld_sort_u32_noalloc: the padding of a non-power-of-two sort,
+// in a device array of the library itself, so that the call allocates
+// nothing. Every device holds its own copy until the process ends; host code
+// reaches a device's copy only through the address hipGetSymbolAddress gives
+// for it (the array's name is not a device address in host code).
+constexpr size_t kNoAllocWords = MELD_NOALLOC_SCRATCH_WORDS;
+__device__ __align__(256) uint32_t scratch[kNoAllocWords];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t *g_scratch_ptr[kMaxDevices] = {};
+
+// Looks up device `device`'s copy of the scratch array once; the device must
+// be current.
+hipError_t noalloc_scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device] != nullptr) return hipSuccess;
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<uint32_t *>(ptr);
+    return hipSuccess;
+}
+
+uint32_t *noalloc_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
 
 }  // namespace
 
@@ -1013,6 +1045,11 @@ meld_status meld_create(int hip_device, meld_ctx **out) {
     if (hip_device < 0 || hip_device >= count)
         return fail(MELD_EINVAL, "meld_create: device %d out of range (%d devices)", hip_device,
                     count);
+    {
+        DeviceGuard g(hip_device);
+        e = noalloc_scratch_init(hip_device);
+        if (e != hipSuccess) return hip_fail(e, "meld_create: address of the device scratch");
+    }
     meld_ctx *ctx = new (std::nothrow) meld_ctx();
     if (ctx == nullptr) return fail(MELD_ENOMEM, "meld_create: out of host memory");
     ctx->device = hip_device;
@@ -1066,6 +1103,37 @@ meld_status meld_sort_u32(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size
         if (st != MELD_OK) return st;
     }
     return sort_impl(ctx, keys, payload, n, plan, -1, s);
+}
+
+meld_status meld_sort_u32_noalloc(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n,
+                                  meld_variant variant, void *stream) {
+    const char *name = "meld_sort_u32_noalloc";
+    if (ctx == nullptr) return fail(MELD_EINVAL, "%s: ctx is NULL", name);
+    if (n >= (1ull << 31)) return fail(MELD_EINVAL, "%s: n = %zu >= 2^31", name, n);
+    if ((unsigned)variant > MELD_MELDED_INPLACE) return fail(MELD_EINVAL, "%s: bad variant", name);
+    if (n <= 1) return MELD_OK;
+    DeviceGuard g(ctx->device);
+    if (!is_device_ptr(ctx, keys) || (payload != nullptr && !is_device_ptr(ctx, payload)))
+        return fail(MELD_EINVAL, "%s: keys and payload must be device pointers on device %d",
+                    name, ctx->device);
+    const bool pairs = payload != nullptr;
+    const uint32_t log_n = log2_ceil(n);
+    SortPlan plan = fixed_plan(ctx, pairs, n, variant);
+    // MELD_AUTO: a decision the tuner already holds, never a timed trial
+    // (trials copy the input into allocated scratch)
+    if (variant == MELD_AUTO) (void)cached_sort_plan(ctx, pairs, log_n, &plan);
+    const size_t pad = ((size_t)1 << log_n) - n;
+    const size_t words = pairs ? 2 * pad : pad;
+    const bool one_tile = log_n <= plan.log_t;  // padded in LDS, no scratch
+    if (!one_tile && words > kNoAllocWords)
+        return fail(MELD_EINVAL,
+                    "%s: n = %zu needs %zu words of padding, above the %zu-word scratch "
+                    "(MELD_NOALLOC_SCRATCH_WORDS); use meld_sort_u32",
+                    name, n, words, kNoAllocWords);
+    uint32_t *tail = noalloc_scratch(ctx->device);
+    if (tail == nullptr) return fail(MELD_EHIP, "%s: no device scratch on device %d", name, ctx->device);
+    return sort_impl(ctx, keys, payload, n, plan, -1, static_cast<hipStream_t>(stream), nullptr,
+                     tail, kNoAllocWords);
 }
 
 meld_status meld_sort_u32_timed(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n,
