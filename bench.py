@@ -60,7 +60,7 @@ def _parse():
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the Poisson serving trace (0 skips serving)")
     ap.add_argument("--profile", nargs="?", const="region", default=None,
-                    choices=["region", "sort", "pairs", "next"],
+                    choices=["region", "region_sweep", "sort", "pairs", "next"],
                     help="short run for rocprofv3: 'region' (a 256 MiB copy, then the "
                          "region in each form), 'sort' (2^16 keys and the 4096-segment sort, "
                          "each form), 'pairs' (a 256 MiB copy, then one 2^28-pair sort per "
@@ -208,6 +208,9 @@ def main():
         return
     if args.profile == "region":
         _profile_region(torch, np, meld, workloads, dev)
+        return
+    if args.profile == "region_sweep":
+        _profile_region_sweep(torch, np, meld, workloads, dev)
         return
 
     # ---- Headline: bitonic sort of 2^28 (key, payload = index) pairs ----------
@@ -455,6 +458,23 @@ def _profile_region(torch, np, meld, workloads, dev):
     print(json.dumps({"profile_run": "region", "copy_bytes": 2 * src.numel() * 4}))
 
 
+def _profile_region_sweep(torch, np, meld, workloads, dev):
+    """p = 0.5, 2^24 lanes: for trips (10, 10), (20, 20) and (32, 32), the divergent and
+    melded forms, then each form's memory path alone (gathers only)."""
+    x, tab, st, sf = workloads.region_inputs(SEED, N_LANES)
+    xd, td = torch.from_numpy(x).to(dev), torch.from_numpy(tab).to(dev)
+    y = torch.empty_like(xd)
+    thr = workloads.thr_from_p(0.5)
+    for tt, tf in ((10, 10), (20, 20), (32, 32)):
+        st_t, sf_t = dict(st, trips=tt), dict(sf, trips=tf)
+        for only in (False, True):
+            for v in ("divergent", "melded"):
+                meld.divergent_region(xd, td, SEED, thr, st_t, sf_t, variant=v, out=y,
+                                      gathers_only=only)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_run": "region_sweep"}))
+
+
 def _bench_region(torch, np, meld, workloads, dev, args):
     """The two-sided loop region over 2^24 lanes at p in {0.1, 0.5, 0.9}: per-form
     timings (interleaved), the tuned step, sensitivity cases and variants."""
@@ -488,6 +508,8 @@ def _bench_region(torch, np, meld, workloads, dev, args):
             ti_ms.append(_events_time(torch, lambda: region(p, "melded_inplace"), args.reps))
         d, m = float(np.median(td_ms)), float(np.median(tm_ms))
         mi = float(np.median(ti_ms))
+        ceil = {v: _gathers_only_us(torch, np, meld, xd, td, thr[p], st, sf, ys[p], v, args)
+                for v in ("divergent", "melded")}
         e_t = p * st["trips"] + (1 - p) * sf["trips"]
         alg_bytes = N_LANES * (8 + 4 * e_t)
         per_p[str(p)] = {
@@ -502,6 +524,9 @@ def _bench_region(torch, np, meld, workloads, dev, args):
                                             / HBM_PEAK_GBS, 4),
             "divergent_compulsory_frac": round(REGION_COMPULSORY / (d * 1e-3) / 1e9
                                                / HBM_PEAK_GBS, 4),
+            "gathers_only_us": {v: round(c, 2) for v, c in ceil.items()},
+            "frac_of_gathers_only": {"divergent": round(ceil["divergent"] / (d * 1e3), 4),
+                                     "melded": round(ceil["melded"] / (m * 1e3), 4)},
         }
 
     # Sensitivity: both sides gathering the same entries (sides differ only in
@@ -536,11 +561,16 @@ def _bench_region(torch, np, meld, workloads, dev, args):
             region_trips(v)  # "auto": the tuner times the forms for this shape once
             tm[v] = float(np.median([_events_time(torch, lambda: region_trips(v), args.reps)
                                      for _ in range(3)]))
+        ceil = {v: _gathers_only_us(torch, np, meld, xd, td, thr[0.5], st_t, sf_t, ys[0.5], v,
+                                    args) for v in ("divergent", "melded")}
         trips_sweep[f"{tt},{tf}"] = {"divergent_us": round(tm["divergent"] * 1e3, 2),
                                      "melded_us": round(tm["melded"] * 1e3, 2),
                                      "speedup": round(tm["divergent"] / tm["melded"], 4),
                                      "auto_us": round(tm["auto"] * 1e3, 2),
-                                     "auto_form": _tuned_region_form(meld, tt, tf)}
+                                     "auto_form": _tuned_region_form(meld, tt, tf),
+                                     "gathers_only_us": {v: round(c, 2) for v, c in ceil.items()},
+                                     "gathers_only_speedup": round(ceil["divergent"]
+                                                                   / ceil["melded"], 4)}
 
     variants = _bench_region_variants(torch, np, meld, workloads, xd, td, ys[0.5], args)
     seeds = _bench_seeds(torch, np, meld, workloads, dev, args)
@@ -578,6 +608,16 @@ def _bench_region(torch, np, meld, workloads, dev, args):
         "region_variants": variants,
         "seeds": seeds,
     }
+
+
+def _gathers_only_us(torch, np, meld, xd, td, thr, st, sf, y, variant, args):
+    """Median us of the region's memory path alone in one form (meld_probe_region_gathers:
+    the same lanes, branch, addresses, exec masks and batching, no fma chain)."""
+    def run():
+        meld.divergent_region(xd, td, SEED, thr, st, sf, variant=variant, out=y,
+                              gathers_only=True)
+    run()
+    return float(np.median([_events_time(torch, run, args.reps) for _ in range(3)])) * 1e3
 
 
 def _bench_seeds(torch, np, meld, workloads, dev, args):
@@ -888,6 +928,10 @@ def _bench_serving(meld, workloads, seconds):
             "failed": st["failed"], "p50_ms": round(summ["p50_ms"], 3),
             "p99_ms": round(summ["p99_ms"], 3), "wait_p50_ms": round(summ["wait_p50_ms"], 3),
             "wait_p99_ms": round(summ["wait_p99_ms"], 3),
+            "latency_from": "each job's scheduled Poisson arrival (submitted ahead; the server "
+                            "admits it at its arrival) to its completion",
+            "submit_lead_p50_ms": round(summ["submit_lead_p50_ms"], 3),
+            "submit_lead_min_ms": round(summ["submit_lead_min_ms"], 3),
             "busy_fraction": round(summ["busy_fraction"], 4),
             "jobs_per_s": round(summ["jobs_per_s"], 1),
             "Gkeys_s": round(summ["keys_per_s"] / 1e9, 4),

@@ -316,6 +316,18 @@ meld_status meld_divergent_region_f32(meld_ctx *ctx, const float *x, float *y, s
                                       uint64_t thr, meld_side side_true, meld_side side_false,
                                       meld_variant variant, void *stream);
 
+/* The memory path of meld_divergent_region_f32 alone, for measuring the
+ * ceiling a form's fma chain runs under: the same lanes, branch, gather
+ * addresses, exec masks and batching as that call in form `variant`, with
+ * each step's fma replaced by an xor of the gathered bits:
+ *   bits(y[i]) = bits(x[i]) ^ bits(tab[idx_0]) ^ ... ^ bits(tab[idx_{t-1}])
+ * over the lane's side (y is not the region's value). Arguments and errors as
+ * meld_divergent_region_f32. */
+meld_status meld_probe_region_gathers(meld_ctx *ctx, const float *x, float *y, size_t n,
+                                      const float *tab, size_t tab_len, uint64_t seed,
+                                      uint64_t thr, meld_side side_true, meld_side side_false,
+                                      meld_variant variant, void *stream);
+
 /* Three-way region (the paper's synthetic benchmark SB4, Evaluation section:
  * an if / else-if / else whose three blocks compute alike on different data;
  * its melding is region replication, Detailed Design, "Basic block-Region
@@ -447,6 +459,10 @@ typedef struct {
     uint64_t thr;             /* region: branch threshold in [0, 2^32] */
     meld_side side_true;      /* region sides */
     meld_side side_false;
+    double arrival_s;         /* scheduled arrival on the server's clock (meld_server_now):
+                                 a job submitted ahead waits until then; <= 0, or a time
+                                 already past, queues it at once. Latency is measured
+                                 from it (from the submit time when <= 0). */
 } meld_job;
 
 typedef struct {
@@ -454,6 +470,7 @@ typedef struct {
     meld_status status;       /* MELD_EHIP if its launch failed */
     int kind;
     size_t n;
+    double arrival_s;         /* the job's arrival (its submit time if it gave none) */
     double submit_s, start_s, done_s;  /* seconds since the server was created */
     const void *result_dev;   /* device u32[n] sorted keys or f32[n] y; NULL on failure;
                                  valid until meld_server_release(job_id) */
@@ -483,8 +500,9 @@ meld_status meld_server_create_simulated(size_t mem_budget_bytes, int slots, dou
                                          const uint64_t *fail_ids, size_t n_fail,
                                          meld_server **out);
 
-/* Queues a job; returns its id. MELD_ENOMEM if it needs more than the whole
- * budget (sort: 4n bytes; region: 8n bytes, each rounded up to 256). */
+/* Queues a job (or schedules it for its arrival_s); returns its id.
+ * MELD_ENOMEM if it needs more than the whole budget (sort: 4n bytes; region:
+ * 8n bytes, each rounded up to 256). */
 meld_status meld_server_submit(meld_server *srv, const meld_job *job, uint64_t *job_id);
 
 /* Moves up to cap completions into out (completion order). */
@@ -501,6 +519,10 @@ meld_status meld_server_read(meld_server *srv, uint64_t job_id, void *host_dst, 
 meld_status meld_server_drain(meld_server *srv, double timeout_s);
 
 meld_status meld_server_stats_get(meld_server *srv, meld_server_stats *out);
+
+/* Seconds since the server was created: the clock of arrival_s, submit_s,
+ * start_s and done_s. */
+double meld_server_now(meld_server *srv);
 
 /* Message of the last failed server call on this host thread. */
 const char *meld_server_last_error(void);

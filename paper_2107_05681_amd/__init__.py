@@ -38,7 +38,8 @@ EXPORTS = ("meld_version", "meld_create", "meld_destroy", "meld_last_error", "me
            "meld_server_destroy",
            "meld_divergent_region_f32", "meld_region3_f32", "meld_region_lanetrips_f32",
            "meld_oddeven_sort_buckets_u32", "meld_merge_sort_u32", "meld_sort_plan_describe",
-           "meld_sort_u32_timed", "meld_sort_u32_noalloc")
+           "meld_sort_u32_timed", "meld_sort_u32_noalloc", "meld_probe_region_gathers",
+           "meld_server_now")
 
 
 class MeldError(RuntimeError):
@@ -120,6 +121,9 @@ def load_library():
     lib.meld_set_option.argtypes = [vp, st, i64]
     lib.meld_divergent_region_f32.restype = st
     lib.meld_divergent_region_f32.argtypes = [vp, vp, vp, sz, vp, sz, u64, u64, Side, Side, st, vp]
+    lib.meld_probe_region_gathers.restype = st
+    lib.meld_probe_region_gathers.argtypes = [vp, vp, vp, sz, vp, sz, u64, u64, Side, Side, st,
+                                              vp]
     lib.meld_merge_sort_u32.restype = st
     lib.meld_merge_sort_u32.argtypes = [vp, vp, sz, i64, st, vp]
     lib.meld_oddeven_sort_buckets_u32.restype = st
@@ -322,11 +326,14 @@ def _region_tensors(x, tab, out):
 
 
 def divergent_region(x, tab, seed: int, thr: int, side_true, side_false, variant=AUTO,
-                     out=None, stream=None, ctx=None):
-    """Two-sided loop region over the lanes of ``x`` (see meld_divergent_region_f32)."""
+                     out=None, stream=None, ctx=None, gathers_only=False):
+    """Two-sided loop region over the lanes of ``x`` (see meld_divergent_region_f32).
+    gathers_only: the form's memory path alone (meld_probe_region_gathers)."""
     out = _region_tensors(x, tab, out)
     c, s = _launch_args(x, stream, ctx)
-    _check(load_library().meld_divergent_region_f32(
+    lib = load_library()
+    fn = lib.meld_probe_region_gathers if gathers_only else lib.meld_divergent_region_f32
+    _check(fn(
         c, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), x.numel(),
         ctypes.c_void_p(tab.data_ptr()), tab.numel(), int(seed), int(thr),
         _as_side(side_true), _as_side(side_false), _variant(variant), s))

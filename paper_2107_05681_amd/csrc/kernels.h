@@ -19,6 +19,13 @@ hipError_t launch_region(const float *x, float *y, uint32_t n, const float *tab,
                          uint64_t seed, uint64_t thr, RegionSide T, RegionSide F, RegionForm form,
                          hipStream_t stream);
 
+// The region's memory path alone: launch_region's lanes, branch, addresses,
+// exec masks and batching with the fma replaced by an xor of the gathered
+// bits (y is not the region's value). For measuring a form's ceiling.
+hipError_t launch_region_gathers(const float *x, float *y, uint32_t n, const float *tab,
+                                 uint32_t mask, uint64_t seed, uint64_t thr, RegionSide T,
+                                 RegionSide F, RegionForm form, hipStream_t stream);
+
 // Three-way region (region_variants.hip): way 0 below thr0, way 1 below thr1,
 // way 2 otherwise (thr0 <= thr1 <= 2^32).
 hipError_t launch_region3(const float *x, float *y, uint32_t n, const float *tab, uint32_t mask,

@@ -67,6 +67,9 @@ struct meld_ctx {
 
 namespace {
 constexpr size_t kProbeWords = 64;
+// Tie window of the sort tuner's second round (relative): the spread of the
+// medians of five 2^28-pair sorts or nine smaller ones on one MI355X.
+constexpr double kFinalTie = 0.005;
 
 // Scratch of meld_sort_u32_noalloc: the padding of a non-power-of-two sort,
 // in a device array of the library itself, so that the call allocates
@@ -707,10 +710,8 @@ meld_status auto_sort_plan(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, siz
     for (uint32_t t : tiles)
         for (bool x : xchs)
             for (int f = 0; f < 4; ++f) cands.push_back(SortPlan{t, (f & 1) != 0, (f & 2) != 0, x});
-    const int reps = n >= (1u << 24) ? 2 : 3;
-    for (const SortPlan &p : cands) {
-        double t = 0;
-        st = time_median(
+    auto time_plan = [&](const SortPlan &p, int reps, double *t) {
+        return time_median(
             s, reps,
             [&]() -> meld_status {
                 hipError_t e = hipMemcpyAsync(tk, keys, n * 4, hipMemcpyDeviceToDevice, s);
@@ -718,7 +719,13 @@ meld_status auto_sort_plan(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, siz
                     e = hipMemcpyAsync(tv, payload, n * 4, hipMemcpyDeviceToDevice, s);
                 return e == hipSuccess ? MELD_OK : hip_fail(e, "tuning copy");
             },
-            [&]() { return sort_impl(ctx, tk, tv, n, p, -1, s); }, &t);
+            [&]() { return sort_impl(ctx, tk, tv, n, p, -1, s); }, t);
+    };
+    // Round 1: every candidate, a few runs each.
+    const int reps = n >= (1u << 24) ? 2 : 3;
+    for (const SortPlan &p : cands) {
+        double t = 0;
+        st = time_plan(p, reps, &t);
         if (st != MELD_OK) return st;
         ms.push_back(t);
         flo.push_back(p.lo);
@@ -727,8 +734,40 @@ meld_status auto_sort_plan(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, siz
     double mixed_lo = 0, mixed_hi = 0;
     st = probe_network(ctx, std::min(log_n, max_t), s, &mixed_lo, &mixed_hi);
     if (st != MELD_OK) return st;
-    const int pick = meld::choose((int)cands.size(), ms.data(), flo.data(), fhi.data(), mixed_lo,
-                                  mixed_hi, ctx->theta, ctx->tie);
+    // Round 2: the candidates within the tie window of the fastest, timed
+    // again with more runs, interleaved; the probe then breaks ties only
+    // within a window of kFinalTie, the run-to-run spread of these medians
+    // (the first round's few runs cannot separate plans a percent apart).
+    const double best_ms = *std::min_element(ms.begin(), ms.end());
+    std::vector<int> finalists;
+    for (int i = 0; i < (int)cands.size(); ++i)
+        if (ms[i] <= best_ms * (1.0 + ctx->tie)) finalists.push_back(i);
+    int pick = 0;
+    if (finalists.size() > 1) {
+        const int reps2 = n >= (1u << 24) ? 5 : 9;
+        std::vector<std::vector<double>> runs(finalists.size());
+        for (int r = 0; r < reps2; ++r)
+            for (size_t f = 0; f < finalists.size(); ++f) {
+                double t = 0;
+                st = time_plan(cands[finalists[f]], 1, &t);
+                if (st != MELD_OK) return st;
+                runs[f].push_back(t);
+            }
+        std::vector<double> ms2;
+        std::vector<int> flo2, fhi2;
+        for (size_t f = 0; f < finalists.size(); ++f) {
+            std::sort(runs[f].begin(), runs[f].end());
+            ms2.push_back(runs[f][runs[f].size() / 2]);
+            flo2.push_back(flo[finalists[f]]);
+            fhi2.push_back(fhi[finalists[f]]);
+            ms[finalists[f]] = ms2.back();
+        }
+        const int p2 = meld::choose((int)finalists.size(), ms2.data(), flo2.data(), fhi2.data(),
+                                    mixed_lo, mixed_hi, ctx->theta, kFinalTie);
+        pick = finalists[p2];
+    } else {
+        pick = finalists[0];
+    }
     *out = cands[pick];
     meld::TuneEntry e;
     e.op = "sort";
@@ -1028,6 +1067,45 @@ meld_status merge_sort_impl(meld_ctx *ctx, uint32_t *keys, size_t n, int64_t max
     return MELD_OK;
 }
 
+// The region call and its gathers-only probe: argument checks, MELD_AUTO,
+// launch.
+meld_status region_entry(meld_ctx *ctx, const float *x, float *y, size_t n, const float *tab,
+                         size_t tab_len, uint64_t seed, uint64_t thr, meld_side side_true,
+                         meld_side side_false, meld_variant variant, void *stream,
+                         bool gathers_only, const char *name) {
+    if (ctx == nullptr) return fail(MELD_EINVAL, "%s: ctx is NULL", name);
+    if (n >= (1ull << 32)) return fail(MELD_EINVAL, "%s: n >= 2^32", name);
+    if (tab_len == 0 || (tab_len & (tab_len - 1)) != 0 || tab_len > (1ull << 32))
+        return fail(MELD_EINVAL,
+                    "%s: tab_len = %zu is not a power of two <= 2^32", name,
+                    tab_len);
+    if (thr > (1ull << 32))
+        return fail(MELD_EINVAL, "%s: thr > 2^32", name);
+    if (side_true.trips > 65536 || side_false.trips > 65536)
+        return fail(MELD_EINVAL, "%s: trips > 65536", name);
+    if ((unsigned)variant > MELD_MELDED_INPLACE)
+        return fail(MELD_EINVAL, "%s: bad variant", name);
+    if (n == 0) return MELD_OK;
+    DeviceGuard g(ctx->device);
+    if (!is_device_ptr(ctx, x) || !is_device_ptr(ctx, y) || !is_device_ptr(ctx, tab))
+        return fail(MELD_EINVAL,
+                    "%s: x, y and tab must be device pointers on device %d", name,
+                    ctx->device);
+    if (x == y) return fail(MELD_EINVAL, "%s: y aliases x", name);
+    const meld::RegionSide T{side_true.a, side_true.off, side_true.step, side_true.trips};
+    const meld::RegionSide F{side_false.a, side_false.off, side_false.step, side_false.trips};
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    meld::RegionForm form = region_form(variant);
+    if (variant == MELD_AUTO) {
+        meld_status st = auto_region_form(ctx, x, y, n, tab, tab_len, seed, thr, T, F, s, &form);
+        if (st != MELD_OK) return st;
+    }
+    auto launch = gathers_only ? meld::launch_region_gathers : meld::launch_region;
+    hipError_t e = launch(x, y, (uint32_t)n, tab, (uint32_t)(tab_len - 1), seed, thr, T, F, form, s);
+    if (e != hipSuccess) return hip_fail(e, "region launch");
+    return MELD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1304,37 +1382,16 @@ meld_status meld_divergent_region_f32(meld_ctx *ctx, const float *x, float *y, s
                                       const float *tab, size_t tab_len, uint64_t seed,
                                       uint64_t thr, meld_side side_true, meld_side side_false,
                                       meld_variant variant, void *stream) {
-    if (ctx == nullptr) return fail(MELD_EINVAL, "meld_divergent_region_f32: ctx is NULL");
-    if (n >= (1ull << 32)) return fail(MELD_EINVAL, "meld_divergent_region_f32: n >= 2^32");
-    if (tab_len == 0 || (tab_len & (tab_len - 1)) != 0 || tab_len > (1ull << 32))
-        return fail(MELD_EINVAL,
-                    "meld_divergent_region_f32: tab_len = %zu is not a power of two <= 2^32",
-                    tab_len);
-    if (thr > (1ull << 32))
-        return fail(MELD_EINVAL, "meld_divergent_region_f32: thr > 2^32");
-    if (side_true.trips > 65536 || side_false.trips > 65536)
-        return fail(MELD_EINVAL, "meld_divergent_region_f32: trips > 65536");
-    if ((unsigned)variant > MELD_MELDED_INPLACE)
-        return fail(MELD_EINVAL, "meld_divergent_region_f32: bad variant");
-    if (n == 0) return MELD_OK;
-    DeviceGuard g(ctx->device);
-    if (!is_device_ptr(ctx, x) || !is_device_ptr(ctx, y) || !is_device_ptr(ctx, tab))
-        return fail(MELD_EINVAL,
-                    "meld_divergent_region_f32: x, y and tab must be device pointers on device %d",
-                    ctx->device);
-    if (x == y) return fail(MELD_EINVAL, "meld_divergent_region_f32: y aliases x");
-    const meld::RegionSide T{side_true.a, side_true.off, side_true.step, side_true.trips};
-    const meld::RegionSide F{side_false.a, side_false.off, side_false.step, side_false.trips};
-    const hipStream_t s = static_cast<hipStream_t>(stream);
-    meld::RegionForm form = region_form(variant);
-    if (variant == MELD_AUTO) {
-        meld_status st = auto_region_form(ctx, x, y, n, tab, tab_len, seed, thr, T, F, s, &form);
-        if (st != MELD_OK) return st;
-    }
-    hipError_t e = meld::launch_region(x, y, (uint32_t)n, tab, (uint32_t)(tab_len - 1), seed, thr,
-                                       T, F, form, s);
-    if (e != hipSuccess) return hip_fail(e, "region launch");
-    return MELD_OK;
+    return region_entry(ctx, x, y, n, tab, tab_len, seed, thr, side_true, side_false, variant,
+                        stream, false, "meld_divergent_region_f32");
+}
+
+meld_status meld_probe_region_gathers(meld_ctx *ctx, const float *x, float *y, size_t n,
+                                      const float *tab, size_t tab_len, uint64_t seed,
+                                      uint64_t thr, meld_side side_true, meld_side side_false,
+                                      meld_variant variant, void *stream) {
+    return region_entry(ctx, x, y, n, tab, tab_len, seed, thr, side_true, side_false, variant,
+                        stream, true, "meld_probe_region_gathers");
 }
 
 meld_status meld_region3_f32(meld_ctx *ctx, const float *x, float *y, size_t n,

@@ -31,6 +31,11 @@
 // read by lane i at step k is read again by lane i + step at step k - 1, and
 // with the hardware's round-robin placement such lanes would sit in another
 // XCD's L2 (table traffic 250 -> 135 MB per 2^24 lanes).
+//
+// Each kernel also exists with ONLY_GATHERS set: the same lanes, branch,
+// addresses, exec masks and batching, with the fma replaced by an xor of the
+// gathered bits. It measures what the form's memory path alone costs (the
+// ceiling the fma chain runs under); its y is not the region's value.
 #include "device_common.h"
 #include "kernels.h"
 #include "region_steps.h"
@@ -39,8 +44,7 @@ namespace meld {
 
 namespace {
 
-
-
+template <bool ONLY_GATHERS>
 __global__ __launch_bounds__(kRegionThreads) void region_divergent_kernel(
     const float *__restrict__ x, float *__restrict__ y, uint32_t n, uint32_t lane0,
     const float *__restrict__ tab,
@@ -52,16 +56,17 @@ __global__ __launch_bounds__(kRegionThreads) void region_divergent_kernel(
     float acc = x[i];
     if (taken) {
         MELD_SIDE_MARK("true");
-        acc = side_steps(acc, i + T.off, T.trips, T.a, T.step, tab, mask);
+        acc = side_steps<ONLY_GATHERS>(acc, i + T.off, T.trips, T.a, T.step, tab, mask);
     } else {
         MELD_SIDE_MARK("false");
-        acc = side_steps(acc, i + F.off, F.trips, F.a, F.step, tab, mask);
+        acc = side_steps<ONLY_GATHERS>(acc, i + F.off, F.trips, F.a, F.step, tab, mask);
     }
     y[i] = acc;
 }
 
 // Steps only the longer side has: unaligned, run by that side's lanes with
 // that side's own operands.
+template <bool ONLY_GATHERS>
 __device__ __forceinline__ float longer_side_steps(float acc, uint32_t i, bool taken,
                                                    const float *__restrict__ tab, uint32_t mask,
                                                    const RegionSide &T, const RegionSide &F,
@@ -70,12 +75,14 @@ __device__ __forceinline__ float longer_side_steps(float acc, uint32_t i, bool t
     const uint32_t extra = true_longer ? T.trips - common : F.trips - common;
     if (extra != 0 && taken == true_longer) {
         const RegionSide L = true_longer ? T : F;
-        acc = side_steps(acc, i + L.off + common * L.step, extra, L.a, L.step, tab, mask);
+        acc = side_steps<ONLY_GATHERS>(acc, i + L.off + common * L.step, extra, L.a, L.step, tab,
+                                       mask);
     }
     return acc;
 }
 
 // The melded form used by the library.
+template <bool ONLY_GATHERS>
 __global__ __launch_bounds__(kRegionThreads) void region_melded_kernel(
     const float *__restrict__ x, float *__restrict__ y, uint32_t n, uint32_t lane0,
     const float *__restrict__ tab,
@@ -87,9 +94,9 @@ __global__ __launch_bounds__(kRegionThreads) void region_melded_kernel(
     const float a = taken ? T.a : F.a;  // differing operand of the aligned fma: a select
     const uint32_t common = T.trips < F.trips ? T.trips : F.trips;
     float acc = x[i];
-    acc = melded_common_steps(acc, taken, i + T.off, i + F.off, common, a, T.step, F.step, tab,
-                              mask);
-    y[i] = longer_side_steps(acc, i, taken, tab, mask, T, F, common);
+    acc = melded_common_steps<ONLY_GATHERS>(acc, taken, i + T.off, i + F.off, common, a, T.step,
+                                            F.step, tab, mask);
+    y[i] = longer_side_steps<ONLY_GATHERS>(acc, i, taken, tab, mask, T, F, common);
 }
 
 // The melded form with the gathers aligned as well: one gather instruction per
@@ -98,6 +105,7 @@ __global__ __launch_bounds__(kRegionThreads) void region_melded_kernel(
 // a gather whose lanes mix two address streams costs several times the
 // vector-memory work of one lane-linear stream, which makes this form slower
 // than the divergent one whenever the sides read different data.
+template <bool ONLY_GATHERS>
 __global__ __launch_bounds__(kRegionThreads) void region_melded_inplace_kernel(
     const float *__restrict__ x, float *__restrict__ y, uint32_t n, uint32_t lane0,
     const float *__restrict__ tab,
@@ -110,8 +118,24 @@ __global__ __launch_bounds__(kRegionThreads) void region_melded_inplace_kernel(
     const uint32_t off = taken ? T.off : F.off;
     const uint32_t step = taken ? T.step : F.step;
     const uint32_t common = T.trips < F.trips ? T.trips : F.trips;
-    float acc = side_steps(x[i], i + off, common, a, step, tab, mask);
-    y[i] = longer_side_steps(acc, i, taken, tab, mask, T, F, common);
+    float acc = side_steps<ONLY_GATHERS>(x[i], i + off, common, a, step, tab, mask);
+    y[i] = longer_side_steps<ONLY_GATHERS>(acc, i, taken, tab, mask, T, F, common);
+}
+
+template <bool ONLY_GATHERS>
+hipError_t launch_region_t(const float *x, float *y, uint32_t n, const float *tab, uint32_t mask,
+                           uint64_t seed, uint64_t thr, RegionSide T, RegionSide F,
+                           RegionForm form, hipStream_t stream) {
+    const uint64_t bkey = stream_key(seed, 4);
+    auto kern = form == RegionForm::kMelded          ? region_melded_kernel<ONLY_GATHERS>
+                : form == RegionForm::kMeldedInPlace ? region_melded_inplace_kernel<ONLY_GATHERS>
+                                                     : region_divergent_kernel<ONLY_GATHERS>;
+    for (uint64_t i0 = 0; i0 < n; i0 += kRegionLaunchLanes) {
+        const uint32_t len = (uint32_t)(n - i0 < kRegionLaunchLanes ? n - i0 : kRegionLaunchLanes);
+        hipLaunchKernelGGL(kern, dim3(blocks_for(len, kRegionThreads)), dim3(kRegionThreads), 0,
+                           stream, x, y, n, (uint32_t)i0, tab, mask, bkey, thr, T, F);
+    }
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -119,16 +143,13 @@ __global__ __launch_bounds__(kRegionThreads) void region_melded_inplace_kernel(
 hipError_t launch_region(const float *x, float *y, uint32_t n, const float *tab, uint32_t mask,
                          uint64_t seed, uint64_t thr, RegionSide T, RegionSide F, RegionForm form,
                          hipStream_t stream) {
-    const uint64_t bkey = stream_key(seed, 4);
-    auto kern = form == RegionForm::kMelded          ? region_melded_kernel
-                : form == RegionForm::kMeldedInPlace ? region_melded_inplace_kernel
-                                                     : region_divergent_kernel;
-    for (uint64_t i0 = 0; i0 < n; i0 += kRegionLaunchLanes) {
-        const uint32_t len = (uint32_t)(n - i0 < kRegionLaunchLanes ? n - i0 : kRegionLaunchLanes);
-        hipLaunchKernelGGL(kern, dim3(blocks_for(len, kRegionThreads)), dim3(kRegionThreads), 0,
-                           stream, x, y, n, (uint32_t)i0, tab, mask, bkey, thr, T, F);
-    }
-    return hipGetLastError();
+    return launch_region_t<false>(x, y, n, tab, mask, seed, thr, T, F, form, stream);
+}
+
+hipError_t launch_region_gathers(const float *x, float *y, uint32_t n, const float *tab,
+                                 uint32_t mask, uint64_t seed, uint64_t thr, RegionSide T,
+                                 RegionSide F, RegionForm form, hipStream_t stream) {
+    return launch_region_t<true>(x, y, n, tab, mask, seed, thr, T, F, form, stream);
 }
 
 }  // namespace meld

@@ -31,10 +31,20 @@ __device__ __forceinline__ void gather_group(float (&g)[G], uint32_t idx, uint32
     for (int u = 0; u < G; ++u) g[u] = tab[(idx + (uint32_t)u * step) & mask];
 }
 
-template <int G>
+// One step's arithmetic: the region's fma, or (ONLY_GATHERS, for measuring
+// what the gathers alone cost) an integer xor of the gathered bits.
+template <bool ONLY_GATHERS>
+__device__ __forceinline__ float step_op(float acc, float a, float g) {
+    if constexpr (ONLY_GATHERS)
+        return __uint_as_float(__float_as_uint(acc) ^ __float_as_uint(g));
+    else
+        return __builtin_fmaf(acc, a, g);
+}
+
+template <int G, bool ONLY_GATHERS = false>
 __device__ __forceinline__ float fma_group(float acc, float a, const float (&g)[G]) {
 #pragma unroll
-    for (int u = 0; u < G; ++u) acc = __builtin_fmaf(acc, a, g[u]);
+    for (int u = 0; u < G; ++u) acc = step_op<ONLY_GATHERS>(acc, a, g[u]);
     return acc;
 }
 
@@ -61,11 +71,12 @@ __device__ __forceinline__ void gather_chunk(Chunk &ch, uint32_t c, uint32_t idx
     if (c & 1) gather_group(ch.g1, idx, step, tab, mask);
 }
 
+template <bool ONLY_GATHERS = false>
 __device__ __forceinline__ float fma_chunk(float acc, float a, const Chunk &ch, uint32_t c) {
-    if (c & 8) acc = fma_group(acc, a, ch.g8);
-    if (c & 4) acc = fma_group(acc, a, ch.g4);
-    if (c & 2) acc = fma_group(acc, a, ch.g2);
-    if (c & 1) acc = fma_group(acc, a, ch.g1);
+    if (c & 8) acc = fma_group<8, ONLY_GATHERS>(acc, a, ch.g8);
+    if (c & 4) acc = fma_group<4, ONLY_GATHERS>(acc, a, ch.g4);
+    if (c & 2) acc = fma_group<2, ONLY_GATHERS>(acc, a, ch.g2);
+    if (c & 1) acc = fma_group<1, ONLY_GATHERS>(acc, a, ch.g1);
     return acc;
 }
 
@@ -78,6 +89,7 @@ constexpr uint32_t kBatch = 8;
 constexpr uint32_t kChunkMax = 2 * kBatch;
 
 // Steps of one side.
+template <bool ONLY_GATHERS = false>
 __device__ __forceinline__ float side_steps(float acc, uint32_t idx, uint32_t steps, float a,
                                             uint32_t step, const float *__restrict__ tab,
                                             uint32_t mask) {
@@ -85,14 +97,14 @@ __device__ __forceinline__ float side_steps(float acc, uint32_t idx, uint32_t st
     for (; k + kChunkMax <= steps; k += kBatch) {
         float g[kBatch];
         gather_group(g, idx, step, tab, mask);
-        acc = fma_group(acc, a, g);
+        acc = fma_group<kBatch, ONLY_GATHERS>(acc, a, g);
         idx += kBatch * step;
     }
     const uint32_t c = steps - k;
     if (c != 0) {
         Chunk ch;
         gather_chunk(ch, c, idx, step, tab, mask);
-        acc = fma_chunk(acc, a, ch, c);
+        acc = fma_chunk<ONLY_GATHERS>(acc, a, ch, c);
     }
     return acc;
 }
@@ -103,6 +115,7 @@ __device__ __forceinline__ float side_steps(float acc, uint32_t idx, uint32_t st
 // instructions), while the index arithmetic, the fma chain and the loop
 // control run once on the whole wave with the multiplier selected per lane.
 // Same batching as side_steps.
+template <bool ONLY_GATHERS = false>
 __device__ __forceinline__ float melded_common_steps(float acc, bool taken, uint32_t idx_t,
                                                      uint32_t idx_f, uint32_t steps, float a,
                                                      uint32_t step_t, uint32_t step_f,
@@ -130,7 +143,7 @@ __device__ __forceinline__ float melded_common_steps(float acc, bool taken, uint
         float g[kBatch];
 #pragma unroll
         for (int u = 0; u < (int)kBatch; ++u) g[u] = taken ? gt[u] : gf[u];
-        acc = fma_group(acc, a, g);
+        acc = fma_group<kBatch, ONLY_GATHERS>(acc, a, g);
         idx_t += kBatch * step_t;
         idx_f += kBatch * step_f;
     }
@@ -146,7 +159,7 @@ __device__ __forceinline__ float melded_common_steps(float acc, bool taken, uint
             gather_chunk(ch, c, idx_f, step_f, tab, mask);
             MELD_SIDE_MARK("gathers false end");
         }
-        acc = fma_chunk(acc, a, ch, c);
+        acc = fma_chunk<ONLY_GATHERS>(acc, a, ch, c);
     }
     return acc;
 }

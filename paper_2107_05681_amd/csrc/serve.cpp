@@ -63,7 +63,7 @@ size_t job_bytes(const meld_job &j) {
 struct JobRec {
     meld_job job;
     uint64_t id = 0;
-    double submit_s = 0, start_s = 0, done_s = 0;
+    double arrival_s = 0, submit_s = 0, start_s = 0, done_s = 0;
     meld_status status = MELD_OK;
     size_t offset = 0;     // within the unit's arena block
     int unit = -1;         // index into Server::units_
@@ -309,6 +309,9 @@ struct meld_server {
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
     uint64_t next_id = 1;
     std::deque<uint64_t> pending;
+    // Jobs submitted ahead of their arrival, by (arrival, submission order):
+    // they join the queue when the server's clock reaches their arrival.
+    std::multimap<double, uint64_t> future;
     std::map<uint64_t, JobRec> jobs;
     std::deque<uint64_t> completed;
     std::vector<Unit> units;           // indexed by unit id
@@ -445,15 +448,27 @@ struct meld_server {
         jobs.erase(id);
     }
 
+    // Moves the jobs whose arrival has come from `future` to the queue.
+    void arrive() {
+        const double t = now();
+        while (!future.empty() && future.begin()->first <= t) {
+            pending.push_back(future.begin()->second);
+            future.erase(future.begin());
+        }
+    }
+
     void run() {
         exec->thread_init();
         std::unique_lock<std::mutex> lk(mu);
         while (!stop) {
+            arrive();
             poll_units();
             admit();
             bool busy = false;
             for (int su : slot_unit) busy |= su >= 0;
-            cv.wait_for(lk, busy ? std::chrono::microseconds(20) : std::chrono::milliseconds(2));
+            double wait_s = busy ? 20e-6 : 2e-3;
+            if (!future.empty()) wait_s = std::min(wait_s, std::max(0.0, future.begin()->first - now()));
+            cv.wait_for(lk, std::chrono::duration<double>(wait_s));
         }
     }
 };
@@ -538,8 +553,14 @@ meld_status meld_server_submit(meld_server *srv, const meld_job *job, uint64_t *
     rec.job = *job;
     rec.id = srv->next_id++;
     rec.submit_s = srv->now();
+    // A job scheduled ahead waits for its arrival; one submitted at or after
+    // its arrival (or with none, arrival_s <= 0) joins the queue now.
+    rec.arrival_s = job->arrival_s > 0 ? job->arrival_s : rec.submit_s;
     srv->jobs[rec.id] = rec;
-    srv->pending.push_back(rec.id);
+    if (rec.arrival_s > rec.submit_s)
+        srv->future.emplace(rec.arrival_s, rec.id);
+    else
+        srv->pending.push_back(rec.id);
     if (job_id) *job_id = rec.id;
     srv->cv.notify_one();
     return MELD_OK;
@@ -559,6 +580,7 @@ meld_status meld_server_poll(meld_server *srv, meld_completion *out, size_t cap,
         c.status = j.status;
         c.kind = j.job.kind;
         c.n = j.job.n;
+        c.arrival_s = j.arrival_s;
         c.submit_s = j.submit_s;
         c.start_s = j.start_s;
         c.done_s = j.done_s;
@@ -589,7 +611,7 @@ meld_status meld_server_drain(meld_server *srv, double timeout_s) {
     for (;;) {
         {
             std::lock_guard<std::mutex> lk(srv->mu);
-            bool busy = !srv->pending.empty();
+            bool busy = !srv->pending.empty() || !srv->future.empty();
             for (int su : srv->slot_unit) busy |= su >= 0;
             if (!busy) return MELD_OK;
         }
@@ -624,9 +646,11 @@ meld_status meld_server_stats_get(meld_server *srv, meld_server_stats *out) {
     if (srv == nullptr || out == nullptr) return serve_fail(MELD_EINVAL, "meld_server_stats_get: NULL");
     std::lock_guard<std::mutex> lk(srv->mu);
     *out = srv->stats;
-    out->pending = srv->pending.size();
+    out->pending = srv->pending.size() + srv->future.size();
     return MELD_OK;
 }
+
+double meld_server_now(meld_server *srv) { return srv == nullptr ? 0.0 : srv->now(); }
 
 void meld_server_destroy(meld_server *srv) {
     if (srv == nullptr) return;

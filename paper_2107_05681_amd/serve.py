@@ -11,12 +11,14 @@ JOB_SORT, JOB_REGION = 0, 1
 
 class Job(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("n", ctypes.c_size_t), ("seed", ctypes.c_uint64),
-                ("thr", ctypes.c_uint64), ("side_true", Side), ("side_false", Side)]
+                ("thr", ctypes.c_uint64), ("side_true", Side), ("side_false", Side),
+                ("arrival_s", ctypes.c_double)]
 
 
 class Completion(ctypes.Structure):
     _fields_ = [("job_id", ctypes.c_uint64), ("status", ctypes.c_int), ("kind", ctypes.c_int),
-                ("n", ctypes.c_size_t), ("submit_s", ctypes.c_double),
+                ("n", ctypes.c_size_t), ("arrival_s", ctypes.c_double),
+                ("submit_s", ctypes.c_double),
                 ("start_s", ctypes.c_double), ("done_s", ctypes.c_double),
                 ("result_dev", ctypes.c_void_p), ("batched", ctypes.c_int)]
 
@@ -57,6 +59,8 @@ def _lib():
         lib.meld_server_last_error.argtypes = []
         lib.meld_server_destroy.restype = None
         lib.meld_server_destroy.argtypes = [vp]
+        lib.meld_server_now.restype = ctypes.c_double
+        lib.meld_server_now.argtypes = [vp]
         lib._serve_bound = True
     return lib
 
@@ -83,10 +87,16 @@ class Server:
                                                     len(fail_ids), ctypes.byref(self._h)))
         self._buf = (Completion * 4096)()
 
-    def submit(self, job: dict) -> int:
+    def now(self) -> float:
+        """Seconds on the server's clock (the clock of arrival_s and the completions)."""
+        return float(_lib().meld_server_now(self._h))
+
+    def submit(self, job: dict, arrival_s: float = 0.0) -> int:
+        """Queues a job; with arrival_s (server clock) ahead of now it waits until then."""
         j = Job(int(job["kind"]), int(job["n"]), int(job["seed"]), int(job.get("thr", 0)),
                 _as_side(job.get("side_true", dict(a=1, off=0, step=1, trips=0))),
-                _as_side(job.get("side_false", dict(a=1, off=0, step=1, trips=0))))
+                _as_side(job.get("side_false", dict(a=1, off=0, step=1, trips=0))),
+                float(arrival_s))
         jid = ctypes.c_uint64()
         _check(_lib().meld_server_submit(self._h, ctypes.byref(j), ctypes.byref(jid)))
         return int(jid.value)
@@ -99,7 +109,8 @@ class Server:
             for i in range(n.value):
                 c = self._buf[i]
                 out.append(dict(job_id=int(c.job_id), status=int(c.status), kind=int(c.kind),
-                                n=int(c.n), submit_s=c.submit_s, start_s=c.start_s,
+                                n=int(c.n), arrival_s=c.arrival_s, submit_s=c.submit_s,
+                                start_s=c.start_s,
                                 done_s=c.done_s, result_dev=c.result_dev, batched=c.batched))
             if n.value < len(self._buf):
                 return out
@@ -134,19 +145,21 @@ class Server:
 
 
 def replay(server: Server, trace: list[dict], on_complete=None, release=True,
-           timeout_s=120.0) -> list[dict]:
-    """Submits each job at its arrival time (relative to now), collects every completion.
-
-    ``on_complete(completion, job)`` runs before the result is released."""
-    done, by_id = [], {}
-    t0 = time.perf_counter()
-    i = 0
-    deadline = t0 + timeout_s
+           timeout_s=120.0, lead_s=None) -> list[dict]:
+    """Runs a trace: every job is submitted ahead with its scheduled arrival on the
+    server's clock (start + the trace's arrival_s, start = now + lead_s), so the
+    server admits it at its arrival however late the host loop runs; then collects
+    every completion. ``on_complete(completion, job)`` runs before the result is
+    released."""
+    if lead_s is None:
+        lead_s = 0.05 + 2e-5 * len(trace)  # time to submit the whole trace
+    start = server.now() + lead_s
+    by_id = {}
+    for job in trace:
+        by_id[server.submit(job, arrival_s=start + job["arrival_s"])] = job
+    done = []
+    deadline = time.perf_counter() + lead_s + (trace[-1]["arrival_s"] if trace else 0) + timeout_s
     while len(done) < len(trace):
-        now = time.perf_counter() - t0
-        while i < len(trace) and trace[i]["arrival_s"] <= now:
-            by_id[server.submit(trace[i])] = trace[i]
-            i += 1
         comps = server.poll()
         for c in comps:
             job = by_id[c["job_id"]]
@@ -158,19 +171,25 @@ def replay(server: Server, trace: list[dict], on_complete=None, release=True,
         if not comps:
             if time.perf_counter() > deadline:
                 raise TimeoutError(f"{len(done)} of {len(trace)} jobs completed")
-            nxt = trace[i]["arrival_s"] - (time.perf_counter() - t0) if i < len(trace) else 1e-4
-            time.sleep(min(max(nxt, 0.0), 1e-4))
+            time.sleep(1e-4)
     return done
 
 
 def latency_summary(done: list[dict]) -> dict:
+    """Latency from each job's arrival (its submit time where it has none) to its
+    completion, the queue wait (arrival to start), the submit lead (arrival minus
+    submit: how far ahead of its arrival the job was handed over), throughput over
+    the span from the first arrival to the last completion, and the share of that
+    span during which at least one job ran."""
     import numpy as np
-    lat = np.array([c["done_s"] - c["submit_s"] for c in done])
-    span = max(c["done_s"] for c in done) - min(c["submit_s"] for c in done)
+    arr = np.array([c.get("arrival_s", c["submit_s"]) for c in done])
+    sub = np.array([c["submit_s"] for c in done])
+    lat = np.array([c["done_s"] for c in done]) - arr
+    wait = np.array([c["start_s"] for c in done]) - arr
+    lead = arr - sub
+    span = max(c["done_s"] for c in done) - float(arr.min())
     keys = sum(c["n"] for c in done if c["kind"] == JOB_SORT)
     lanes = sum(c["n"] for c in done if c["kind"] == JOB_REGION)
-    wait = np.array([c["start_s"] - c["submit_s"] for c in done])
-    # utilisation: the share of the span during which at least one job ran
     busy, end = 0.0, -np.inf
     for a, b in sorted((c["start_s"], c["done_s"]) for c in done):
         if a > end:
@@ -183,5 +202,7 @@ def latency_summary(done: list[dict]) -> dict:
                 p99_ms=float(np.percentile(lat, 99) * 1e3), mean_ms=float(lat.mean() * 1e3),
                 wait_p50_ms=float(np.percentile(wait, 50) * 1e3),
                 wait_p99_ms=float(np.percentile(wait, 99) * 1e3),
+                submit_lead_p50_ms=float(np.percentile(lead, 50) * 1e3),
+                submit_lead_min_ms=float(lead.min() * 1e3),
                 jobs_per_s=len(done) / span, keys_per_s=keys / span, lanes_per_s=lanes / span,
                 span_s=span, busy_fraction=busy / span if span > 0 else 0.0)

@@ -129,3 +129,28 @@ def test_region_rejects_bad_arguments():
                                        ctypes.c_void_p(y.data_ptr()), 128,
                                        ctypes.c_void_p(tab.data_ptr()), 16, 1, 0, s, s, 1, None)
     assert st == meld.EINVAL
+
+
+@pytest.mark.parametrize("p", [0.1, 0.5, 0.9])
+def test_gathers_only_probe_reads_the_region_addresses(p):
+    # meld_probe_region_gathers: every form reads exactly the region's table
+    # entries; y = x ^ tab[idx_0] ^ ... ^ tab[idx_{t-1}] as bits, per the lane's
+    # side (numpy, with the oracle's branch bits).
+    seed, n, tab_log2 = 4, (1 << 14) + 19, 16
+    x, tab, st, sf = workloads.region_inputs(seed, n, tab_log2=tab_log2)
+    st["trips"], sf["trips"] = 5, 19
+    thr = workloads.thr_from_p(p)
+    mask = (1 << tab_log2) - 1
+    taken = np.array([(oracle.branch_hash(seed, i) >> 32) < thr for i in range(n)])
+    lanes = np.arange(n, dtype=np.uint64)
+    tb = tab.view(np.uint32)
+    want = x.view(np.uint32).copy()
+    for side, sel in ((st, taken), (sf, ~taken)):
+        for k in range(side["trips"]):
+            idx = ((lanes + side["off"] + k * side["step"]) % (1 << 32)).astype(np.uint64) & mask
+            want[sel] ^= tb[idx[sel]]
+    dev = _dev()
+    xd, td = torch.from_numpy(x).to(dev), torch.from_numpy(tab).to(dev)
+    for v in VARIANTS:
+        y = meld.divergent_region(xd, td, seed, thr, st, sf, variant=v, gathers_only=True)
+        assert np.array_equal(y.cpu().numpy().view(np.uint32), want), (v, p)

@@ -1,5 +1,6 @@
 """Host-only tests of the serving scheduler over the simulated executor."""
 import os
+import time
 
 import pytest
 
@@ -114,3 +115,43 @@ def test_latency_summary_busy_fraction_and_waits():
     assert abs(s["busy_fraction"] - (3.0 + 1.0 + 0.5) / 10.0) < 1e-12
     assert abs(s["wait_p50_ms"] - 1000.0) < 1e-9  # waits 1.0, 1.5, 1.0, 0.5: median 1.0
     assert s["jobs"] == 4 and abs(s["keys_per_s"] - 4.0) < 1e-12
+
+
+def test_jobs_scheduled_ahead_start_no_earlier_than_their_arrival():
+    meld, serve = _serve()
+    with serve.Server(budget_bytes=1 << 30, slots=4, simulated_ns_per_item=1) as srv:
+        t0 = srv.now()
+        arrivals = [t0 + 0.05 + 0.002 * i for i in range(20)]
+        ids = [srv.submit(_sort(1000 + i, i), arrival_s=a) for i, a in enumerate(arrivals)]
+        assert srv.stats()["pending"] == 20  # not yet arrived
+        srv.drain(30)
+        comps = {c["job_id"]: c for c in srv.poll()}
+    for jid, a in zip(ids, arrivals):
+        c = comps[jid]
+        assert c["arrival_s"] == a and c["submit_s"] < a
+        assert c["start_s"] >= a and c["done_s"] >= c["start_s"]
+
+
+def test_latency_counts_from_the_arrival_not_the_submit():
+    meld, serve = _serve()
+    with serve.Server(budget_bytes=1 << 30, slots=1, simulated_ns_per_item=1) as srv:
+        time.sleep(0.6)
+        late = srv.now() - 0.5  # submitted half a second after its arrival
+        jid = srv.submit(_sort(100), arrival_s=late)
+        srv.drain(30)
+        c = srv.poll()[0]
+    assert c["job_id"] == jid and c["arrival_s"] == late
+    s = serve.latency_summary([c])
+    assert s["p50_ms"] >= 500.0 and s["submit_lead_min_ms"] <= -500.0
+
+
+def test_replay_schedules_the_trace_on_the_server_clock():
+    meld, serve = _serve()
+    trace = [dict(_sort(500 + i, i), arrival_s=0.001 * i) for i in range(50)]
+    with serve.Server(budget_bytes=1 << 30, slots=2, simulated_ns_per_item=1) as srv:
+        done = serve.replay(srv, trace, timeout_s=60)
+    done.sort(key=lambda c: c["job_id"])
+    base = done[0]["arrival_s"]
+    for job, c in zip(trace, done):
+        assert abs(c["arrival_s"] - base - job["arrival_s"]) < 1e-9
+        assert c["start_s"] >= c["arrival_s"] and c["submit_s"] <= c["arrival_s"]
