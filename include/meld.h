@@ -29,6 +29,13 @@
  *   - `stream` is a hipStream_t (NULL = the legacy default stream). Calls are
  *     asynchronous on it; results are ready once the stream has reached the
  *     call. Kernel faults surface at the caller's next synchronisation.
+ *     Exception: a call that needs more context scratch than the context
+ *     holds (the first non-power-of-two sort at a larger padding, a
+ *     segmented sort over more segments than before, the first MELD_AUTO
+ *     trials of a shape) waits for the device (hipDeviceSynchronize) before it
+ *     frees the smaller buffer and allocates the larger one; later calls of
+ *     that size or less are asynchronous. meld_sort_u32_noalloc never
+ *     allocates or waits.
  *   - Argument errors are detected before anything is enqueued and return
  *     MELD_EINVAL with a message in meld_last_error(); the arrays are then
  *     untouched. A failed launch returns MELD_EHIP.
