@@ -68,7 +68,7 @@ struct meld_ctx {
 namespace {
 constexpr size_t kProbeWords = 64;
 // Tie window of the sort tuner's second round (relative): the spread of the
-// medians of five 2^28-pair sorts or nine smaller ones on one MI355X.
+// medians of five or nine timed local-sort launches on one MI355X.
 constexpr double kFinalTie = 0.005;
 
 // Scratch of meld_sort_u32_noalloc: the padding of a non-power-of-two sort,
@@ -698,19 +698,7 @@ meld_status auto_sort_plan(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, siz
     if (st != MELD_OK) return st;
     uint32_t *tk = ctx->tune_buf;
     uint32_t *tv = pairs ? ctx->tune_buf + n : nullptr;
-    std::vector<SortPlan> cands;
-    std::vector<double> ms;
-    std::vector<int> flo, fhi;
-    // Low-phase paths: the forced one, else both (LDS network, lane exchanges).
-    std::vector<bool> xchs;
-    if (ctx->lane_exchange >= 0)
-        xchs.push_back(ctx->lane_exchange != 0);
-    else
-        xchs = {false, true};
-    for (uint32_t t : tiles)
-        for (bool x : xchs)
-            for (int f = 0; f < 4; ++f) cands.push_back(SortPlan{t, (f & 1) != 0, (f & 2) != 0, x});
-    auto time_plan = [&](const SortPlan &p, int reps, double *t) {
+    auto time_plan = [&](const SortPlan &p, int64_t steps, int reps, double *t) {
         return time_median(
             s, reps,
             [&]() -> meld_status {
@@ -719,55 +707,84 @@ meld_status auto_sort_plan(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, siz
                     e = hipMemcpyAsync(tv, payload, n * 4, hipMemcpyDeviceToDevice, s);
                 return e == hipSuccess ? MELD_OK : hip_fail(e, "tuning copy");
             },
-            [&]() { return sort_impl(ctx, tk, tv, n, p, -1, s); }, t);
+            [&]() { return sort_impl(ctx, tk, tv, n, p, steps, s); }, t);
     };
-    // Round 1: every candidate, a few runs each.
+    // The candidates within the tie window of the fastest, timed again with
+    // more runs, interleaved; returns the index of the fastest (or, within
+    // `tie`, the one the probe's rule prefers) and updates ms.
+    auto final_round = [&](const std::vector<SortPlan> &c, std::vector<double> &ms, int64_t steps,
+                           double mixed_lo, double mixed_hi, double tie, int *pick) {
+        const double best_ms = *std::min_element(ms.begin(), ms.end());
+        std::vector<int> fin;
+        for (int i = 0; i < (int)c.size(); ++i)
+            if (ms[i] <= best_ms * (1.0 + ctx->tie)) fin.push_back(i);
+        if (fin.size() > 1) {
+            const int reps2 = n >= (1u << 24) ? 5 : 9;
+            std::vector<std::vector<double>> runs(fin.size());
+            for (int r = 0; r < reps2; ++r)
+                for (size_t f = 0; f < fin.size(); ++f) {
+                    double t = 0;
+                    meld_status st2 = time_plan(c[fin[f]], steps, 1, &t);
+                    if (st2 != MELD_OK) return st2;
+                    runs[f].push_back(t);
+                }
+            for (size_t f = 0; f < fin.size(); ++f) {
+                std::sort(runs[f].begin(), runs[f].end());
+                ms[fin[f]] = runs[f][runs[f].size() / 2];
+            }
+        }
+        std::vector<double> m2;
+        std::vector<int> lo2, hi2;
+        for (int i : fin) {
+            m2.push_back(ms[i]);
+            lo2.push_back(c[i].lo);
+            hi2.push_back(c[i].hi);
+        }
+        *pick = fin[meld::choose((int)fin.size(), m2.data(), lo2.data(), hi2.data(), mixed_lo,
+                                 mixed_hi, ctx->theta, tie)];
+        return MELD_OK;
+    };
     const int reps = n >= (1u << 24) ? 2 : 3;
-    for (const SortPlan &p : cands) {
-        double t = 0;
-        st = time_plan(p, reps, &t);
+    // Step 1, the tile: whole sorts with the default forms (the forms change
+    // only the local-sort launch, a few percent of a large sort).
+    std::vector<SortPlan> tplans;
+    std::vector<double> tms;
+    for (uint32_t t : tiles) {
+        tplans.push_back(SortPlan{t, true, true, plan_xch(ctx)});
+        double ms1 = 0;
+        st = time_plan(tplans.back(), -1, reps, &ms1);
         if (st != MELD_OK) return st;
-        ms.push_back(t);
-        flo.push_back(p.lo);
-        fhi.push_back(p.hi);
+        tms.push_back(ms1);
     }
+    int tpick = 0;
+    st = final_round(tplans, tms, -1, 0.0, 0.0, 0.0, &tpick);
+    if (st != MELD_OK) return st;
+    const uint32_t log_t = tplans[tpick].log_t;
+    const uint32_t local_log = std::max<uint32_t>(std::min(log_t, log_n), 1);
+    const int64_t local_steps = (int64_t)local_log * (local_log + 1) / 2;
+    // Step 2, the forms: the local-sort launch alone (the network's first
+    // local_steps steps), every form per stage on each low-phase path.
+    std::vector<bool> xchs;
+    if (ctx->lane_exchange >= 0)
+        xchs.push_back(ctx->lane_exchange != 0);
+    else
+        xchs = {false, true};
+    std::vector<SortPlan> cands;
+    std::vector<double> ms;
+    for (bool x : xchs)
+        for (int f = 0; f < 4; ++f) {
+            cands.push_back(SortPlan{log_t, (f & 1) != 0, (f & 2) != 0, x});
+            double t = 0;
+            st = time_plan(cands.back(), local_steps, reps, &t);
+            if (st != MELD_OK) return st;
+            ms.push_back(t);
+        }
     double mixed_lo = 0, mixed_hi = 0;
     st = probe_network(ctx, std::min(log_n, max_t), s, &mixed_lo, &mixed_hi);
     if (st != MELD_OK) return st;
-    // Round 2: the candidates within the tie window of the fastest, timed
-    // again with more runs, interleaved; the probe then breaks ties only
-    // within a window of kFinalTie, the run-to-run spread of these medians
-    // (the first round's few runs cannot separate plans a percent apart).
-    const double best_ms = *std::min_element(ms.begin(), ms.end());
-    std::vector<int> finalists;
-    for (int i = 0; i < (int)cands.size(); ++i)
-        if (ms[i] <= best_ms * (1.0 + ctx->tie)) finalists.push_back(i);
     int pick = 0;
-    if (finalists.size() > 1) {
-        const int reps2 = n >= (1u << 24) ? 5 : 9;
-        std::vector<std::vector<double>> runs(finalists.size());
-        for (int r = 0; r < reps2; ++r)
-            for (size_t f = 0; f < finalists.size(); ++f) {
-                double t = 0;
-                st = time_plan(cands[finalists[f]], 1, &t);
-                if (st != MELD_OK) return st;
-                runs[f].push_back(t);
-            }
-        std::vector<double> ms2;
-        std::vector<int> flo2, fhi2;
-        for (size_t f = 0; f < finalists.size(); ++f) {
-            std::sort(runs[f].begin(), runs[f].end());
-            ms2.push_back(runs[f][runs[f].size() / 2]);
-            flo2.push_back(flo[finalists[f]]);
-            fhi2.push_back(fhi[finalists[f]]);
-            ms[finalists[f]] = ms2.back();
-        }
-        const int p2 = meld::choose((int)finalists.size(), ms2.data(), flo2.data(), fhi2.data(),
-                                    mixed_lo, mixed_hi, ctx->theta, kFinalTie);
-        pick = finalists[p2];
-    } else {
-        pick = finalists[0];
-    }
+    st = final_round(cands, ms, local_steps, mixed_lo, mixed_hi, kFinalTie, &pick);
+    if (st != MELD_OK) return st;
     *out = cands[pick];
     meld::TuneEntry e;
     e.op = "sort";
@@ -777,10 +794,10 @@ meld_status auto_sort_plan(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, siz
     e.log_t = (int)out->log_t;
     e.xch = out->xch ? 1 : 0;
     e.form = out->lo ? 1 : 0;
-    e.ms = ms[pick];
+    e.ms = tms[tpick];
     e.mixed_lo = mixed_lo;
     e.mixed_hi = mixed_hi;
-    e.trials = (int)cands.size();
+    e.trials = (int)(tplans.size() + cands.size());
     ctx->tuner.put(e);
     return MELD_OK;
 }
