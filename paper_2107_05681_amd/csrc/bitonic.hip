@@ -66,69 +66,91 @@ struct ElemOf<true> {
 enum IoMode { kPlain = kIoPlain, kPlainVec = kIoPlainVec, kTail = kIoTail, kSentinel = kIoSentinel };
 
 // Global accesses of the streaming passes, the merge tails and the tile
-// sorts: every element is read once and written once per launch and the
-// array (2 x 1 GiB for 2^28 pairs) is far larger than the caches, so loads
-// and stores carry the nontemporal hint. On the 2^28-pair sort: register
-// passes 775 -> 737 us, merge tails 792 -> 767 us, gathered passes 862 ->
-// 836 us per launch (whole sort 33.5 -> 32.4 ms); the hint on loads or on
-// stores alone gained 1 % or nothing.
+// sorts of a large array (SortArray::nt, set when the array is far larger
+// than the caches): every element is read once and written once per launch,
+// so loads and stores carry the nontemporal hint. On the 2^28-pair sort:
+// register passes 775 -> 737 us, merge tails 792 -> 767 us, gathered passes
+// 862 -> 836 us per launch (whole sort 33.5 -> 32.4 ms); the hint on loads or
+// on stores alone gained 1 % or nothing. A small array stays in L2 between
+// launches, which the hint would give up (the 2^16-key sort: 47 -> 50 us).
+// The choice is made once per load or store sequence (a template argument
+// below it), not per access.
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ uint32_t ld4(const uint32_t *p) { return __builtin_nontemporal_load(p); }
-__device__ __forceinline__ void st4(uint32_t *p, uint32_t v) { __builtin_nontemporal_store(v, p); }
-__device__ __forceinline__ uint4 ld16(const uint32_t *p) {
-    const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
-    return make_uint4(v.x, v.y, v.z, v.w);
+template <bool NT>
+__device__ __forceinline__ uint32_t ld4(const uint32_t *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    return *p;
 }
+template <bool NT>
+__device__ __forceinline__ void st4(uint32_t *p, uint32_t v) {
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+template <bool NT>
+__device__ __forceinline__ uint4 ld16(const uint32_t *p) {
+    if constexpr (NT) {
+        const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+        return make_uint4(v.x, v.y, v.z, v.w);
+    }
+    return *reinterpret_cast<const uint4 *>(p);
+}
+template <bool NT>
 __device__ __forceinline__ void st16(uint32_t *p, uint4 v) {
-    const u32x4 w = {v.x, v.y, v.z, v.w};
-    __builtin_nontemporal_store(w, reinterpret_cast<u32x4 *>(p));
+    if constexpr (NT) {
+        const u32x4 w = {v.x, v.y, v.z, v.w};
+        __builtin_nontemporal_store(w, reinterpret_cast<u32x4 *>(p));
+    } else {
+        *reinterpret_cast<uint4 *>(p) = v;
+    }
 }
 
-template <int MODE>
+template <int MODE, bool NT = false>
 __device__ __forceinline__ uint32_t ld_u32(const uint32_t *main, const uint32_t *tail, uint32_t n,
                                            uint32_t p) {
     if constexpr (MODE == kTail) {
         const uint32_t *src = p < n ? main + p : tail + (p - n);
-        return ld4(src);
+        return ld4<NT>(src);
     } else if constexpr (MODE == kSentinel) {
         return p < n ? main[p] : kPadValue;
     } else {
-        return ld4(main + p);
+        return ld4<NT>(main + p);
     }
 }
 
-template <int MODE>
+template <int MODE, bool NT = false>
 __device__ __forceinline__ void st_u32(uint32_t *main, uint32_t *tail, uint32_t n, uint32_t p,
                                        uint32_t v) {
     if constexpr (MODE == kTail) {
         uint32_t *dst = p < n ? main + p : tail + (p - n);
-        st4(dst, v);
+        st4<NT>(dst, v);
     } else if constexpr (MODE == kSentinel) {
         if (p < n) main[p] = v;
     } else {
-        st4(main + p, v);
+        st4<NT>(main + p, v);
     }
 }
 
-template <bool PAIRS, int MODE>
+template <bool PAIRS, int MODE, bool NT = false>
 __device__ __forceinline__ typename ElemOf<PAIRS>::type load_elem(const SortArray &a, uint32_t p) {
-    const uint32_t k = ld_u32<MODE>(a.keys, a.tk, a.n, p);
+    const uint32_t k = ld_u32<MODE, NT>(a.keys, a.tk, a.n, p);
     if constexpr (PAIRS) {
-        const uint32_t v = ld_u32<MODE>(a.vals, a.tv, a.n, p);
+        const uint32_t v = ld_u32<MODE, NT>(a.vals, a.tv, a.n, p);
         return ((uint64_t)k << 32) | v;
     } else {
         return k;
     }
 }
 
-template <bool PAIRS, int MODE>
+template <bool PAIRS, int MODE, bool NT = false>
 __device__ __forceinline__ void store_elem(const SortArray &a, uint32_t p,
                                            typename ElemOf<PAIRS>::type e) {
     if constexpr (PAIRS) {
-        st_u32<MODE>(a.keys, a.tk, a.n, p, (uint32_t)(e >> 32));
-        st_u32<MODE>(a.vals, a.tv, a.n, p, (uint32_t)e);
+        st_u32<MODE, NT>(a.keys, a.tk, a.n, p, (uint32_t)(e >> 32));
+        st_u32<MODE, NT>(a.vals, a.tv, a.n, p, (uint32_t)e);
     } else {
-        st_u32<MODE>(a.keys, a.tk, a.n, p, e);
+        st_u32<MODE, NT>(a.keys, a.tk, a.n, p, e);
     }
 }
 
@@ -444,17 +466,18 @@ __device__ __forceinline__ void window_load(E (&e)[kMergeE], const E *p, uint32_
 // group is contiguous in the array). Modes: vector (16-byte groups),
 // sentinel (positions >= n read as the pad value), plain or tail (positions
 // >= n from the tail workspace; a tile wholly below n loads directly).
-template <bool PAIRS, int L, int C>
-__device__ __forceinline__ void regs_load(const SortArray &a, const TileMap<L, C> &map, uint32_t t,
-                                          int mode, typename ElemOf<PAIRS>::type (&e)[kMergeE]) {
+template <bool PAIRS, int L, int C, bool NT>
+__device__ __forceinline__ void regs_load_t(const SortArray &a, const TileMap<L, C> &map,
+                                            uint32_t t, int mode,
+                                            typename ElemOf<PAIRS>::type (&e)[kMergeE]) {
     using E = typename ElemOf<PAIRS>::type;
     if (mode == kPlainVec) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const uint32_t p = map(merge_index<L, -1>(t, 4 * c));
-            const uint4 k = ld16(a.keys + p);
+            const uint4 k = ld16<NT>(a.keys + p);
             if constexpr (PAIRS) {
-                const uint4 v = ld16(a.vals + p);
+                const uint4 v = ld16<NT>(a.vals + p);
                 e[4 * c + 0] = ((E)k.x << 32) | v.x;
                 e[4 * c + 1] = ((E)k.y << 32) | v.y;
                 e[4 * c + 2] = ((E)k.z << 32) | v.z;
@@ -475,7 +498,55 @@ __device__ __forceinline__ void regs_load(const SortArray &a, const TileMap<L, C
 #pragma unroll
         for (int r = 0; r < kMergeE; ++r) {
             const uint32_t p = map(merge_index<L, -1>(t, r));
-            e[r] = below_n ? load_elem<PAIRS, kPlain>(a, p) : load_elem<PAIRS, kTail>(a, p);
+            e[r] = below_n ? load_elem<PAIRS, kPlain, NT>(a, p) : load_elem<PAIRS, kTail, NT>(a, p);
+        }
+    }
+}
+
+template <bool PAIRS, int L, int C>
+__device__ __forceinline__ void regs_load(const SortArray &a, const TileMap<L, C> &map, uint32_t t,
+                                          int mode, typename ElemOf<PAIRS>::type (&e)[kMergeE]) {
+    if (a.nt != 0)
+        regs_load_t<PAIRS, L, C, true>(a, map, t, mode, e);
+    else
+        regs_load_t<PAIRS, L, C, false>(a, map, t, mode, e);
+}
+
+// The global stores of a tile held in layout V (vector modes) or window L-4.
+template <bool PAIRS, int L, int C, bool NT>
+__device__ __forceinline__ void regs_store_t(const SortArray &a, const TileMap<L, C> &map,
+                                             uint32_t t, int mode,
+                                             typename ElemOf<PAIRS>::type (&e)[kMergeE]) {
+    if (mode == kPlainVec) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const uint32_t p = map(merge_index<L, -1>(t, 4 * c));
+            if constexpr (PAIRS) {
+                st16<NT>(a.keys + p, make_uint4((uint32_t)(e[4 * c] >> 32),
+                                                (uint32_t)(e[4 * c + 1] >> 32),
+                                                (uint32_t)(e[4 * c + 2] >> 32),
+                                                (uint32_t)(e[4 * c + 3] >> 32)));
+                st16<NT>(a.vals + p, make_uint4((uint32_t)e[4 * c], (uint32_t)e[4 * c + 1],
+                                                (uint32_t)e[4 * c + 2], (uint32_t)e[4 * c + 3]));
+            } else {
+                st16<NT>(a.keys + p, make_uint4(e[4 * c], e[4 * c + 1], e[4 * c + 2], e[4 * c + 3]));
+            }
+        }
+        return;
+    }
+    if (mode == kSentinel) {
+#pragma unroll
+        for (int r = 0; r < kMergeE; ++r)
+            store_elem<PAIRS, kSentinel>(a, map(merge_index<L, L - 4>(t, r)), e[r]);
+    } else {
+        const bool below_n = map((1u << L) - 1) < a.n;
+#pragma unroll
+        for (int r = 0; r < kMergeE; ++r) {
+            const uint32_t p = map(merge_index<L, L - 4>(t, r));
+            if (below_n)
+                store_elem<PAIRS, kPlain, NT>(a, p, e[r]);
+            else
+                store_elem<PAIRS, kTail, NT>(a, p, e[r]);
         }
     }
 }
@@ -488,37 +559,13 @@ __device__ __forceinline__ void regs_store(const SortArray &a, typename ElemOf<P
                                            typename ElemOf<PAIRS>::type (&e)[kMergeE]) {
     if (mode == kPlainVec) {
         if constexpr (FROM != -1) merge_transpose<L, FROM, -1>(e, s, t);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const uint32_t p = map(merge_index<L, -1>(t, 4 * c));
-            if constexpr (PAIRS) {
-                st16(a.keys + p,
-                     make_uint4((uint32_t)(e[4 * c] >> 32), (uint32_t)(e[4 * c + 1] >> 32),
-                                (uint32_t)(e[4 * c + 2] >> 32), (uint32_t)(e[4 * c + 3] >> 32)));
-                st16(a.vals + p, make_uint4((uint32_t)e[4 * c], (uint32_t)e[4 * c + 1],
-                                            (uint32_t)e[4 * c + 2], (uint32_t)e[4 * c + 3]));
-            } else {
-                st16(a.keys + p, make_uint4(e[4 * c], e[4 * c + 1], e[4 * c + 2], e[4 * c + 3]));
-            }
-        }
-        return;
-    }
-    merge_transpose<L, FROM, L - 4>(e, s, t);
-    if (mode == kSentinel) {
-#pragma unroll
-        for (int r = 0; r < kMergeE; ++r)
-            store_elem<PAIRS, kSentinel>(a, map(merge_index<L, L - 4>(t, r)), e[r]);
     } else {
-        const bool below_n = map((1u << L) - 1) < a.n;
-#pragma unroll
-        for (int r = 0; r < kMergeE; ++r) {
-            const uint32_t p = map(merge_index<L, L - 4>(t, r));
-            if (below_n)
-                store_elem<PAIRS, kPlain>(a, p, e[r]);
-            else
-                store_elem<PAIRS, kTail>(a, p, e[r]);
-        }
+        merge_transpose<L, FROM, L - 4>(e, s, t);
     }
+    if (a.nt != 0)
+        regs_store_t<PAIRS, L, C, true>(a, map, t, mode, e);
+    else
+        regs_store_t<PAIRS, L, C, false>(a, map, t, mode, e);
 }
 
 // One pass of S steps (on element bits L-1 .. L-S of a tile of 2^L) of
@@ -840,7 +887,7 @@ hipError_t launch_sort_regs_p(const SortArray &a, uint32_t log_t, uint32_t n_til
 
 constexpr int kGlobalThreads = 256;
 
-template <bool PAIRS, int R, int MODE>
+template <bool PAIRS, int R, int MODE, bool NT>
 __global__ __launch_bounds__(kGlobalThreads) void bitonic_global_kernel(SortArray a,
                                                                       uint32_t n_threads,
                                                                       uint32_t m, uint32_t b_lo,
@@ -854,7 +901,7 @@ __global__ __launch_bounds__(kGlobalThreads) void bitonic_global_kernel(SortArra
     E e[1 << R];
 #pragma unroll
     for (int q = 0; q < (1 << R); ++q)
-        e[q] = load_elem<PAIRS, MODE>(a, base + ((uint32_t)q << b_lo));
+        e[q] = load_elem<PAIRS, MODE, NT>(a, base + ((uint32_t)q << b_lo));
 #pragma unroll
     for (int s = R - 1; s >= 0; --s) {
         if (R - 1 - s < nsteps) {
@@ -865,7 +912,7 @@ __global__ __launch_bounds__(kGlobalThreads) void bitonic_global_kernel(SortArra
     }
 #pragma unroll
     for (int q = 0; q < (1 << R); ++q)
-        store_elem<PAIRS, MODE>(a, base + ((uint32_t)q << b_lo), e[q]);
+        store_elem<PAIRS, MODE, NT>(a, base + ((uint32_t)q << b_lo), e[q]);
 }
 
 __global__ void fill_u32_kernel(uint32_t *p, uint32_t value, size_t count) {
@@ -949,9 +996,13 @@ hipError_t launch_global_r(const SortArray &a, uint32_t log_n, uint32_t m, uint3
                            int32_t step_limit, hipStream_t stream) {
     const uint32_t n_threads = 1u << (log_n - R);
     const uint32_t blocks = (n_threads + kGlobalThreads - 1) / kGlobalThreads;
-    hipLaunchKernelGGL((bitonic_global_kernel<PAIRS, R, MODE>), dim3(blocks),
-                       dim3(kGlobalThreads), 0, stream, a, n_threads, m, b_lo,
-                       step_limit < 0 ? R : step_limit);
+    const int32_t nsteps = step_limit < 0 ? R : step_limit;
+    if (a.nt != 0)
+        hipLaunchKernelGGL((bitonic_global_kernel<PAIRS, R, MODE, true>), dim3(blocks),
+                           dim3(kGlobalThreads), 0, stream, a, n_threads, m, b_lo, nsteps);
+    else
+        hipLaunchKernelGGL((bitonic_global_kernel<PAIRS, R, MODE, false>), dim3(blocks),
+                           dim3(kGlobalThreads), 0, stream, a, n_threads, m, b_lo, nsteps);
     return hipGetLastError();
 }
 

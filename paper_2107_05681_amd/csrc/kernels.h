@@ -55,6 +55,7 @@ struct SortArray {
     uint32_t *tk;    // tail workspace for keys (may be NULL)
     uint32_t *tv;    // tail workspace for vals (may be NULL)
     uint32_t n;
+    uint32_t nt;     // nonzero: global accesses carry the nontemporal hint
 };
 
 // Runs, on every tile of 2^log_t elements, the network steps of phases

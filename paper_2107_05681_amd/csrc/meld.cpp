@@ -67,6 +67,9 @@ struct meld_ctx {
 
 namespace {
 constexpr size_t kProbeWords = 64;
+// Sorts whose array (padded, keys and payloads) exceeds this many bytes use
+// nontemporal global accesses.
+constexpr size_t kNontemporalBytes = (size_t)256 << 20;
 // Tie window of the sort tuner's second round (relative): the spread of the
 // medians of five or nine timed local-sort launches on one MI355X.
 constexpr double kFinalTie = 0.005;
@@ -519,7 +522,10 @@ meld_status sort_impl(meld_ctx *ctx, uint32_t *keys, uint32_t *payload, size_t n
     const uint32_t log_n = log2_ceil(n);
     const size_t big_n = (size_t)1 << log_n;
 
-    SortArray a{keys, payload, nullptr, nullptr, (uint32_t)n};
+    // Nontemporal accesses once the array outgrows the caches (L2 and the
+    // 256 MB Infinity Cache); below, the array stays cached between launches.
+    const bool nt = big_n * (pairs ? 8 : 4) > kNontemporalBytes;
+    SortArray a{keys, payload, nullptr, nullptr, (uint32_t)n, nt ? 1u : 0u};
     int64_t left = step_limit;  // < 0: unlimited
     auto take = [&left](uint64_t steps) -> int32_t {
         if (left < 0) return -1;
