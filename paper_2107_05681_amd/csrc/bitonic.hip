@@ -887,6 +887,38 @@ hipError_t launch_sort_regs_p(const SortArray &a, uint32_t log_t, uint32_t n_til
 
 constexpr int kGlobalThreads = 256;
 
+// Start of row q (q << b_lo elements into p), computed on the scalar unit
+// and kept there: the empty asm hides it from reassociation with the lane's
+// offset, so each access is a scalar base plus one 32-bit lane offset. The
+// stores compute their row starts again (FRESH: a volatile asm, which the
+// compiler cannot merge with the loads' one), rather than keeping 2^R of
+// them live across the compare-exchange steps.
+// The row start is a global-memory pointer (address space 1): through a
+// generic pointer the compiler would emit flat instructions.
+typedef __attribute__((address_space(1))) uint32_t global_u32;
+template <bool FRESH = false>
+__device__ __forceinline__ global_u32 *row_ptr(uint32_t *p, int q, uint32_t b_lo) {
+    uint32_t *r = p + ((size_t)q << b_lo);
+    if constexpr (FRESH)
+        asm volatile("" : "+s"(r));
+    else
+        asm("" : "+s"(r));
+    return (global_u32 *)r;
+}
+
+template <bool NT>
+__device__ __forceinline__ uint32_t ld4g(const global_u32 *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    return *p;
+}
+template <bool NT>
+__device__ __forceinline__ void st4g(global_u32 *p, uint32_t v) {
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
 template <bool PAIRS, int R, int MODE, bool NT>
 __global__ __launch_bounds__(kGlobalThreads) void bitonic_global_kernel(SortArray a,
                                                                       uint32_t n_threads,
@@ -899,9 +931,24 @@ __global__ __launch_bounds__(kGlobalThreads) void bitonic_global_kernel(SortArra
     const uint32_t base = ((t >> b_lo) << (b_lo + R)) | low;
     const bool up = ((base >> m) & 1u) == 0;
     E e[1 << R];
+    if constexpr (MODE == kPlain) {
+        // Row q of every lane starts at the uniform address keys + (q << b_lo)
+        // (a scalar base) and the lane adds its own 32-bit offset: one offset
+        // register serves all 2^R rows, where per-element 64-bit addresses
+        // kept live from the loads to the stores took 256 VGPRs at R = 6.
 #pragma unroll
-    for (int q = 0; q < (1 << R); ++q)
-        e[q] = load_elem<PAIRS, MODE, NT>(a, base + ((uint32_t)q << b_lo));
+        for (int q = 0; q < (1 << R); ++q) {
+            const uint32_t k = ld4g<NT>(row_ptr(a.keys, q, b_lo) + base);
+            if constexpr (PAIRS)
+                e[q] = ((E)k << 32) | ld4g<NT>(row_ptr(a.vals, q, b_lo) + base);
+            else
+                e[q] = k;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < (1 << R); ++q)
+            e[q] = load_elem<PAIRS, MODE, NT>(a, base + ((uint32_t)q << b_lo));
+    }
 #pragma unroll
     for (int s = R - 1; s >= 0; --s) {
         if (R - 1 - s < nsteps) {
@@ -910,9 +957,21 @@ __global__ __launch_bounds__(kGlobalThreads) void bitonic_global_kernel(SortArra
                 if ((q & (1 << s)) == 0) cex_regs(e[q], e[q | (1 << s)], up);
         }
     }
+    if constexpr (MODE == kPlain) {
 #pragma unroll
-    for (int q = 0; q < (1 << R); ++q)
-        store_elem<PAIRS, MODE, NT>(a, base + ((uint32_t)q << b_lo), e[q]);
+        for (int q = 0; q < (1 << R); ++q) {
+            if constexpr (PAIRS) {
+                st4g<NT>(row_ptr<true>(a.keys, q, b_lo) + base, (uint32_t)(e[q] >> 32));
+                st4g<NT>(row_ptr<true>(a.vals, q, b_lo) + base, (uint32_t)e[q]);
+            } else {
+                st4g<NT>(row_ptr<true>(a.keys, q, b_lo) + base, e[q]);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < (1 << R); ++q)
+            store_elem<PAIRS, MODE, NT>(a, base + ((uint32_t)q << b_lo), e[q]);
+    }
 }
 
 __global__ void fill_u32_kernel(uint32_t *p, uint32_t value, size_t count) {
