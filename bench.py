@@ -789,16 +789,20 @@ def _bench_sort16(torch, np, meld, workloads, dev, args):
 
 
 def _profile_sorts(torch, np, meld, workloads, dev):
-    """One launch sequence per form: 2^16-key sort, then the 4096-segment sort."""
+    """One launch sequence per form: 2^16-key sort, then the 4096-segment sort, on the
+    lane-exchange path; then the same on the LDS comparator network."""
     keys = torch.from_numpy(workloads.keys_u32(SEED, 1 << 16).view(np.int32)).to(dev)
-    for v in ("divergent", "melded"):
-        meld.sort(keys.clone(), variant=v)
     off = workloads.segment_offsets(SEED, 4096)
     od = torch.from_numpy(off.view(np.int32)).to(dev)
     seg = torch.from_numpy(workloads.keys_u32(SEED, int(off[-1])).view(np.int32)).to(dev)
     meld.set_option(0, meld.OPT_USE_GRAPHS, 0)
-    for lo, hi in (("divergent", "divergent"), ("melded", "melded")):
-        meld.segmented_sort(seg.clone(), od, low=lo, high=hi)
+    for x in (PATHS["lane_exchange"], PATHS["lds"]):
+        _set_path(meld, x)
+        for v in ("divergent", "melded"):
+            meld.sort(keys.clone(), variant=v)
+        for lo, hi in (("divergent", "divergent"), ("melded", "melded")):
+            meld.segmented_sort(seg.clone(), od, low=lo, high=hi)
+    _set_path(meld, -1)
     torch.cuda.synchronize()
     print(json.dumps({"profile_run": "sort"}))
 
