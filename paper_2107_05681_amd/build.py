@@ -12,8 +12,10 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libmeld.so")
 
-SOURCES = ["region.hip", "region_variants.hip", "bitonic.hip", "oddeven.hip", "mergesort.hip",
-           "segsort.hip", "probe.hip", "gen.hip", "meld.cpp", "tune.cpp", "serve.cpp"]
+# Longest compiles first (the local tile sorts unroll every phase).
+SOURCES = ["bitonic_local_xch.hip", "bitonic_local_lds.hip", "bitonic.hip", "segsort.hip",
+           "region.hip", "region_variants.hip", "oddeven.hip", "mergesort.hip", "probe.hip",
+           "gen.hip", "meld.cpp", "tune.cpp", "serve.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -1,0 +1,13 @@
+// Local tile sort, low-phase path: phases k <= 64 as Figure 1's LDS comparator network.
+#include "local_sort.h"
+
+namespace meld {
+
+hipError_t launch_bitonic_sort_regs_lds(const SortArray &a, uint32_t log_t, uint32_t n_tiles,
+                                        int32_t step_limit, bool meld_lo, bool meld_hi,
+                                        int io_mode, hipStream_t stream) {
+    return launch_sort_regs_path<false>(a, log_t, n_tiles, step_limit, meld_lo, meld_hi, io_mode,
+                                        stream);
+}
+
+}  // namespace meld

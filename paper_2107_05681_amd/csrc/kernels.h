@@ -81,6 +81,13 @@ hipError_t launch_bitonic_tile(const SortArray &a, uint32_t log_t, uint32_t n_ti
 hipError_t launch_bitonic_sort_regs(const SortArray &a, uint32_t log_t, uint32_t n_tiles,
                                     int32_t step_limit, bool meld_lo, bool meld_hi, bool xch,
                                     int io_mode, hipStream_t stream);
+// The same on one path each (xch true and false), one translation unit each.
+hipError_t launch_bitonic_sort_regs_xch(const SortArray &a, uint32_t log_t, uint32_t n_tiles,
+                                        int32_t step_limit, bool meld_lo, bool meld_hi,
+                                        int io_mode, hipStream_t stream);
+hipError_t launch_bitonic_sort_regs_lds(const SortArray &a, uint32_t log_t, uint32_t n_tiles,
+                                        int32_t step_limit, bool meld_lo, bool meld_hi,
+                                        int io_mode, hipStream_t stream);
 
 // Steps j = 2^b_hi .. 2^b_lo of phase k = 2^m over all N = 2^log_n elements
 // in one pass through LDS: each workgroup gathers 2^(b_hi-b_lo+1) rows of

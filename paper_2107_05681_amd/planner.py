@@ -499,7 +499,7 @@ KERNELS = (
      ("region_variants", "three_way_thirds", "speedup")),
     ("region_variants.hip", r"region_lt_divergent_kernel", r"region_lt_melded_kernel",
      (("true", "false"),), ("region_variants", "per_lane_trips_8_32_p0.5", "speedup")),
-    ("bitonic.hip", r"bitonic_sort_regs_kernelILb0ELi13ELb0ELb0E",
+    ("bitonic_local_lds.hip", r"bitonic_sort_regs_kernelILb0ELi13ELb0ELb0E",
      r"bitonic_sort_regs_kernelILb0ELi13ELb1ELb1E",
      (("ascending batch", "descending batch"), ("ascending regs", "descending regs")),
      ("sort", "keys_2^16", "speedup")),

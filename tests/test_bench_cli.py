@@ -60,19 +60,37 @@ def test_committed_record_names_existing_sources():
     assert rec["traffic_bytes"] > 0 and rec["fetch_factor"] > 0 and rec["write_factor"] > 0
 
 
-def test_sort_roofline_takes_the_kind_with_the_largest_total():
+def test_sort_roofline_takes_the_kernel_with_the_largest_total():
     import numpy as np
-    plan = {"passes": [{"kind": "local"}, {"kind": "regs"}, {"kind": "merge"},
-                       {"kind": "regs"}, {"kind": "merge"}]}
+    plan = {"log_tile": 13,
+            "passes": [{"kind": "local", "steps": 91}, {"kind": "regs", "steps": 1},
+                       {"kind": "merge", "steps": 13}, {"kind": "regs", "steps": 2},
+                       {"kind": "merge", "steps": 13}]}
     n = 1 << 20
     launches = [[1.0, 0.2, 0.5, 0.2, 0.5], [1.2, 0.2, 0.7, 0.2, 0.7]]
     roof, per = bench._sort_roofline(np, plan, launches, n)
     assert per["merge"]["launches_per_sort"] == 2
     assert abs(per["merge"]["avg_launch_us"] - 600.0) < 1e-6
     assert abs(per["merge"]["ms_per_sort"] - 1.2) < 1e-9
-    assert roof["kind"] == "merge"  # 1.2 ms per sort against 1.1 (local) and 0.4 (regs)
+    assert roof["kind"] == "merge"  # 1.2 ms per sort against 1.1 (local) and 0.2 (each regs)
+    assert roof["kernel"].startswith("bitonic_pass_regs_kernel<true, 13, 13, 13>")
+    assert roof["launches_per_sort"] == 2
     assert abs(roof["achieved"] - 16 * n / 600e-6 / 1e9) < 0.1
     assert abs(roof["frac"] - roof["achieved"] / bench.HBM_PEAK_GBS) < 1e-4
+
+
+def test_sort_roofline_counts_each_streaming_pass_kernel_apart():
+    import numpy as np
+    # the register passes together outweigh the merge tail, but each step count
+    # is a kernel of its own; the merge tail is the largest single kernel
+    plan = {"log_tile": 13,
+            "passes": [{"kind": "regs", "steps": 1}, {"kind": "merge", "steps": 13},
+                       {"kind": "regs", "steps": 2}, {"kind": "merge", "steps": 13},
+                       {"kind": "regs", "steps": 3}]}
+    launches = [[0.5, 0.6, 0.5, 0.6, 0.5]]
+    roof, per = bench._sort_roofline(np, plan, launches, 1 << 20)
+    assert per["regs"]["ms_per_sort"] > per["merge"]["ms_per_sort"]
+    assert roof["kind"] == "merge"
 
 
 def test_cpu_info_reports_model_and_counts():

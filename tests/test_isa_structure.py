@@ -23,14 +23,20 @@ HIPCC = "/opt/rocm/bin/hipcc"
 pytestmark = pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not available")
 
 
-def _asm(src, tmp_path):
+def _asm(src, tmp_path, defines=()):
     out = tmp_path / (os.path.basename(src) + ".s")
     subprocess.check_call(
         [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}", "--offload-device-only", "-S",
-         os.path.join(CSRC, src), "-o", str(out)], stderr=subprocess.DEVNULL)
+         *[f"-D{d}" for d in defines], os.path.join(CSRC, src), "-o", str(out)],
+        stderr=subprocess.DEVNULL)
     return out.read_text()
+
+
+# The local tile sorts are checked at the two tile sizes the tests read
+# (2^11 and 2^13); the same templates as the library's build, fewer of them.
+LOCAL_SIZES = ("MELD_REGS_SIZES(X)=X(11) X(13)",)
 
 
 def _kernel(asm, pattern):
@@ -51,6 +57,16 @@ def _blocks_after(body, marker):
 @pytest.fixture(scope="module")
 def bitonic_asm(tmp_path_factory):
     return _asm("bitonic.hip", tmp_path_factory.mktemp("isa"))
+
+
+@pytest.fixture(scope="module")
+def local_lds_asm(tmp_path_factory):
+    return _asm("bitonic_local_lds.hip", tmp_path_factory.mktemp("isa"), LOCAL_SIZES)
+
+
+@pytest.fixture(scope="module")
+def local_xch_asm(tmp_path_factory):
+    return _asm("bitonic_local_xch.hip", tmp_path_factory.mktemp("isa"), LOCAL_SIZES)
 
 
 @pytest.fixture(scope="module")
@@ -109,12 +125,12 @@ def test_region_melded_inplace_has_no_side_blocks(region_asm):
 
 
 @pytest.mark.parametrize("pairs", [False, True])
-def test_register_phases_divergent_vs_melded(bitonic_asm, pairs):
+def test_register_phases_divergent_vs_melded(local_lds_asm, pairs):
     # Phases k >= 128 of the tile sort run in registers: the divergent form
     # keeps Figure 1's two sides (one per direction), the melded one has none.
     p = "b1" if pairs else "b0"
-    div = _kernel(bitonic_asm, rf"bitonic_sort_regs_kernelIL{p}ELi13ELb0ELb0ELb0E")
-    mel = _kernel(bitonic_asm, rf"bitonic_sort_regs_kernelIL{p}ELi13ELb1ELb1ELb0E")
+    div = _kernel(local_lds_asm, rf"bitonic_sort_regs_kernelIL{p}ELi13ELb0ELb0ELb0E")
+    mel = _kernel(local_lds_asm, rf"bitonic_sort_regs_kernelIL{p}ELi13ELb1ELb1ELb0E")
     width = "u64" if pairs else "u32"
     for side in ("ascending regs\n", "descending regs\n"):
         blocks = _blocks_after(div, side)
@@ -205,16 +221,17 @@ def _lane_sides(body):
 
 
 @pytest.mark.parametrize("pairs", [False, True])
-def test_lane_exchanges_sit_outside_the_divergent_sides(bitonic_asm, pairs):
+def test_lane_exchanges_sit_outside_the_divergent_sides(local_xch_asm, pairs):
     # Tile sort of 2^11 with lane exchanges: three lane steps in phases
-    # k <= 64 and the two of the later phases' last layout. The divergent form
-    # moves each partner value with a DPP move of its own, before the branch;
-    # its sides hold only compares and selects.
+    # k <= 64 and three in the later phases' last layouts (phase 2^9's step on
+    # element bit 4, phase 2^10's on bits 5 and 4), each phase unrolled. The
+    # divergent form moves each partner value with a DPP move of its own,
+    # before the branch; its sides hold only compares and selects.
     p = "b1" if pairs else "b0"
-    div = _kernel_all(bitonic_asm, rf"bitonic_sort_regs_kernelIL{p}ELi11ELb0ELb0ELb1E")
+    div = _kernel_all(local_xch_asm, rf"bitonic_sort_regs_kernelIL{p}ELi11ELb0ELb0ELb1E")
     sides = _lane_sides(div)
-    assert sum(1 for d, _ in sides if d == "ascending") >= 5
-    assert sum(1 for d, _ in sides if d == "descending") >= 5
+    assert sum(1 for d, _ in sides if d == "ascending") >= 6
+    assert sum(1 for d, _ in sides if d == "descending") >= 6
     for _, text in sides:
         assert "_dpp" not in text and "ds_" not in text and "permlane" not in text
         # each side its own compare (keys: min and max) and select
@@ -222,22 +239,22 @@ def test_lane_exchanges_sit_outside_the_divergent_sides(bitonic_asm, pairs):
                 ("v_min_u32" in text and "v_max_u32" in text)), text[:400]
         assert "v_cndmask_b32" in text
     halves = 2 if pairs else 1
-    assert div.count("v_mov_b32_dpp") == 5 * 16 * halves
+    assert div.count("v_mov_b32_dpp") == 6 * 16 * halves
     assert "quad_perm:[1,0,3,2]" in div and "quad_perm:[2,3,0,1]" in div
 
 
 @pytest.mark.parametrize("pairs", [False, True])
-def test_lane_exchanges_melded_compare_select_on_the_full_wave(bitonic_asm, pairs):
+def test_lane_exchanges_melded_compare_select_on_the_full_wave(local_xch_asm, pairs):
     p = "b1" if pairs else "b0"
-    mel = _kernel_all(bitonic_asm, rf"bitonic_sort_regs_kernelIL{p}ELi11ELb1ELb1ELb1E")
+    mel = _kernel_all(local_xch_asm, rf"bitonic_sort_regs_kernelIL{p}ELi11ELb1ELb1ELb1E")
     assert "; side" not in mel
     if pairs:
         # both halves moved, one 64-bit compare, a select per half
-        assert mel.count("v_mov_b32_dpp") == 5 * 16 * 2
+        assert mel.count("v_mov_b32_dpp") == 6 * 16 * 2
         assert re.search(r"v_cmp_(lt|gt)_u64", mel)
     else:
         # the move folds into the min and max that use it
-        assert mel.count("v_min_u32_dpp") == 5 * 16 and mel.count("v_max_u32_dpp") == 5 * 16
+        assert mel.count("v_min_u32_dpp") == 6 * 16 and mel.count("v_max_u32_dpp") == 6 * 16
         assert "v_mov_b32_dpp" not in mel
 
 
