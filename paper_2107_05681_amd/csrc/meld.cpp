@@ -445,6 +445,31 @@ std::vector<uint32_t> split_passes(uint32_t d, uint32_t max_gather) {
     return sizes;
 }
 
+// Pair sorts: launch time of a streaming pass over 2^28 pairs on one MI355X
+// (kernel trace of the tuned sort, microseconds) by its step count: register
+// passes of 1 .. 6 steps, gathered passes of 7 and 8. Only their ratios
+// matter: a phase's global steps are split into the passes of the least total
+// (9 steps as 2 + 7 rather than 5 + 4, 12 as 5 + 7 rather than 6 + 6).
+constexpr double kPairPassUs[9] = {0.0, 640.0, 655.0, 672.0, 687.0, 754.0, 800.0, 752.0, 1024.0};
+
+// Sizes (high bits first) of the streaming passes of d global pair steps; the
+// gathered sizes only where gather_ok.
+std::vector<uint32_t> split_passes_pairs(uint32_t d, bool gather_ok) {
+    const uint32_t max_r = gather_ok ? meld::kMaxGatherStepsPairs : meld::kMaxFusedSteps;
+    std::vector<double> best(d + 1, 1e300);
+    std::vector<uint32_t> first(d + 1, 0);
+    best[0] = 0.0;
+    for (uint32_t x = 1; x <= d; ++x)
+        for (uint32_t r = 1; r <= std::min(x, max_r); ++r)
+            if (best[x - r] + kPairPassUs[r] < best[x]) {
+                best[x] = best[x - r] + kPairPassUs[r];
+                first[x] = r;
+            }
+    std::vector<uint32_t> sizes;
+    for (uint32_t x = d; x > 0; x -= first[x]) sizes.push_back(first[x]);
+    return sizes;
+}
+
 // One launch of a single-array sort.
 enum class PassKind { kTile, kLocal, kRegs, kGather, kMerge };
 struct SortPass {
@@ -483,7 +508,10 @@ std::vector<SortPass> sort_passes(const SortPlan &plan, bool pairs, uint32_t log
         // possible: up to kMaxFusedSteps per pass in registers, more (high
         // bits first) through gathered LDS tiles where their rows fit.
         uint32_t b_hi = m - 1;
-        for (uint32_t r : split_passes(m - log_t, max_gather)) {
+        const std::vector<uint32_t> sizes =
+            pairs ? split_passes_pairs(m - log_t, log_n >= gather_log)
+                  : split_passes(m - log_t, max_gather);
+        for (uint32_t r : sizes) {
             const uint32_t b_lo = b_hi + 1 - r;
             const bool gather_fits = log_n >= gather_log && b_lo + r >= gather_log;
             if (r > meld::kMaxFusedSteps && gather_fits) {
