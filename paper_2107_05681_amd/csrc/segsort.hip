@@ -338,6 +338,48 @@ __device__ __forceinline__ void phase_windows_xch(uint32_t (&e)[kSegE], uint32_t
     seg_reg_steps<MELDED>(e, top < 3 ? top : 3, up, unlimited);
 }
 
+// to_window and phase_windows_xch with every window base known at compile
+// time (CUR: the window e is in; TOP: the highest step bit left), for the
+// sizes that dominate the work: 2^14-key chunks and their merges.
+template <int CUR, int B>
+__device__ __forceinline__ void to_window_c(uint32_t (&e)[kSegE], uint32_t *s, uint32_t t) {
+    if constexpr (CUR != B) {
+        window_store_w<CUR>(e, s + padded(window_tpart(t, CUR)));
+        __syncthreads();
+        window_load_w<B>(e, s + padded(window_tpart(t, B)));
+        __syncthreads();
+    }
+}
+
+template <bool MELDED, int TOP, int CUR>
+__device__ __forceinline__ void phase_windows_xch_c(uint32_t (&e)[kSegE], uint32_t *s, uint32_t t,
+                                                    bool up) {
+    int32_t unlimited = 0x7FFFFFFF;
+    if constexpr (TOP >= 6) {
+        constexpr int B = TOP - 3;
+        to_window_c<CUR, B>(e, s, t);
+        seg_reg_steps<MELDED>(e, 3, up, unlimited);
+        phase_windows_xch_c<MELDED, B - 1, B>(e, s, t, up);
+    } else {
+        to_window_c<CUR, 0>(e, s, t);
+        if constexpr (TOP >= 5) lane_step<1, MELDED, kSegLaneGroup>(e, up, ((t >> 1) & 1u) == 0);
+        if constexpr (TOP >= 4) lane_step<0, MELDED, kSegLaneGroup>(e, up, (t & 1u) == 0);
+        seg_reg_steps<MELDED>(e, TOP < 3 ? TOP : 3, up, unlimited);
+    }
+}
+
+// Phases 2^P .. 2^M of a team sort on the lane-exchange path, each starting
+// and ending in W0.
+template <bool MELDED, int P, int M>
+__device__ __forceinline__ void team_phases_xch_c(uint32_t (&e)[kSegE], uint32_t *s, uint32_t t,
+                                                  uint32_t cbase) {
+    if constexpr (P <= M) {
+        const bool up = (((cbase >> P) | (t >> (P - 4))) & 1u) == 0;
+        phase_windows_xch_c<MELDED, P - 1, 0>(e, s, t, up);
+        team_phases_xch_c<MELDED, P + 1, M>(e, s, t, cbase);
+    }
+}
+
 // A team of 2^(m-4) lanes (lane t) sorts the 2^m positions cbase + i of a
 // segment (8 <= m <= 14): positions below len come from keys[lo + q], the
 // others are padding. s is the team's own LDS region of 17 * 2^(m-4) words.
@@ -368,10 +410,14 @@ __device__ __forceinline__ void team_sort(uint32_t *__restrict__ keys,
         cur = lt;
         to_window(e, s, t, cur, 0);
         xch_network_low<MELD_LO, kSegLaneGroup>(e, t, -1);
+        if (MELD_HI && m == kSegLogChunk) {
+            team_phases_xch_c<MELD_HI, 7, (int)kSegLogChunk>(e, s, t, cbase);
+        } else {
 #pragma unroll 1
-        for (uint32_t p = 7; p <= m; ++p) {
-            const bool up = (((cbase >> p) | (t >> (p - 4))) & 1u) == 0;
-            phase_windows_xch<MELD_HI>(e, s, t, cur, (int)p - 1, up);
+            for (uint32_t p = 7; p <= m; ++p) {
+                const bool up = (((cbase >> p) | (t >> (p - 4))) & 1u) == 0;
+                phase_windows_xch<MELD_HI>(e, s, t, cur, (int)p - 1, up);
+            }
         }
     } else {
 #pragma unroll
@@ -454,10 +500,12 @@ __device__ void chunk_merge(uint32_t *__restrict__ keys, uint32_t *__restrict__ 
 #pragma unroll
     for (int r = 0; r < kSegE; ++r) e[r] = (work + cbase + ((uint32_t)r << lt))[tl];
     uint32_t cur = lt;
-    if constexpr (XCH)
-        phase_windows_xch<true>(e, s, t, cur, (int)kSegLogChunk - 1, up);
-    else
+    if constexpr (XCH) {
+        phase_windows_xch_c<true, (int)kSegLogChunk - 1, (int)lt>(e, s, t, up);
+        cur = 0;
+    } else {
         phase_windows<true>(e, s, t, cur, (int)kSegLogChunk - 1, up);
+    }
     to_window(e, s, t, cur, lt);
     if (last) {
 #pragma unroll
