@@ -806,6 +806,34 @@ def _bench_sort16(torch, np, meld, workloads, dev, args):
     _set_path(meld, -1)
     out["melded_lane_exchange_vs_melded_lds"] = round(
         out["lds"]["melded_us"] / out["lane_exchange"]["melded_us"], 4)
+    # MELD_AUTO (its tile and forms tuned on the first call) and the seeds 1..3
+    meld.sort(k.copy_(kin), None, variant="auto")
+    auto_plan = meld.sort_plan(n, pairs=False, variant="auto", device=0)
+    out["auto"] = {"plan": {key: auto_plan[key] for key in
+                            ("log_tile", "low", "high", "low_path", "hbm_passes")}}
+    for seed in (1, 2, 3):
+        ks = kin if seed == SEED else torch.from_numpy(
+            workloads.keys_u32(seed, n).view(np.int32)).to(dev)
+        t = {v: [] for v in ("divergent", "melded", "auto")}
+        for rep in range(41):
+            for v in t:
+                k.copy_(ks)
+                s = torch.cuda.Event(enable_timing=True)
+                e = torch.cuda.Event(enable_timing=True)
+                s.record()
+                meld.sort(k, None, variant=v)
+                e.record()
+                e.synchronize()
+                if rep > 0:
+                    t[v].append(s.elapsed_time(e))
+        med = {v: float(np.median(x)) for v, x in t.items()}
+        out["auto"][f"seed_{seed}"] = {
+            "divergent_us": round(med["divergent"] * 1e3, 2),
+            "melded_us": round(med["melded"] * 1e3, 2),
+            "auto_us": round(med["auto"] * 1e3, 2),
+            "auto_us_dist": _dist(np, t["auto"]),
+            "speedup": round(med["divergent"] / med["melded"], 4),
+            "auto_Gkeys_s": round(n / (med["auto"] * 1e-3) / 1e9, 3)}
     return out
 
 
