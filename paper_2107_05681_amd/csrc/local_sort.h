@@ -68,31 +68,6 @@ __device__ __forceinline__ void reg_steps(E (&e)[kMergeE], int hi_q, bool up, in
     }
 }
 
-// Moves a tile held in window prev to window B (run-time bases) through LDS.
-template <bool PAIRS, typename E>
-__device__ __forceinline__ void window_move(E (&e)[kMergeE], E *s, uint32_t t, uint32_t prev,
-                                            uint32_t B) {
-    if (B == prev) return;
-    if constexpr (PAIRS) {
-        // 8-byte elements: the per-case copies that the compile-time
-        // windows leave behind cost more than the scalar offsets
-        // (2^28 pairs: local sort 5.73 -> 5.97 ms melded)
-        const uint32_t tp = merge_phys(window_tpart(t, prev));
-        const uint32_t tb = merge_phys(window_tpart(t, B));
-#pragma unroll
-        for (int r = 0; r < kMergeE; ++r) s[tp + merge_phys((uint32_t)r << prev)] = e[r];
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < kMergeE; ++r) e[r] = s[tb + merge_phys((uint32_t)r << B)];
-        __syncthreads();
-    } else {
-        window_store(e, s + merge_phys(window_tpart(t, prev)), prev);
-        __syncthreads();
-        window_load(e, s + merge_phys(window_tpart(t, B)), B);
-        __syncthreads();
-    }
-}
-
 // Phases 2^M .. 2^L of the lane-exchange path with every window base known at
 // compile time, so that each LDS access of a window move has an immediate
 // offset (with run-time bases, every element's offset costs scalar

@@ -302,66 +302,6 @@ __device__ __forceinline__ uint32_t window_tpart(uint32_t t, uint32_t B) {
     return (t & ((1u << B) - 1)) | ((t >> B) << (B + 4));
 }
 
-// The 16 elements of window W at p[merge_phys(r << W)] (p: the lane's part,
-// already through merge_phys). With W fixed at compile time every position is
-// an immediate offset of the LDS instruction (at most merge_phys(15 << 10)
-// elements = 65280 bytes for keys, merge_phys(15 << 9) for pairs); a run-time
-// W costs scalar arithmetic and a vector add per element.
-template <int W, typename E>
-__device__ __forceinline__ void window_store_w(const E (&e)[kMergeE], E *p) {
-#pragma unroll
-    for (int r = 0; r < kMergeE; ++r) p[merge_phys((uint32_t)r << W)] = e[r];
-}
-template <int W, typename E>
-__device__ __forceinline__ void window_load_w(E (&e)[kMergeE], const E *p) {
-#pragma unroll
-    for (int r = 0; r < kMergeE; ++r) e[r] = p[merge_phys((uint32_t)r << W)];
-}
-
-// Run-time window bases are 0 .. 10 (tiles of at most 2^14 elements); each
-// case ends in its own mark so that the compiler keeps the cases apart
-// instead of merging them back into one block with computed offsets.
-#define WINDOW_CASE(W, CALL, TAG) \
-    case W:                       \
-        CALL;                     \
-        asm volatile("; window " TAG " " #W ::: "memory"); \
-        break;
-
-template <typename E>
-__device__ __forceinline__ void window_store(const E (&e)[kMergeE], E *p, uint32_t W) {
-    switch (W) {
-        WINDOW_CASE(0, (window_store_w<0, E>(e, p)), "store")
-        WINDOW_CASE(1, (window_store_w<1, E>(e, p)), "store")
-        WINDOW_CASE(2, (window_store_w<2, E>(e, p)), "store")
-        WINDOW_CASE(3, (window_store_w<3, E>(e, p)), "store")
-        WINDOW_CASE(4, (window_store_w<4, E>(e, p)), "store")
-        WINDOW_CASE(5, (window_store_w<5, E>(e, p)), "store")
-        WINDOW_CASE(6, (window_store_w<6, E>(e, p)), "store")
-        WINDOW_CASE(7, (window_store_w<7, E>(e, p)), "store")
-        WINDOW_CASE(8, (window_store_w<8, E>(e, p)), "store")
-        WINDOW_CASE(9, (window_store_w<9, E>(e, p)), "store")
-        default: window_store_w<10, E>(e, p); break;
-    }
-}
-
-template <typename E>
-__device__ __forceinline__ void window_load(E (&e)[kMergeE], const E *p, uint32_t W) {
-    switch (W) {
-        WINDOW_CASE(0, (window_load_w<0, E>(e, p)), "load")
-        WINDOW_CASE(1, (window_load_w<1, E>(e, p)), "load")
-        WINDOW_CASE(2, (window_load_w<2, E>(e, p)), "load")
-        WINDOW_CASE(3, (window_load_w<3, E>(e, p)), "load")
-        WINDOW_CASE(4, (window_load_w<4, E>(e, p)), "load")
-        WINDOW_CASE(5, (window_load_w<5, E>(e, p)), "load")
-        WINDOW_CASE(6, (window_load_w<6, E>(e, p)), "load")
-        WINDOW_CASE(7, (window_load_w<7, E>(e, p)), "load")
-        WINDOW_CASE(8, (window_load_w<8, E>(e, p)), "load")
-        WINDOW_CASE(9, (window_load_w<9, E>(e, p)), "load")
-        default: window_load_w<10, E>(e, p); break;
-    }
-}
-#undef WINDOW_CASE
-
 // Thread t's 16 elements of a tile in layout V (C >= 2, so each 16-byte
 // group is contiguous in the array). Modes: vector (16-byte groups),
 // sentinel (positions >= n read as the pad value), plain or tail (positions
