@@ -111,6 +111,32 @@ def test_sort_plan_covers_every_step_once(n, pairs):
     assert len(passes) == 1 + sum(1 + -(-(m - t) // mx) for m in range(t + 1, log_n + 1))
 
 
+def test_pair_plan_splits_each_phase_by_pass_cost():
+    # 2^28 pairs, tile 2^13: phases with 9 .. 12 global steps run a register pass
+    # of 2 .. 5 steps and a gathered pass of 7 (cheaper than two register passes
+    # of 5 + 4 .. 6 + 6); 7 and 8 steps are one gathered pass; at most 6 steps one
+    # register pass; the pass count stays the fewest.
+    meld, _ = _lib()
+    d = meld.sort_plan(1 << 28, True)
+    assert d["log_tile"] == 13 and d["hbm_passes"] == 38
+    by_phase = {}
+    for p in d["passes"][1:]:
+        if p["kind"] != "merge":
+            by_phase.setdefault(p["m"], []).append((p["kind"], p["steps"]))
+    for m, parts in by_phase.items():
+        g = m - 13
+        if g <= 6:
+            assert parts == [("regs", g)]
+        elif g <= 8:
+            assert parts == [("gather", g)]
+        elif g <= 13:
+            assert parts == [("regs", g - 7), ("gather", 7)], (m, parts)
+        elif g == 14:
+            assert parts == [("gather", 7), ("gather", 7)]
+        else:
+            assert sorted(parts) == [("gather", 7), ("gather", 8)]
+
+
 def test_sort_plan_edge_cases():
     meld, lib = _lib()
     assert meld.sort_plan(0)["passes"] == [] and meld.sort_plan(1)["hbm_passes"] == 0
