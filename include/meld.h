@@ -469,7 +469,8 @@ typedef struct {
     double arrival_s;         /* scheduled arrival on the server's clock (meld_server_now):
                                  a job submitted ahead waits until then; <= 0, or a time
                                  already past, queues it at once. Latency is measured
-                                 from it (from the submit time when <= 0). */
+                                 from it (from the submit time when <= 0). NaN or
+                                 infinite: MELD_EINVAL. */
 } meld_job;
 
 typedef struct {

@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
@@ -541,6 +542,8 @@ meld_status meld_server_submit(meld_server *srv, const meld_job *job, uint64_t *
     if (job->kind == MELD_JOB_REGION &&
         (job->thr > (1ull << 32) || job->side_true.trips > 65536 || job->side_false.trips > 65536))
         return serve_fail(MELD_EINVAL, "meld_server_submit: bad region parameters");
+    if (!std::isfinite(job->arrival_s))
+        return serve_fail(MELD_EINVAL, "meld_server_submit: arrival_s is not finite");
     const size_t bytes = job_bytes(*job);
     std::lock_guard<std::mutex> lk(srv->mu);
     srv->stats.submitted++;

@@ -52,6 +52,16 @@ def test_oversize_job_is_rejected():
         assert srv.stats()["rejected"] == 1
 
 
+def test_non_finite_arrival_is_rejected():
+    meld, serve = _serve()
+    with serve.Server(budget_bytes=1 << 20, slots=1, simulated_ns_per_item=1) as srv:
+        for bad in (float("inf"), float("nan")):
+            with pytest.raises(meld.MeldError) as e:
+                srv.submit(_sort(100), arrival_s=bad)
+            assert e.value.status == meld.EINVAL
+        assert srv.stats()["pending"] == 0
+
+
 def test_fifo_admission_order():
     meld, serve = _serve()
     trace = [dict(_region(20000, i), arrival_s=0.0) for i in range(30)]
