@@ -430,6 +430,8 @@ hipError_t launch_bitonic_gather(const SortArray &a, uint32_t log_n, uint32_t m,
     const int32_t nsteps = step_limit < 0 ? r : step_limit;
     if (a.vals != nullptr) {
         switch (r) {
+            case 5: return launch_gather_r<true, 5>(a, log_n, m, b_lo, nsteps, io_mode, stream);
+            case 6: return launch_gather_r<true, 6>(a, log_n, m, b_lo, nsteps, io_mode, stream);
             case 7: return launch_gather_r<true, 7>(a, log_n, m, b_lo, nsteps, io_mode, stream);
             case 8: return launch_gather_r<true, 8>(a, log_n, m, b_lo, nsteps, io_mode, stream);
             default: return hipErrorInvalidValue;

@@ -91,12 +91,13 @@ hipError_t launch_bitonic_sort_regs_lds(const SortArray &a, uint32_t log_t, uint
 
 // Steps j = 2^b_hi .. 2^b_lo of phase k = 2^m over all N = 2^log_n elements
 // in one pass through LDS: each workgroup gathers 2^(b_hi-b_lo+1) rows of
-// contiguous elements (b_hi - b_lo + 1 in 7..8 for pairs, 7..9 for keys;
+// contiguous elements (b_hi - b_lo + 1 in 5..8 for pairs, 7..9 for keys;
 // rows of at least 32 elements). io_mode plain, vector or tail.
 hipError_t launch_bitonic_gather(const SortArray &a, uint32_t log_n, uint32_t m, uint32_t b_hi,
                                  uint32_t b_lo, int32_t step_limit, int io_mode,
                                  hipStream_t stream);
 constexpr uint32_t kMaxGatherStepsPairs = 8, kMaxGatherStepsKeys = 9;
+constexpr uint32_t kMinGatherStepsPairs = 5;
 
 // Steps j = 2^(log_t-1) .. 1 of phase k = 2^m > 2^log_t on every tile, in
 // registers with LDS transposes (log_t in 8..14; io_mode plain, vector or

@@ -446,28 +446,42 @@ std::vector<uint32_t> split_passes(uint32_t d, uint32_t max_gather) {
 }
 
 // Pair sorts: launch time of a streaming pass over 2^28 pairs on one MI355X
-// (kernel trace of the tuned sort, microseconds) by its step count: register
-// passes of 1 .. 6 steps, gathered passes of 7 and 8. Only their ratios
-// matter: a phase's global steps are split into the passes of the least total
-// (9 steps as 2 + 7 rather than 5 + 4, 12 as 5 + 7 rather than 6 + 6).
-constexpr double kPairPassUs[9] = {0.0, 640.0, 655.0, 672.0, 687.0, 754.0, 800.0, 752.0, 1024.0};
+// (microseconds, per pass size, the kernel trace of a sort on one box):
+// register passes of 1 .. 6 steps, gathered passes of 5 .. 8. Only their
+// ratios matter: a phase's global steps are split into the passes of the
+// least total (12 steps as two gathered passes of 6, 11 as 5 + 6, a phase of
+// 5 or 6 steps as one gathered pass).
+constexpr double kPairRegsUs[7] = {0.0, 641.0, 693.0, 728.0, 767.0, 789.0, 763.0};
+constexpr double kPairGatherUs[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 745.0, 720.0, 759.0, 852.0};
 
-// Sizes (high bits first) of the streaming passes of d global pair steps; the
-// gathered sizes only where gather_ok.
-std::vector<uint32_t> split_passes_pairs(uint32_t d, bool gather_ok) {
-    const uint32_t max_r = gather_ok ? meld::kMaxGatherStepsPairs : meld::kMaxFusedSteps;
+struct PassSplit {
+    uint32_t r;   // steps of the pass
+    bool gather;  // through a gathered LDS tile (else registers)
+};
+
+// The streaming passes (high bits first) of d global pair steps, of least
+// total time under the tables; gathered passes only where gather_ok.
+std::vector<PassSplit> split_passes_pairs(uint32_t d, bool gather_ok) {
     std::vector<double> best(d + 1, 1e300);
-    std::vector<uint32_t> first(d + 1, 0);
+    std::vector<PassSplit> first(d + 1, PassSplit{0, false});
     best[0] = 0.0;
-    for (uint32_t x = 1; x <= d; ++x)
-        for (uint32_t r = 1; r <= std::min(x, max_r); ++r)
-            if (best[x - r] + kPairPassUs[r] < best[x]) {
-                best[x] = best[x - r] + kPairPassUs[r];
-                first[x] = r;
+    for (uint32_t x = 1; x <= d; ++x) {
+        for (uint32_t r = 1; r <= std::min(x, meld::kMaxFusedSteps); ++r)
+            if (best[x - r] + kPairRegsUs[r] < best[x]) {
+                best[x] = best[x - r] + kPairRegsUs[r];
+                first[x] = PassSplit{r, false};
             }
-    std::vector<uint32_t> sizes;
-    for (uint32_t x = d; x > 0; x -= first[x]) sizes.push_back(first[x]);
-    return sizes;
+        if (!gather_ok) continue;
+        for (uint32_t r = meld::kMinGatherStepsPairs; r <= std::min(x, meld::kMaxGatherStepsPairs);
+             ++r)
+            if (best[x - r] + kPairGatherUs[r] < best[x]) {
+                best[x] = best[x - r] + kPairGatherUs[r];
+                first[x] = PassSplit{r, true};
+            }
+    }
+    std::vector<PassSplit> out;
+    for (uint32_t x = d; x > 0; x -= first[x].r) out.push_back(first[x]);
+    return out;
 }
 
 // One launch of a single-array sort.
@@ -508,13 +522,18 @@ std::vector<SortPass> sort_passes(const SortPlan &plan, bool pairs, uint32_t log
         // possible: up to kMaxFusedSteps per pass in registers, more (high
         // bits first) through gathered LDS tiles where their rows fit.
         uint32_t b_hi = m - 1;
-        const std::vector<uint32_t> sizes =
-            pairs ? split_passes_pairs(m - log_t, log_n >= gather_log)
-                  : split_passes(m - log_t, max_gather);
-        for (uint32_t r : sizes) {
+        std::vector<PassSplit> sizes;
+        if (pairs) {
+            sizes = split_passes_pairs(m - log_t, log_n >= gather_log);
+        } else {
+            for (uint32_t r : split_passes(m - log_t, max_gather))
+                sizes.push_back(PassSplit{r, r > meld::kMaxFusedSteps});
+        }
+        for (const PassSplit &ps : sizes) {
+            const uint32_t r = ps.r;
             const uint32_t b_lo = b_hi + 1 - r;
             const bool gather_fits = log_n >= gather_log && b_lo + r >= gather_log;
-            if (r > meld::kMaxFusedSteps && gather_fits) {
+            if (ps.gather && gather_fits) {
                 out.push_back({PassKind::kGather, m, b_hi, b_lo, r});
             } else {
                 // register passes only (balanced)

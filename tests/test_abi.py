@@ -103,7 +103,7 @@ def test_sort_plan_covers_every_step_once(n, pairs):
             assert p["steps"] == r and p["b_lo"] >= t
             assert r <= (6 if p["kind"] == "regs" else (8 if pairs else 9))
             if p["kind"] == "gather":
-                assert r >= 7
+                assert r >= (5 if pairs else 7)
             seen += [(m, b) for b in range(p["b_hi"], p["b_lo"] - 1, -1)]
     assert seen == order
     # fewest passes: per phase one merge tail plus ceil((m - t) / max steps)
@@ -112,29 +112,24 @@ def test_sort_plan_covers_every_step_once(n, pairs):
 
 
 def test_pair_plan_splits_each_phase_by_pass_cost():
-    # 2^28 pairs, tile 2^13: phases with 9 .. 12 global steps run a register pass
-    # of 2 .. 5 steps and a gathered pass of 7 (cheaper than two register passes
-    # of 5 + 4 .. 6 + 6); 7 and 8 steps are one gathered pass; at most 6 steps one
-    # register pass; the pass count stays the fewest.
+    # 2^28 pairs, tile 2^13: each phase's g = m - 13 global steps go in the
+    # passes of least modelled time (register passes of up to 6 steps,
+    # gathered passes of 5 .. 8), in the fewest passes: one up to 8 steps, two
+    # beyond.
     meld, _ = _lib()
     d = meld.sort_plan(1 << 28, True)
     assert d["log_tile"] == 13 and d["hbm_passes"] == 38
     by_phase = {}
     for p in d["passes"][1:]:
         if p["kind"] != "merge":
-            by_phase.setdefault(p["m"], []).append((p["kind"], p["steps"]))
-    for m, parts in by_phase.items():
-        g = m - 13
-        if g <= 6:
-            assert parts == [("regs", g)]
-        elif g <= 8:
-            assert parts == [("gather", g)]
-        elif g <= 13:
-            assert parts == [("regs", g - 7), ("gather", 7)], (m, parts)
-        elif g == 14:
-            assert parts == [("gather", 7), ("gather", 7)]
-        else:
-            assert sorted(parts) == [("gather", 7), ("gather", 8)]
+            by_phase.setdefault(p["m"] - 13, []).append((p["kind"], p["steps"]))
+    expect = {1: [("regs", 1)], 2: [("regs", 2)], 3: [("regs", 3)], 4: [("regs", 4)],
+              5: [("gather", 5)], 6: [("gather", 6)], 7: [("gather", 7)], 8: [("gather", 8)],
+              9: [("regs", 3), ("gather", 6)], 10: [("regs", 3), ("gather", 7)],
+              11: [("gather", 5), ("gather", 6)], 12: [("gather", 6), ("gather", 6)],
+              13: [("gather", 6), ("gather", 7)], 14: [("gather", 7), ("gather", 7)],
+              15: [("gather", 7), ("gather", 8)]}
+    assert by_phase == expect
 
 
 def test_sort_plan_edge_cases():

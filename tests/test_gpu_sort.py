@@ -248,17 +248,21 @@ def test_sort_tile_option_rejects_out_of_range(tile_option):
 
 @pytest.mark.parametrize("pairs", [False, True])
 def test_gathered_passes_stage_parity(pairs, tile_option):
-    # Tiles of 2^8 in a 2^15 array: the last phase (k = 2^15) has 7
-    # streaming steps and runs them as one gathered LDS pass, the phase before
-    # has 6 (registers). Every step prefix of these two phases is checked.
+    # Tiles of 2^8 in a 2^15 array: the last three phases (k = 2^13 .. 2^15)
+    # have 5, 6 and 7 streaming steps; keys run 7 as one gathered LDS pass and
+    # 5, 6 in registers, pairs all three as gathered passes. Every step prefix
+    # of these three phases is checked.
     _dev()
     tile_option(8)
     log_n = 15
     n = 1 << log_n
     keys = workloads.keys_u32(400 + pairs, n)
     vals = workloads.iota_u32(n) if pairs else None
+    plan = meld.sort_plan(n, pairs, variant="melded", device=0)
+    gathered = sorted(p["steps"] for p in plan["passes"] if p["kind"] == "gather")
+    assert gathered == ([5, 6, 7] if pairs else [7])
     total = oracle.bitonic_num_steps(n)
-    for s in range(total - 15 - 14, total + 1):
+    for s in range(total - 15 - 14 - 13, total + 1):
         ref = oracle.bitonic_emulate(keys, vals, max_steps=s)
         for v, x in FORMS:
             _path(x)
