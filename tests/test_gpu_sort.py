@@ -280,8 +280,9 @@ def test_gathered_passes_stage_parity(pairs, tile_option):
 @pytest.mark.parametrize("log_t", [8, 9])
 @pytest.mark.parametrize("n", [1 << 17, (1 << 17) - 3, (1 << 18) + 5])
 def test_gathered_passes_full_sort(log_t, n, tile_option):
-    # Small tiles make phases with 7..10 streaming steps, so gathered passes
-    # (and their per-element tail path for ragged n) run.
+    # Small tiles make phases with up to 10 streaming steps, so gathered passes
+    # (pairs from 5 steps, keys from 7; with their per-element tail path for
+    # ragged n) run.
     _dev()
     tile_option(log_t)
     keys = workloads.keys_u32(500 + log_t, n)
