@@ -46,9 +46,19 @@ __device__ __forceinline__ uint32_t lane_xor_move(uint32_t x) {
                                                  false);
 }
 
+// Lane t ^ 4 (lane bit 2): a half-row mirror (lane t ^ 7 within each group
+// of 8), then a quad reversal (t ^ 3): (t ^ 3) ^ 7 = t ^ 4. Two DPP moves.
+__device__ __forceinline__ uint32_t lane_xor4(uint32_t x) {
+    const int y = __builtin_amdgcn_update_dpp((int)x, (int)x, 0x141, 0xF, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_update_dpp(y, y, 0x1B, 0xF, 0xF, false);
+}
+
 template <int B, bool FUSED>
 __device__ __forceinline__ uint32_t lane_xor(uint32_t x) {
-    return FUSED ? lane_xor_fused<B>(x) : lane_xor_move<B>(x);
+    if constexpr (B == 2)
+        return lane_xor4(x);
+    else
+        return FUSED ? lane_xor_fused<B>(x) : lane_xor_move<B>(x);
 }
 
 template <int B, bool FUSED>

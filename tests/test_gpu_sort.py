@@ -219,6 +219,34 @@ def test_stage_parity_small_tiles(log_t, log_n, pairs, tile_option):
                 assert np.array_equal(_to_host(kd), ref), (s, v, x)
 
 
+@pytest.mark.parametrize("log_t", [9, 13])
+@pytest.mark.parametrize("pairs", [False, True])
+def test_merge_tail_stage_parity(log_t, pairs, tile_option):
+    # The merge tails of 2^9 and 2^13 end in layout W0 with three lane steps
+    # (element bits 6, 5 and 4; the one on bit 6 exchanges with lane t ^ 4):
+    # every step prefix of the last phase of a 2^(log_t + 1) array, its
+    # streaming step and the whole merge tail.
+    _dev()
+    tile_option(log_t)
+    n = 1 << (log_t + 1)
+    keys = workloads.keys_u32(600 + log_t, n)
+    vals = workloads.iota_u32(n) if pairs else None
+    total = oracle.bitonic_num_steps(n)
+    for s in range(total - (log_t + 1), total + 1):
+        ref = oracle.bitonic_emulate(keys, vals, max_steps=s)
+        for v, x in FORMS:
+            _path(x)
+            kd = _to_dev(keys)
+            vd = None if vals is None else _to_dev(vals)
+            meld.sort_steps(kd, vd, max_steps=s, variant=v)
+            torch.cuda.synchronize()
+            if pairs:
+                assert np.array_equal(_to_host(kd), ref[0]) and \
+                    np.array_equal(_to_host(vd), ref[1]), (s, v, x)
+            else:
+                assert np.array_equal(_to_host(kd), ref), (s, v, x)
+
+
 @pytest.mark.parametrize("n", [1 << 12, (1 << 15) + 9])
 def test_sort_unaligned_arrays(n):
     # Views one element into their buffers: not 16-byte aligned, so the
