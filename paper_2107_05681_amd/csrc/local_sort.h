@@ -72,17 +72,26 @@ __device__ __forceinline__ void reg_steps(E (&e)[kMergeE], int hi_q, bool up, in
 // compile time, so that each LDS access of a window move has an immediate
 // offset (with run-time bases, every element's offset costs scalar
 // arithmetic and a vector add). Phase M starts and ends in layout W0; TOP is
-// the highest step bit left in the phase and PREV the layout e is in.
+// the highest step bit left in the phase and PREV the layout e is in. Four-bit
+// windows while TOP is at least 7, then W0, where the steps on element bits
+// 6, 5 and 4 are lane exchanges (lane t ^ 4, t ^ 2, t ^ 1): phase 2^7 needs no
+// transpose at all and phase 2^11 one fewer.
 template <int L, bool MELD_HI, int TOP, int PREV, typename E>
 __device__ __forceinline__ void xch_phase_windows(E (&e)[kMergeE], E *s, uint32_t t, bool up,
                                                   int32_t &left) {
-    if constexpr (TOP >= 6) {
+    if constexpr (TOP >= 7) {
         constexpr int B = TOP - 3;
         merge_transpose<L, PREV, B>(e, s, t);
         reg_steps<MELD_HI>(e, 3, up, left);
         xch_phase_windows<L, MELD_HI, B - 1, B>(e, s, t, up, left);
     } else {
         if constexpr (PREV != 0) merge_transpose<L, PREV, 0>(e, s, t);
+        if constexpr (TOP >= 6) {
+            if (left > 0) {
+                lane_step<2, MELD_HI>(e, up, ((t >> 2) & 1u) == 0);
+                --left;
+            }
+        }
         if constexpr (TOP >= 5) {
             if (left > 0) {
                 lane_step<1, MELD_HI>(e, up, ((t >> 1) & 1u) == 0);
@@ -146,8 +155,8 @@ __device__ __forceinline__ void lds_phases(E (&e)[kMergeE], E *s, uint32_t t, ui
 // access at all. Phases 2^1 .. 2^3 then have a direction fixed per register
 // and phases 2^4 .. 2^6 one from a lane bit; form MELD_LO decides how those
 // run. Phases m >= 7 take windows with bases m-4, m-8, ... while their top
-// step bit is at least 6 and end in W0, where the steps on bits 5 and 4 are
-// lane exchanges: a window fewer for m = 9, 10, 13, 14.
+// step bit is at least 7 and end in W0, where the steps on bits 6, 5 and 4
+// are lane exchanges (phase 2^7 runs in W0 alone).
 //
 // In window B element bit m (>= B+4) is thread bit m-4, so the direction is
 // the same for all of a thread's elements and, for m <= 9, differs between

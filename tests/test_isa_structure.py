@@ -220,18 +220,26 @@ def _lane_sides(body):
                       re.S | re.M)
 
 
+# Tile sort of 2^11 with lane exchanges, each phase unrolled: three lane steps
+# in phases k <= 64 (element bits 4, 5, 4), and in the later phases the steps
+# of each phase's last layout W0 on element bits 6 .. 4 that remain: bits 6, 5,
+# 4 for phases 2^7 and 2^11, bit 4 for 2^9, bits 5, 4 for 2^10. Steps on bits
+# 4 and 5 (lane bits 0, 1) take one DPP move per 32-bit value, those on bit 6
+# (lane t ^ 4) two.
+LANE_STEPS_LOW_BITS = 3 + 2 + 1 + 2 + 2    # on lane bits 0 and 1
+LANE_STEPS_BIT2 = 2                           # on lane bit 2
+
+
 @pytest.mark.parametrize("pairs", [False, True])
 def test_lane_exchanges_sit_outside_the_divergent_sides(local_xch_asm, pairs):
-    # Tile sort of 2^11 with lane exchanges: three lane steps in phases
-    # k <= 64 and three in the later phases' last layouts (phase 2^9's step on
-    # element bit 4, phase 2^10's on bits 5 and 4), each phase unrolled. The
-    # divergent form moves each partner value with a DPP move of its own,
+    # The divergent form moves each partner value with DPP moves of its own,
     # before the branch; its sides hold only compares and selects.
     p = "b1" if pairs else "b0"
     div = _kernel_all(local_xch_asm, rf"bitonic_sort_regs_kernelIL{p}ELi11ELb0ELb0ELb1E")
     sides = _lane_sides(div)
-    assert sum(1 for d, _ in sides if d == "ascending") >= 6
-    assert sum(1 for d, _ in sides if d == "descending") >= 6
+    steps = LANE_STEPS_LOW_BITS + LANE_STEPS_BIT2
+    assert sum(1 for d, _ in sides if d == "ascending") >= steps
+    assert sum(1 for d, _ in sides if d == "descending") >= steps
     for _, text in sides:
         assert "_dpp" not in text and "ds_" not in text and "permlane" not in text
         # each side its own compare (keys: min and max) and select
@@ -239,8 +247,9 @@ def test_lane_exchanges_sit_outside_the_divergent_sides(local_xch_asm, pairs):
                 ("v_min_u32" in text and "v_max_u32" in text)), text[:400]
         assert "v_cndmask_b32" in text
     halves = 2 if pairs else 1
-    assert div.count("v_mov_b32_dpp") == 6 * 16 * halves
+    assert div.count("v_mov_b32_dpp") == (LANE_STEPS_LOW_BITS + 2 * LANE_STEPS_BIT2) * 16 * halves
     assert "quad_perm:[1,0,3,2]" in div and "quad_perm:[2,3,0,1]" in div
+    assert "row_half_mirror" in div and "quad_perm:[3,2,1,0]" in div
 
 
 @pytest.mark.parametrize("pairs", [False, True])
@@ -250,12 +259,13 @@ def test_lane_exchanges_melded_compare_select_on_the_full_wave(local_xch_asm, pa
     assert "; side" not in mel
     if pairs:
         # both halves moved, one 64-bit compare, a select per half
-        assert mel.count("v_mov_b32_dpp") == 6 * 16 * 2
+        assert mel.count("v_mov_b32_dpp") == (LANE_STEPS_LOW_BITS + 2 * LANE_STEPS_BIT2) * 16 * 2
         assert re.search(r"v_cmp_(lt|gt)_u64", mel)
     else:
-        # the move folds into the min and max that use it
-        assert mel.count("v_min_u32_dpp") == 6 * 16 and mel.count("v_max_u32_dpp") == 6 * 16
-        assert "v_mov_b32_dpp" not in mel
+        # on lane bits 0 and 1 the move folds into the min and max that use it
+        assert mel.count("v_min_u32_dpp") == LANE_STEPS_LOW_BITS * 16
+        assert mel.count("v_max_u32_dpp") == LANE_STEPS_LOW_BITS * 16
+        assert mel.count("v_mov_b32_dpp") == 2 * LANE_STEPS_BIT2 * 16
 
 
 @pytest.fixture(scope="module")
