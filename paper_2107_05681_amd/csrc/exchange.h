@@ -2,9 +2,10 @@
 //
 // Layout W0 of a tile held 16 elements per lane: register r of lane t holds
 // element 16 t + r, so element bits 0..3 are the register index and element
-// bits 4, 5 are lane bits 0, 1. A step on element bit 4 or 5 pairs every
-// lane with lane t ^ 1 or t ^ 2, inside its quad: a DPP quad permutation
-// brings the partner's value, with no LDS access and no wait.
+// bits 4, 5, 6 are lane bits 0, 1, 2. A step on element bit 4 or 5 pairs
+// every lane with lane t ^ 1 or t ^ 2, inside its quad: a DPP quad
+// permutation brings the partner's value, with no LDS access and no wait. A
+// step on element bit 6 pairs lane t with t ^ 4: two DPP moves.
 //
 // Warp-level exchanges are never part of a melded region (Detailed Design,
 // "Computing Melding Profitability": such intrinsics are not melded), so in
