@@ -493,16 +493,16 @@ def waves_per_simd(vgprs: int, agprs: int = 0) -> int:
 # of their regions and the bench.py figure that times the two forms.
 KERNELS = (
     ("region.hip", r"region_divergent_kernel", r"region_melded_kernel", (("true", "false"),),
-     ("melded_vs_divergent", "0.5", "speedup")),
+     ("region", "melded_vs_divergent", "0.5", "speedup")),
     ("region_variants.hip", r"region3_divergent_kernel", r"region3_melded_kernel",
      (("way 0", "way 1"), ("way 0", "way 2"), ("way 1", "way 2")),
-     ("region_variants", "three_way_thirds", "speedup")),
+     ("region", "region_variants", "three_way_thirds", "speedup")),
     ("region_variants.hip", r"region_lt_divergent_kernel", r"region_lt_melded_kernel",
-     (("true", "false"),), ("region_variants", "per_lane_trips_8_32_p0.5", "speedup")),
+     (("true", "false"),), ("region", "region_variants", "per_lane_trips_8_32_p0.5", "speedup")),
     ("bitonic_local_lds.hip", r"bitonic_sort_regs_kernelILb0ELi13ELb0ELb0E",
      r"bitonic_sort_regs_kernelILb0ELi13ELb1ELb1E",
      (("ascending batch", "descending batch"), ("ascending regs", "descending regs")),
-     ("sort", "keys_2^16", "speedup")),
+     ("sort_keys_2^16", "lds", "local_sort_kernel", "speedup")),
     ("oddeven.hip", r"oddeven_bucket_kernelILi8ELi1024ELb0E", r"oddeven_bucket_kernelILi8ELi1024ELb1E",
      (("lower", "upper"),), ("oddeven_buckets", "buckets_2^13", "speedup")),
     ("mergesort.hip", r"merge_pass_kernelILb0E", r"merge_pass_kernelILb1E", (("take a", "take b"),),
@@ -510,7 +510,7 @@ KERNELS = (
     ("segsort.hip", r"seg_sort_kernelILb0ELb0E", r"seg_sort_kernelILb1ELb1E",
      (("ascending", "descending"), ("ascending batch", "descending batch"),
       ("ascending regs", "descending regs")),
-     ("segmented", None, "speedup_melded")),
+     ("segmented", "seed_1", "speedup_melded_lds_path")),
 )
 
 
