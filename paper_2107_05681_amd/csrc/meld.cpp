@@ -446,38 +446,66 @@ std::vector<uint32_t> split_passes(uint32_t d, uint32_t max_gather) {
 }
 
 // Pair sorts: launch time of a streaming pass over 2^28 pairs on one MI355X
-// (microseconds, per pass size, the kernel trace of a sort on one box):
-// register passes of 1 .. 6 steps, gathered passes of 5 .. 8. Only their
-// ratios matter: a phase's global steps are split into the passes of the
-// least total (12 steps as two gathered passes of 6, 11 as 5 + 6, a phase of
-// 5 or 6 steps as one gathered pass).
-constexpr double kPairRegsUs[7] = {0.0, 641.0, 693.0, 728.0, 767.0, 789.0, 763.0};
-constexpr double kPairGatherUs[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 745.0, 720.0, 759.0, 852.0};
+// (microseconds; median of four sorts in one process), by kind, steps r and
+// lowest array bit b_lo (column b_lo - 13; the rows of the pass lie 2^b_lo
+// elements apart). The time depends on where the pass sits, not only on its
+// size: passes whose steps span array bits 19 .. 24 (rows 2 .. 64 MiB apart)
+// run up to 40 % slower than the same pass on bits from 13 up. Only the
+// ratios matter. Zero: not measured (b_lo + r > 28); the lookup clamps b_lo
+// into the measured columns.
+constexpr uint16_t kPairRegsUs[7][15] = {
+    {0},
+    {643, 632, 647, 651, 639, 647, 660, 679, 675, 718, 702, 691, 654, 658, 668},
+    {651, 657, 673, 673, 674, 670, 711, 737, 776, 859, 750, 665, 677, 704, 0},
+    {670, 677, 696, 698, 696, 696, 733, 785, 868, 900, 723, 700, 723, 0, 0},
+    {689, 708, 724, 724, 733, 753, 784, 848, 845, 778, 727, 734, 0, 0, 0},
+    {720, 736, 744, 733, 768, 850, 858, 848, 782, 764, 753, 0, 0, 0, 0},
+    {725, 735, 746, 759, 799, 890, 960, 801, 797, 778, 0, 0, 0, 0, 0},
+};
+constexpr uint16_t kPairGatherUs[9][15] = {
+    {0}, {0}, {0}, {0}, {0},
+    {657, 667, 698, 698, 749, 829, 871, 827, 726, 704, 716, 0, 0, 0, 0},
+    {656, 704, 716, 771, 882, 762, 781, 788, 777, 794, 0, 0, 0, 0, 0},
+    {759, 814, 798, 796, 822, 802, 748, 762, 769, 0, 0, 0, 0, 0, 0},
+    {857, 890, 897, 914, 913, 888, 932, 1218, 0, 0, 0, 0, 0, 0, 0},
+};
+
+double pair_pass_us(bool gather, uint32_t r, uint32_t b_lo) {
+    const uint32_t hi = 28 - r;  // last measured b_lo for this r
+    const uint32_t col = std::min(std::max(b_lo, 13u), hi) - 13;
+    return gather ? kPairGatherUs[r][col] : kPairRegsUs[r][col];
+}
 
 struct PassSplit {
     uint32_t r;   // steps of the pass
     bool gather;  // through a gathered LDS tile (else registers)
 };
 
-// The streaming passes (high bits first) of d global pair steps, of least
-// total time under the tables; gathered passes only where gather_ok.
-std::vector<PassSplit> split_passes_pairs(uint32_t d, bool gather_ok) {
+// The streaming passes (high bits first) of the d global pair steps on array
+// bits log_t .. log_t + d - 1, of least total time under the tables; the
+// first pass of the x lowest steps (r of them) has b_lo = log_t + x - r.
+// Gathered passes only where gather_ok.
+std::vector<PassSplit> split_passes_pairs(uint32_t d, uint32_t log_t, bool gather_ok) {
     std::vector<double> best(d + 1, 1e300);
     std::vector<PassSplit> first(d + 1, PassSplit{0, false});
     best[0] = 0.0;
     for (uint32_t x = 1; x <= d; ++x) {
-        for (uint32_t r = 1; r <= std::min(x, meld::kMaxFusedSteps); ++r)
-            if (best[x - r] + kPairRegsUs[r] < best[x]) {
-                best[x] = best[x - r] + kPairRegsUs[r];
+        for (uint32_t r = 1; r <= std::min(x, meld::kMaxFusedSteps); ++r) {
+            const double c = best[x - r] + pair_pass_us(false, r, log_t + x - r);
+            if (c < best[x]) {
+                best[x] = c;
                 first[x] = PassSplit{r, false};
             }
+        }
         if (!gather_ok) continue;
         for (uint32_t r = meld::kMinGatherStepsPairs; r <= std::min(x, meld::kMaxGatherStepsPairs);
-             ++r)
-            if (best[x - r] + kPairGatherUs[r] < best[x]) {
-                best[x] = best[x - r] + kPairGatherUs[r];
+             ++r) {
+            const double c = best[x - r] + pair_pass_us(true, r, log_t + x - r);
+            if (c < best[x]) {
+                best[x] = c;
                 first[x] = PassSplit{r, true};
             }
+        }
     }
     std::vector<PassSplit> out;
     for (uint32_t x = d; x > 0; x -= first[x].r) out.push_back(first[x]);
@@ -524,7 +552,7 @@ std::vector<SortPass> sort_passes(const SortPlan &plan, bool pairs, uint32_t log
         uint32_t b_hi = m - 1;
         std::vector<PassSplit> sizes;
         if (pairs) {
-            sizes = split_passes_pairs(m - log_t, log_n >= gather_log);
+            sizes = split_passes_pairs(m - log_t, log_t, log_n >= gather_log);
         } else {
             for (uint32_t r : split_passes(m - log_t, max_gather))
                 sizes.push_back(PassSplit{r, r > meld::kMaxFusedSteps});
