@@ -446,28 +446,28 @@ std::vector<uint32_t> split_passes(uint32_t d, uint32_t max_gather) {
 }
 
 // Pair sorts: launch time of a streaming pass over 2^28 pairs on one MI355X
-// (microseconds; median of four sorts in one process), by kind, steps r and
-// lowest array bit b_lo (column b_lo - 13; the rows of the pass lie 2^b_lo
-// elements apart). The time depends on where the pass sits, not only on its
-// size: passes whose steps span array bits 19 .. 24 (rows 2 .. 64 MiB apart)
-// run up to 40 % slower than the same pass on bits from 13 up. Only the
-// ratios matter. Zero: not measured (b_lo + r > 28); the lookup clamps b_lo
-// into the measured columns.
+// (microseconds; median of four sorts in one process; gathered passes in
+// XCD runs), by kind, steps r and lowest array bit b_lo (column b_lo - 13;
+// the rows of the pass lie 2^b_lo elements apart). The time depends on where
+// the pass sits, not only on its size: passes whose steps span array bits
+// 19 .. 24 (rows 2 .. 64 MiB apart) run up to 70 % slower than the same pass
+// on bits from 13 up. Only the ratios matter. Zero: not measured
+// (b_lo + r > 28); the lookup clamps b_lo into the measured columns.
 constexpr uint16_t kPairRegsUs[7][15] = {
     {0},
-    {643, 632, 647, 651, 639, 647, 660, 679, 675, 718, 702, 691, 654, 658, 668},
-    {651, 657, 673, 673, 674, 670, 711, 737, 776, 859, 750, 665, 677, 704, 0},
-    {670, 677, 696, 698, 696, 696, 733, 785, 868, 900, 723, 700, 723, 0, 0},
-    {689, 708, 724, 724, 733, 753, 784, 848, 845, 778, 727, 734, 0, 0, 0},
-    {720, 736, 744, 733, 768, 850, 858, 848, 782, 764, 753, 0, 0, 0, 0},
-    {725, 735, 746, 759, 799, 890, 960, 801, 797, 778, 0, 0, 0, 0, 0},
+    {644, 636, 650, 651, 639, 647, 662, 675, 675, 720, 711, 690, 660, 663, 672},
+    {652, 657, 674, 672, 675, 669, 706, 735, 779, 866, 784, 668, 680, 708, 0},
+    {671, 679, 698, 698, 692, 702, 733, 786, 851, 917, 728, 702, 725, 0, 0},
+    {690, 707, 724, 724, 732, 755, 784, 840, 864, 767, 728, 737, 0, 0, 0},
+    {720, 736, 742, 736, 768, 847, 860, 849, 783, 766, 754, 0, 0, 0, 0},
+    {724, 737, 748, 763, 801, 908, 958, 800, 796, 776, 0, 0, 0, 0, 0},
 };
 constexpr uint16_t kPairGatherUs[9][15] = {
     {0}, {0}, {0}, {0}, {0},
-    {657, 667, 698, 698, 749, 829, 871, 827, 726, 704, 716, 0, 0, 0, 0},
-    {656, 704, 716, 771, 882, 762, 781, 788, 777, 794, 0, 0, 0, 0, 0},
-    {759, 814, 798, 796, 822, 802, 748, 762, 769, 0, 0, 0, 0, 0, 0},
-    {857, 890, 897, 914, 913, 888, 932, 1218, 0, 0, 0, 0, 0, 0, 0},
+    {659, 673, 736, 725, 763, 869, 818, 1108, 764, 711, 750, 0, 0, 0, 0},
+    {651, 728, 780, 813, 850, 736, 747, 930, 754, 753, 0, 0, 0, 0, 0},
+    {714, 727, 736, 735, 730, 729, 736, 775, 778, 0, 0, 0, 0, 0, 0},
+    {740, 790, 851, 855, 866, 842, 936, 1006, 0, 0, 0, 0, 0, 0, 0},
 };
 
 double pair_pass_us(bool gather, uint32_t r, uint32_t b_lo) {

@@ -116,8 +116,9 @@ def test_pair_plan_splits_each_phase_by_pass_cost():
     # passes of least modelled time (register passes of up to 6 steps,
     # gathered passes of 5 .. 8, each priced at its own lowest array bit), in
     # the fewest passes: one up to 8 steps, two beyond. Where the two passes
-    # go matters: 10 steps as 4 + 6, not 3 + 7; 11 as 6 + 5 and 13 as 7 + 6
-    # (the first pass, on the high bits, takes the larger share).
+    # go matters: 10 steps as 7 + 3 (gathered, then registers), 11 as 6 + 5,
+    # 12 as 7 + 5 and 13 as 7 + 6 (the first pass, on the high bits, takes
+    # the larger share).
     meld, _ = _lib()
     d = meld.sort_plan(1 << 28, True)
     assert d["log_tile"] == 13 and d["hbm_passes"] == 38
@@ -127,8 +128,8 @@ def test_pair_plan_splits_each_phase_by_pass_cost():
             by_phase.setdefault(p["m"] - 13, []).append((p["kind"], p["steps"]))
     expect = {1: [("regs", 1)], 2: [("regs", 2)], 3: [("regs", 3)], 4: [("regs", 4)],
               5: [("gather", 5)], 6: [("gather", 6)], 7: [("gather", 7)], 8: [("gather", 8)],
-              9: [("regs", 3), ("gather", 6)], 10: [("regs", 4), ("gather", 6)],
-              11: [("gather", 6), ("gather", 5)], 12: [("gather", 6), ("gather", 6)],
+              9: [("regs", 3), ("gather", 6)], 10: [("gather", 7), ("regs", 3)],
+              11: [("gather", 6), ("gather", 5)], 12: [("gather", 7), ("gather", 5)],
               13: [("gather", 7), ("gather", 6)], 14: [("gather", 7), ("gather", 7)],
               15: [("gather", 7), ("gather", 8)]}
     assert by_phase == expect
