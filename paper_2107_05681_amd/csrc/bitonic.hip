@@ -112,19 +112,24 @@ __global__ __launch_bounds__(NT) void bitonic_tile_kernel(SortArray a, uint32_t 
         tile_store<PAIRS, MODE, NT>(a, s, base, T);
 }
 
-// Workgroup order of a gathered pass. Consecutive workgroups go to the
-// eight XCDs in turn, each with its own L2; the tiles of consecutive middle
-// indices (array bits [C, b_lo)) hold neighbouring 2^C-element pieces of
-// every row. Within each group of 8 * 2^kXcdRunLog workgroups, the XCD of
-// workgroup b (b % 8) takes 2^kXcdRunLog tiles in a row, so each L2 streams
-// runs of 4 * 2^C contiguous elements per row, and the group still covers
-// one contiguous range of middle indices (a bijection on the low bits of b).
-constexpr uint32_t kXcdRunLog = 2;
-__device__ __forceinline__ uint32_t xcd_runs(uint32_t b, uint32_t spread) {
-    if (spread < 3 + kXcdRunLog) return b;
-    constexpr uint32_t mask = (8u << kXcdRunLog) - 1;
+// Workgroup order of the streaming passes. Consecutive workgroups go to
+// the eight XCDs in turn, each with its own L2, so tiles that lie next to
+// each other in the array would each go to another XCD. xcd_run_index gives
+// every XCD runs of 2^RUN consecutive tile indices instead: within each group
+// of 8 * 2^RUN workgroups, workgroup b's XCD (b % 8) takes 2^RUN indices in a
+// row, and the group as a whole still covers one contiguous range; a
+// workgroup in a last, partial group keeps its index (a bijection on
+// [0, count)). Merge tails (contiguous tiles) take runs of 16 tiles; the
+// tiles of consecutive middle indices of a gathered pass (array bits
+// [C, b_lo)) hold neighbouring 2^C-element pieces of every row, and take runs
+// of 4 (so each L2 streams 4 * 2^C contiguous elements per row).
+constexpr uint32_t kXcdRunLogMerge = 4, kXcdRunLogGather = 2;
+template <uint32_t RUN>
+__device__ __forceinline__ uint32_t xcd_run_index(uint32_t b, uint32_t count) {
+    constexpr uint32_t mask = (8u << RUN) - 1;
+    if (b >= (count & ~mask)) return b;
     const uint32_t j = b & mask;
-    return (b & ~mask) | ((j & 7u) << kXcdRunLog) | (j >> 3);
+    return (b & ~mask) | ((j & 7u) << RUN) | (j >> 3);
 }
 
 // One pass of S steps (on element bits L-1 .. L-S of a tile of 2^L) of
@@ -132,8 +137,9 @@ __device__ __forceinline__ uint32_t xcd_runs(uint32_t b, uint32_t spread) {
 // with C low bits: workgroup b's bits fill array bits [C, b_lo) and then
 // [b_lo + L - C, ...). Merge tail: S = C = L (contiguous tiles, b_lo = L).
 // Gathered streaming pass: C = L - S, so the steps act on array bits
-// b_lo .. b_lo + S - 1 and each of the 2^S rows is 2^C contiguous elements;
-// its workgroups take their tiles in XCD runs (xcd_runs).
+// b_lo .. b_lo + S - 1 and each of the 2^S rows is 2^C contiguous elements.
+// Both take their tiles in XCD runs (a gathered pass only where the middle
+// index has the bits for them).
 template <bool PAIRS, int L, int S, int C>
 __global__ __launch_bounds__(1 << (L - 4)) void bitonic_pass_regs_kernel(SortArray a, uint32_t m,
                                                                          uint32_t b_lo, int mode,
@@ -143,7 +149,11 @@ __global__ __launch_bounds__(1 << (L - 4)) void bitonic_pass_regs_kernel(SortArr
     E *s = reinterpret_cast<E *>(smem);
     const uint32_t t = threadIdx.x;
     const uint32_t spread = b_lo - C;
-    const uint32_t b = S < L ? xcd_runs(blockIdx.x, spread) : blockIdx.x;
+    uint32_t b = blockIdx.x;
+    if constexpr (S == L)
+        b = xcd_run_index<kXcdRunLogMerge>(b, gridDim.x);
+    else if (spread >= 3 + kXcdRunLogGather)
+        b = xcd_run_index<kXcdRunLogGather>(b, gridDim.x);
     const uint32_t base = ((b & ((1u << spread) - 1)) << C) | ((b >> spread) << (b_lo + L - C));
     const TileMap<L, C> map{base, b_lo};
     const bool up = ((base >> m) & 1u) == 0;
