@@ -135,6 +135,34 @@ def test_pair_plan_splits_each_phase_by_pass_cost():
     assert by_phase == expect
 
 
+def test_pair_plan_split_depends_on_the_phase_only():
+    # A phase's streaming passes are priced by the array bits they act on, and
+    # with tile 2^t phase 2^m always acts on bits t .. m-1: arrays of every
+    # size with the same tile split the phases they share alike, and every
+    # pass list covers its phase's steps once, high bits first.
+    meld, _ = _lib()
+
+    def by_phase(n):
+        d = meld.sort_plan(n, True)
+        out = {}
+        for p in d["passes"][1:]:
+            if p["kind"] != "merge":
+                out.setdefault(p["m"], []).append((p["kind"], p["steps"], p["b_hi"], p["b_lo"]))
+        return d["log_tile"], out
+
+    plans = {k: by_phase(1 << k) for k in range(14, 29)}
+    widest = {}
+    for k, (t, _) in plans.items():
+        widest[t] = max(widest.get(t, k), k)
+    for k, (t, plan) in plans.items():
+        ref = plans[widest[t]][1]
+        assert sorted(plan) == list(range(t + 1, k + 1)), k
+        for m, passes in plan.items():
+            assert passes == ref[m], (k, m)
+            bits = [b for _, _, hi, lo in passes for b in range(hi, lo - 1, -1)]
+            assert bits == list(range(m - 1, t - 1, -1)), (k, m)
+
+
 def test_sort_plan_edge_cases():
     meld, lib = _lib()
     assert meld.sort_plan(0)["passes"] == [] and meld.sort_plan(1)["hbm_passes"] == 0
