@@ -159,6 +159,27 @@ def test_sort_pairs_full_size_properties():
         torch.cuda.empty_cache()
 
 
+def test_sort_keys_full_size_exact():
+    # 2^28 keys alone: their streaming passes differ from the pairs' (gathered
+    # tiles of 2^14 keys, the two-pass phases' first passes at array bits 20
+    # and 21, in XCD runs). The output must equal the input sorted, which a
+    # library sort of the same keys as 64-bit values (unsigned order) gives.
+    dev = _dev()
+    n = 1 << 28
+    keys = workloads.keys_u32(2, n)
+    kin = torch.from_numpy(keys.view(np.int32)).to(dev)
+    del keys
+    ref = torch.sort(kin.to(torch.int64) & 0xFFFFFFFF).values
+    for v, x in FORMS:
+        _path(x)
+        k = kin.clone()
+        meld.sort(k, None, variant=v)
+        torch.cuda.synchronize()
+        assert torch.equal(k.to(torch.int64) & 0xFFFFFFFF, ref), (v, x)
+        del k
+        torch.cuda.empty_cache()
+
+
 def test_sort_rejects_host_pointer():
     import ctypes
     lib = meld.load_library()
