@@ -160,7 +160,12 @@ __global__ __launch_bounds__(1 << (L - 4)) void bitonic_pass_regs_kernel(SortArr
     const bool up = ((base >> m) & 1u) == 0;
 
     E e[kMergeE];
+    // The tile's loads go out at a raised wave priority: with two workgroups
+    // per CU, a workgroup starting its tile then issues ahead of the other's
+    // compare-exchange and transpose work, and HBM stays busier.
+    __builtin_amdgcn_s_setprio(2);
     regs_load<PAIRS, L, C>(a, map, t, mode, e);
+    __builtin_amdgcn_s_setprio(0);
     if (0 < nsteps) merge_reg_step<3>(e, up);                // element bit L-1
     if (S >= 2 && 1 < nsteps) merge_reg_step<2>(e, up);      // element bit L-2
     if constexpr (S == L && merge_uses_xch<L>()) {
