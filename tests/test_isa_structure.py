@@ -8,6 +8,9 @@ only) and checks that the two forms differ where they should:
   * the divergent region runs one gather loop per side, the melded region
     keeps each side's gathers in its own block and the fma chain outside, and
     the in-place melded region has no side blocks at all.
+It also checks that the merge tails and gathered passes issue their tile's
+global loads inside a raised wave-priority window that closes before any
+LDS work.
 """
 import os
 import re
@@ -282,3 +285,21 @@ def test_segmented_lane_exchanges_outside_the_sides(segsort_asm):
     mel = _kernel_all(segsort_asm, r"seg_sort_kernelILb1ELb1ELb1E")
     assert not _lane_sides(mel)
     assert "v_min_u32_dpp" in mel and "v_max_u32_dpp" in mel
+
+
+@pytest.mark.parametrize("kernel", [
+    r"bitonic_pass_regs_kernelILb1ELi13ELi13ELi13E",  # merge tail, pairs
+    r"bitonic_pass_regs_kernelILb0ELi14ELi14ELi14E",  # merge tail, keys
+    r"bitonic_pass_regs_kernelILb1ELi13ELi6ELi7E",    # gathered pass of 6 pair steps
+])
+def test_pass_tile_loads_at_raised_priority(bitonic_asm, kernel):
+    # The streaming passes issue every global load of their tile at wave
+    # priority 2 and drop back to 0 before any LDS work.
+    body = _kernel(bitonic_asm, kernel)
+    up = body.index("s_setprio 2")
+    down = body.index("s_setprio 0")
+    loads = [m.start() for m in re.finditer(r"\bglobal_load", body)]
+    lds = [m.start() for m in re.finditer(r"\bds_(read|write|load|store)", body)]
+    assert loads and lds
+    assert all(up < p < down for p in loads)
+    assert min(lds) > down
